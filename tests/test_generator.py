@@ -1,0 +1,73 @@
+"""The seeded instance generator (shared input module, no search arithmetic)."""
+import numpy as np
+
+import mcs_instances as mi
+
+
+def test_splitmix64_published_vector():
+    # splitmix64 seeded with 0 (Steele, Lea and Flood; Vigna's reference code)
+    z = mi.splitmix64(0, 3)
+    assert [int(x) for x in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_uniforms_in_unit_interval():
+    u = mi.uniforms(12345, 10000)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 0.02
+
+
+def test_deterministic_and_seed_sensitive():
+    a = mi.er_graph(30, 0.3, mi.stream_seed(2, 5, 0))
+    b = mi.er_graph(30, 0.3, mi.stream_seed(2, 5, 0))
+    c = mi.er_graph(30, 0.3, mi.stream_seed(2, 5, 1))
+    assert a == b and a != c
+
+
+def test_undirected_simple_and_density():
+    edges = 0
+    for i in range(20):
+        g = mi.er_graph(40, 0.3, mi.stream_seed(9, i, 0))
+        m = mi.to_matrix(g)
+        assert (m == m.T).all() and m.diagonal().sum() == 0
+        edges += m.sum() // 2
+    p_hat = edges / (20 * 40 * 39 / 2)
+    assert abs(p_hat - 0.3) < 0.02
+
+
+def test_directed_independent_arcs():
+    arcs = recip = 0
+    for i in range(20):
+        g = mi.er_graph(50, 0.1, mi.stream_seed(9, i, 0), directed=True)
+        m = mi.to_matrix(g)
+        assert m.diagonal().sum() == 0
+        arcs += m.sum()
+        recip += (m & m.T).sum() // 2
+    pairs = 20 * 50 * 49
+    assert abs(arcs / pairs - 0.1) < 0.01
+    # independent draws: P(both arcs) = p^2
+    assert abs(recip / (pairs / 2) - 0.01) < 0.005
+
+
+def test_labels_range():
+    assert [mi.label_count(n) for n in (40, 50, 60)] == [14, 17, 20]
+    g = mi.er_graph(60, 0.1, 77, directed=True, labelled=True)
+    assert len(g["label"]) == 60 and min(g["label"]) >= 0 and max(g["label"]) < 20
+
+
+def test_workload_shapes():
+    c2 = mi.pairs_c2()
+    assert len(c2) == 180
+    assert {G["n"] for G, _ in c2} == {30, 35, 40}
+    assert all(G["n"] == H["n"] for G, H in c2)
+    c3 = mi.pairs_c3(seeds=range(2))
+    assert len(c3) == 6 and all(G["directed"] and G["label"] for G, _ in c3)
+    shapes = [mi.c4_shape(i) for i in range(4096)]
+    ns = [n for n, _ in shapes]
+    ps = [p for _, p in shapes]
+    assert min(ns) == 10 and max(ns) == 35
+    assert min(ps) >= 0.05 and max(ps) < 0.5
+    c5 = [mi.c5_shape(i) for i in range(1024)]
+    assert all(35 <= n <= 50 for n, _ in c5)
+    assert sum(1 for _, p in c5 if p == 0.2) == 512
+    tr = [mi.c5_shape(i, train=True) for i in range(100)]
+    assert all(20 <= n <= 30 for n, _ in tr)
