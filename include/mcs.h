@@ -1,0 +1,175 @@
+/*
+ * mcs.h -- C ABI of the MI355X (gfx950) maximum common induced subgraph search.
+ *
+ * Problem (paper Sec. II.A): given graphs G and H, find the largest injective
+ * partial map f: V_G -> V_H such that every ordered pair of distinct mapped
+ * vertices agrees on adjacency (A_G(u,u') = A_H(f(u),f(u'))) and, for
+ * vertex-labelled graphs, mapped vertices carry equal labels.  The common
+ * subgraph need not be connected.
+ *
+ * Method (paper Sec. II.B, Eq. 1, Algorithm 1): McSplit branch and bound.
+ * Each open search node holds label classes (L subset of V_G, R subset of V_H);
+ * a child (v, w) splits every class by adjacency to v in G and to w in H, and
+ * is pruned when |M| + sum over classes of min(|L|, |R|) cannot beat the
+ * incumbent.  The library runs this on the GPU: one wavefront per open node,
+ * bitset classes across its lanes, a device work queue shared by all
+ * wavefronts, and a per-instance incumbent updated with atomics.
+ *
+ * Conventions for every entry point:
+ *   - No exception crosses the ABI; every call returns an mcs_status.
+ *   - Host pointers (graphs, results, tuning) are borrowed for the duration of
+ *     the call only.  Device memory is the caller's: the library never
+ *     allocates or frees device memory.
+ *   - A negative status means no result was written except size = -1 in each
+ *     result; mcs_last_error() then names the cause.
+ *   - Vertex ids in results are the caller's original ids.
+ */
+#ifndef MCS_H
+#define MCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCS_OK = 0,           /* solved to proven optimality */
+    MCS_LIMIT = 1,        /* a node or time limit stopped the search: sizes and
+                             mappings are valid, optimal = 0 where not proven */
+    MCS_E_INVALID = -1,   /* malformed input (see mcs_last_error) */
+    MCS_E_TOO_LARGE = -2, /* a graph has more than MCS_MAX_N vertices */
+    MCS_E_DEVICE = -3,    /* a HIP call or the search kernel failed */
+    MCS_E_WORKSPACE = -4, /* workspace missing, too small or misaligned */
+    MCS_E_INTERNAL = -5   /* an internal capacity check fired (a bug) */
+} mcs_status;
+
+#define MCS_MAX_N 64
+
+/* One graph.  adj holds n rows of 64-bit words: bit j of adj[i] is set iff
+ * the arc i -> j exists.  Undirected graphs must be symmetric.  No self loops
+ * (diagonal bits) and no bits at or above n.  label is NULL (unlabelled) or n
+ * vertex labels; G and H of a pair must agree on directed and on labelled. */
+typedef struct {
+    int32_t n;
+    int32_t directed;
+    const uint64_t *adj;
+    const int32_t *label;
+} mcs_graph;
+
+/* Launch and scheduling knobs of the search kernel; zero fields take the
+ * defaults the library derives from the instance sizes. */
+typedef struct {
+    int32_t waves_per_cu;      /* resident search wavefronts per CU (0: as many
+                                  as the LDS stack size allows) */
+    int32_t children_per_wave; /* how many sibling children one wavefront may
+                                  evaluate at once (1, 2, 4 or 8; 0: 8) */
+    int32_t ring_slots;        /* capacity of the device node queue (0: auto) */
+    int32_t donate_low;        /* a busy wavefront donates its shallowest open
+                                  node when fewer nodes than this wait (0: auto) */
+    int32_t check_interval;    /* child batches between queue/limit checks (0: 16) */
+    int32_t no_reprune;        /* 1: do not re-test a frame's bound against the
+                                  incumbent when the search returns to it */
+    int32_t single_wave;       /* 1: whole search on one wavefront, in the
+                                  sequential order (debugging and node-count
+                                  comparisons) */
+    int32_t use_graph;         /* 1: mcs_plan_run replays a HIP graph */
+} mcs_tuning;
+
+typedef struct {
+    int64_t node_limit;        /* stop after about this many nodes (0: none) */
+    double time_limit_s;       /* stop after this much kernel time (<= 0: 600 s) */
+    const mcs_tuning *tuning;  /* NULL: all defaults */
+} mcs_opts;
+
+/* Per-instance result.  map_g/map_h are caller-owned arrays of capacity
+ * min(nG, nH) (either may be NULL); size pairs are written. */
+typedef struct {
+    int32_t size;
+    int32_t optimal;           /* 1: the search finished, size is the MCS */
+    int32_t *map_g;
+    int32_t *map_h;
+    int64_t nodes;             /* search nodes evaluated for this instance
+                                  (the root and every child whose bound was
+                                  computed) */
+    double t_best_s;           /* kernel time at which the final size was found */
+    double t_proof_s;          /* kernel time at which the search of this
+                                  instance finished (0 if it did not) */
+} mcs_result;
+
+/* Whole-launch statistics, filled by mcs_plan_stats. */
+typedef struct {
+    int64_t nodes;             /* sum over instances */
+    int64_t batches;           /* child batches evaluated by all wavefronts */
+    int64_t children;          /* children evaluated (with re-evaluations) */
+    int64_t lane_slots;        /* lanes holding a class in those batches */
+    int64_t donations;         /* nodes published to the shared queue */
+    int64_t pops;              /* nodes taken from the shared queue */
+    int32_t waves;             /* wavefronts launched */
+    int32_t blocks;            /* workgroups launched */
+    int32_t lds_per_wave;      /* bytes of LDS per wavefront */
+    int32_t stopped;           /* 1 if a limit stopped the search */
+    double kernel_ms;          /* search kernel time of the last run */
+} mcs_stats;
+
+typedef struct mcs_plan mcs_plan;
+
+/* Validate count pairs (G[i], H[i]), order vertices by descending degree
+ * (total degree when directed; ties by index), pack bit rows and root classes
+ * on the host (Sec. IV.A ordering; root classes: all vertices, or one class
+ * per label present in both graphs).  No device work.  *out must be released
+ * with mcs_plan_destroy.  Errors: MCS_E_INVALID, MCS_E_TOO_LARGE. */
+mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                           const mcs_opts *opts, mcs_plan **out);
+
+/* Bytes of device workspace the plan needs (256-byte aligned base). */
+size_t mcs_plan_workspace_size(const mcs_plan *plan);
+
+/* Bind the caller's device workspace and copy the packed instances into it
+ * (asynchronous on stream, a hipStream_t or NULL).  The workspace must stay
+ * allocated and untouched by the caller until the plan is destroyed or bound
+ * again.  Errors: MCS_E_WORKSPACE, MCS_E_DEVICE. */
+mcs_status mcs_plan_upload(mcs_plan *plan, void *workspace, size_t bytes, void *stream);
+
+/* Reset the search state and launch the search over all instances
+ * (asynchronous on stream).  Inputs are already resident in the workspace.
+ * Errors: MCS_E_WORKSPACE (no upload yet), MCS_E_DEVICE. */
+mcs_status mcs_plan_run(mcs_plan *plan, void *stream);
+
+/* Wait for the last run, copy results back and map them to original vertex
+ * ids.  results has one entry per instance.  Returns MCS_OK, MCS_LIMIT, or
+ * an error (MCS_E_DEVICE; MCS_E_INTERNAL if the kernel flagged a capacity
+ * fault). */
+mcs_status mcs_plan_results(mcs_plan *plan, mcs_result *results, void *stream);
+
+/* Statistics of the last run (valid after mcs_plan_results). */
+mcs_status mcs_plan_stats(const mcs_plan *plan, mcs_stats *stats);
+
+void mcs_plan_destroy(mcs_plan *plan);
+
+/* Workspace bytes mcs_solve_batch needs for these instances. */
+size_t mcs_workspace_size(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                          const mcs_opts *opts);
+
+/* Solve MCS(G[i], H[i]) for count pairs in one launch: create, upload, run,
+ * results, destroy.  workspace: device memory of mcs_workspace_size bytes. */
+mcs_status mcs_solve_batch(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                           const mcs_opts *opts, void *workspace, size_t bytes,
+                           void *stream, mcs_result *results);
+
+/* One pair: mcs_solve_batch with count = 1. */
+mcs_status mcs_solve(const mcs_graph *G, const mcs_graph *H, const mcs_opts *opts,
+                     void *workspace, size_t bytes, void *stream, mcs_result *result);
+
+/* Static description of a status code. */
+const char *mcs_status_string(mcs_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *mcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCS_H */

@@ -1,0 +1,51 @@
+"""Compile the HIP search library (libmcs.so) in-tree for gfx950.
+
+The library is the product: hand-written HIP kernels plus the host driver of
+the C ABI in include/mcs.h.  It is built with hipcc, always from source."""
+from __future__ import annotations
+
+import os
+import subprocess
+import tempfile
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libmcs.so")
+ARCH = "gfx950"
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# Packed-FP32 instructions stay off in every HIP build of this project.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+          "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS
+
+SOURCES = ["mcs_search.hip", "mcs_host.cpp"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link libmcs.so (atomically replaced)."""
+    with tempfile.TemporaryDirectory(prefix="mcs_build_") as tmp:
+        objs = []
+        for src in SOURCES:
+            obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
+            cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+            _run(cmd, verbose)
+            objs.append(obj)
+        out = os.path.join(tmp, "libmcs.so")
+        _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", out] + objs, verbose)
+        os.replace(out, LIB + ".tmp")
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"build failed: {' '.join(cmd)}\n{r.stdout}")
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,672 @@
+// Host side of the C ABI declared in include/mcs.h: validation, degree
+// ordering and bit packing, workspace layout, kernel launches (direct or from
+// a HIP graph), and mapping the results back to the caller's vertex ids.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mcs.h"
+#include "mcs_layout.h"
+
+extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed);
+extern "C" void *mcs_internal_reset_kernel(void);
+
+namespace {
+
+thread_local std::string g_err;
+
+mcs_status fail(mcs_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+mcs_status hip_fail(hipError_t e, const char *what) {
+    return fail(MCS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                              \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess)                      \
+            return hip_fail(e_, #call);            \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+uint64_t low_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1); }
+
+// Checks one graph; returns MCS_OK or an error with a message.
+mcs_status validate(const mcs_graph &g, const char *which, int idx) {
+    char buf[160];
+    if (g.n < 0) {
+        snprintf(buf, sizeof buf, "%s[%d]: negative vertex count", which, idx);
+        return fail(MCS_E_INVALID, buf);
+    }
+    if (g.n > MCS_MAX_N) {
+        snprintf(buf, sizeof buf, "%s[%d]: %d vertices, the limit is %d", which, idx, g.n,
+                 MCS_MAX_N);
+        return fail(MCS_E_TOO_LARGE, buf);
+    }
+    if (g.n > 0 && !g.adj) {
+        snprintf(buf, sizeof buf, "%s[%d]: adj is NULL", which, idx);
+        return fail(MCS_E_INVALID, buf);
+    }
+    if (g.directed != 0 && g.directed != 1) {
+        snprintf(buf, sizeof buf, "%s[%d]: directed must be 0 or 1", which, idx);
+        return fail(MCS_E_INVALID, buf);
+    }
+    const uint64_t keep = low_mask(g.n);
+    for (int i = 0; i < g.n; i++) {
+        uint64_t r = g.adj[i];
+        if (r & ~keep) {
+            snprintf(buf, sizeof buf, "%s[%d]: row %d has bits at or above n", which, idx, i);
+            return fail(MCS_E_INVALID, buf);
+        }
+        if ((r >> i) & 1) {
+            snprintf(buf, sizeof buf, "%s[%d]: self loop at vertex %d", which, idx, i);
+            return fail(MCS_E_INVALID, buf);
+        }
+        if (!g.directed)
+            for (int j = 0; j < g.n; j++)
+                if (((r >> j) & 1) != ((g.adj[j] >> i) & 1)) {
+                    snprintf(buf, sizeof buf, "%s[%d]: undirected graph is not symmetric at (%d,%d)",
+                             which, idx, i, j);
+                    return fail(MCS_E_INVALID, buf);
+                }
+    }
+    return MCS_OK;
+}
+
+// Descending degree (out + in when directed), ties by index (Sec. IV.A).
+std::vector<int> degree_order(const mcs_graph &g) {
+    std::vector<int> deg(g.n, 0), ord(g.n);
+    for (int i = 0; i < g.n; i++) {
+        deg[i] = popcount64(g.adj[i]);
+        if (g.directed)
+            for (int j = 0; j < g.n; j++)
+                deg[i] += (int)((g.adj[j] >> i) & 1);
+    }
+    for (int i = 0; i < g.n; i++)
+        ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return deg[a] > deg[b]; });
+    return ord;
+}
+
+// rows of the relabelled graph: vertex p is original ord[p]
+std::vector<uint64_t> permuted_rows(const mcs_graph &g, const std::vector<int> &ord) {
+    std::vector<uint64_t> rows(g.n, 0);
+    for (int p = 0; p < g.n; p++)
+        for (int q = 0; q < g.n; q++)
+            if ((g.adj[ord[p]] >> ord[q]) & 1)
+                rows[p] |= 1ull << q;
+    return rows;
+}
+
+std::vector<uint64_t> transpose_rows(const std::vector<uint64_t> &rows) {
+    int n = (int)rows.size();
+    std::vector<uint64_t> t(n, 0);
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++)
+            if ((rows[i] >> j) & 1)
+                t[j] |= 1ull << i;
+    return t;
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+struct mcs_plan {
+    int count = 0;
+    int directed = 0;
+    int word_bytes = 8;
+    int mmax = 0;
+    mcs_tuning tun{};
+    int64_t node_limit = 0;
+    double time_limit_s = 600.0;
+
+    std::vector<mcs::DevInst> inst;
+    std::vector<uint8_t> adj;      // packed rows, word_bytes each
+    std::vector<uint8_t> rootcls;  // packed (L, R) pairs
+    std::vector<std::vector<int>> ordG, ordH;
+    std::vector<int> m;            // min(nG, nH) per instance
+    size_t map_pairs = 0;
+
+    // device layout
+    size_t off_inst = 0, off_adj = 0, off_cls = 0, off_inc = 0, off_open = 0, off_nodes = 0,
+           off_tbest = 0, off_tproof = 0, off_maps = 0, off_glob = 0, off_seq = 0, off_slots = 0,
+           ws_bytes = 0;
+    int ring_slots = 0, slot_bytes = 0, cap_classes = 0, lds_per_wave = 0;
+    int waves_per_block = 4, blocks = 0, waves = 0, lds_per_block = 0;
+    double tick_hz = 1e8;
+
+    uint8_t *ws = nullptr;
+    bool uploaded = false;
+    bool launched = false;
+    mcs::SearchParams sp{};
+    mcs::ResetParams rp{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float last_ms = 0.f;
+
+    // results of the last run
+    std::vector<int> h_inc, h_open;
+    std::vector<unsigned long long> h_nodes, h_tbest, h_tproof;
+    std::vector<uint16_t> h_maps;
+    mcs::DevGlobals h_glob{};
+    bool have_results = false;
+
+    ~mcs_plan() {
+        if (gexec)
+            (void)hipGraphExecDestroy(gexec);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        if (ev0)
+            (void)hipEventDestroy(ev0);
+        if (ev1)
+            (void)hipEventDestroy(ev1);
+    }
+};
+
+namespace {
+
+template <typename W>
+void put_word(std::vector<uint8_t> &buf, uint64_t x) {
+    W w = (W)x;
+    const uint8_t *p = (const uint8_t *)&w;
+    buf.insert(buf.end(), p, p + sizeof(W));
+}
+
+void pack_word(std::vector<uint8_t> &buf, int word_bytes, uint64_t x) {
+    if (word_bytes == 4)
+        put_word<uint32_t>(buf, x);
+    else
+        put_word<uint64_t>(buf, x);
+}
+
+int next_pow2(int x) {
+    int p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mcs_status_string(mcs_status s) {
+    switch (s) {
+    case MCS_OK: return "ok";
+    case MCS_LIMIT: return "limit reached (results valid, not all proven optimal)";
+    case MCS_E_INVALID: return "invalid input";
+    case MCS_E_TOO_LARGE: return "graph too large";
+    case MCS_E_DEVICE: return "device error";
+    case MCS_E_WORKSPACE: return "workspace missing or too small";
+    case MCS_E_INTERNAL: return "internal capacity check failed";
+    }
+    return "unknown status";
+}
+
+const char *mcs_last_error(void) { return g_err.c_str(); }
+
+mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                           const mcs_opts *opts, mcs_plan **out) {
+    g_err.clear();
+    if (!out)
+        return fail(MCS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (count <= 0)
+        return fail(MCS_E_INVALID, "count must be positive");
+    if (!G || !H)
+        return fail(MCS_E_INVALID, "G or H is NULL");
+    int directed = G[0].directed;
+    for (int i = 0; i < count; i++) {
+        mcs_status s = validate(G[i], "G", i);
+        if (s != MCS_OK)
+            return s;
+        s = validate(H[i], "H", i);
+        if (s != MCS_OK)
+            return s;
+        if (G[i].directed != H[i].directed)
+            return fail(MCS_E_INVALID, "G and H of a pair differ in directedness");
+        if ((G[i].label == nullptr) != (H[i].label == nullptr))
+            return fail(MCS_E_INVALID, "G and H of a pair differ in having labels");
+        if (G[i].directed != directed)
+            return fail(MCS_E_INVALID, "all pairs of one call must share directedness");
+    }
+
+    mcs_plan *p = new mcs_plan();
+    p->count = count;
+    p->directed = directed;
+    if (opts) {
+        if (opts->tuning)
+            p->tun = *opts->tuning;
+        p->node_limit = opts->node_limit > 0 ? opts->node_limit : 0;
+        if (opts->time_limit_s > 0)
+            p->time_limit_s = opts->time_limit_s;
+    }
+    int nmax = 0;
+    for (int i = 0; i < count; i++)
+        nmax = std::max(nmax, std::max(G[i].n, H[i].n));
+    p->word_bytes = nmax <= 32 ? 4 : 8;
+    const int NB = 8 * p->word_bytes;
+    const int R = directed ? 4 : 2;
+
+    p->inst.resize(count);
+    p->ordG.resize(count);
+    p->ordH.resize(count);
+    p->m.resize(count);
+    uint32_t cls_off = 0;
+    size_t map_off = 0;
+    for (int i = 0; i < count; i++) {
+        const mcs_graph &g = G[i], &h = H[i];
+        p->ordG[i] = degree_order(g);
+        p->ordH[i] = degree_order(h);
+        std::vector<uint64_t> rg = permuted_rows(g, p->ordG[i]);
+        std::vector<uint64_t> rh = permuted_rows(h, p->ordH[i]);
+        std::vector<std::vector<uint64_t>> sets = {rg, rh};
+        if (directed) {
+            sets.push_back(transpose_rows(rg));
+            sets.push_back(transpose_rows(rh));
+        }
+        for (int s = 0; s < R; s++)
+            for (int j = 0; j < NB; j++)
+                pack_word(p->adj, p->word_bytes, j < (int)sets[s].size() ? sets[s][j] : 0);
+
+        // root classes
+        int K0 = 0;
+        if (g.n > 0 && h.n > 0) {
+            if (!g.label) {
+                pack_word(p->rootcls, p->word_bytes, low_mask(g.n));
+                pack_word(p->rootcls, p->word_bytes, low_mask(h.n));
+                K0 = 1;
+            } else {
+                std::vector<int> seen;
+                for (int a = 0; a < g.n; a++) {
+                    int lab = g.label[p->ordG[i][a]];
+                    if (std::find(seen.begin(), seen.end(), lab) != seen.end())
+                        continue;
+                    seen.push_back(lab);
+                    uint64_t L = 0, Rm = 0;
+                    for (int b = 0; b < g.n; b++)
+                        if (g.label[p->ordG[i][b]] == lab)
+                            L |= 1ull << b;
+                    for (int b = 0; b < h.n; b++)
+                        if (h.label[p->ordH[i][b]] == lab)
+                            Rm |= 1ull << b;
+                    if (!Rm)
+                        continue;
+                    pack_word(p->rootcls, p->word_bytes, L);
+                    pack_word(p->rootcls, p->word_bytes, Rm);
+                    K0++;
+                }
+            }
+        }
+        int mi = std::min(g.n, h.n);
+        p->m[i] = mi;
+        p->mmax = std::max(p->mmax, mi);
+        mcs::DevInst di{};
+        di.nG = (uint8_t)g.n;
+        di.nH = (uint8_t)h.n;
+        di.K0 = (uint8_t)K0;
+        di.cls_off = cls_off;
+        di.map_off = (uint32_t)map_off;
+        di.lb = 0;
+        p->inst[i] = di;
+        cls_off += (uint32_t)K0;
+        map_off += (size_t)mi * (mi + 1) / 2;
+    }
+    if (p->rootcls.empty())
+        pack_word(p->rootcls, p->word_bytes, 0), pack_word(p->rootcls, p->word_bytes, 0);
+    p->map_pairs = std::max<size_t>(map_off, 1);
+    p->cap_classes = std::max(1, p->mmax * (p->mmax + 1) / 2);
+
+    // launch shape
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        dev = 0;
+    int cus = 256, max_lds_block = 65536, clock_khz = 100000;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&max_lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        clock_khz <= 0)
+        clock_khz = 100000;
+    (void)hipGetLastError();
+    p->tick_hz = (double)clock_khz * 1000.0;
+    p->lds_per_wave = mcs::lds_layout(p->word_bytes, directed, p->cap_classes).total;
+    int wpb = 4;
+    while (wpb > 1 && wpb * p->lds_per_wave > max_lds_block)
+        wpb >>= 1;
+    if (p->lds_per_wave > max_lds_block) {
+        delete p;
+        return fail(MCS_E_INTERNAL, "LDS stack of one wavefront exceeds the workgroup limit");
+    }
+    p->waves_per_block = wpb;
+    p->lds_per_block = wpb * p->lds_per_wave;
+    const void *kern = mcs_internal_search_kernel(p->word_bytes, directed);
+    int per_cu = 0;
+    if (p->lds_per_block > 65536)
+        (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  p->lds_per_block);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb,
+                                                     (size_t)p->lds_per_block) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    p->blocks = per_cu * cus;
+    if (p->tun.single_wave)
+        p->blocks = 1;
+    else if (p->tun.waves_per_cu > 0)
+        p->blocks = std::max(1, std::min(p->blocks, (p->tun.waves_per_cu * cus + wpb - 1) / wpb));
+    p->waves = p->blocks * wpb;
+
+    p->ring_slots = p->tun.ring_slots > 0 ? next_pow2(p->tun.ring_slots)
+                                          : next_pow2(std::max(1024, 2 * p->waves));
+    p->slot_bytes = mcs::slot_bytes_for(p->word_bytes, p->mmax);
+
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    p->off_inst = take(sizeof(mcs::DevInst) * count);
+    p->off_adj = take(p->adj.size());
+    p->off_cls = take(p->rootcls.size());
+    p->off_inc = take(sizeof(int) * count);
+    p->off_open = take(sizeof(int) * count);
+    p->off_nodes = take(sizeof(unsigned long long) * count);
+    p->off_tbest = take(sizeof(unsigned long long) * count);
+    p->off_tproof = take(sizeof(unsigned long long) * count);
+    p->off_maps = take(sizeof(uint16_t) * p->map_pairs);
+    p->off_glob = take(sizeof(mcs::DevGlobals));
+    p->off_seq = take(sizeof(unsigned long long) * p->ring_slots);
+    p->off_slots = take((size_t)p->slot_bytes * p->ring_slots);
+    p->ws_bytes = o;
+    *out = p;
+    return MCS_OK;
+}
+
+size_t mcs_plan_workspace_size(const mcs_plan *p) { return p ? p->ws_bytes : 0; }
+
+mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *stream) {
+    g_err.clear();
+    if (!p)
+        return fail(MCS_E_INVALID, "plan is NULL");
+    if (!workspace || bytes < p->ws_bytes || ((uintptr_t)workspace & 255))
+        return fail(MCS_E_WORKSPACE, "workspace must be at least mcs_plan_workspace_size bytes, "
+                                     "256-byte aligned");
+    if (p->ws != (uint8_t *)workspace && p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        (void)hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+    }
+    p->ws = (uint8_t *)workspace;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(hipMemcpyAsync(p->ws + p->off_inst, p->inst.data(), sizeof(mcs::DevInst) * p->count,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p->ws + p->off_adj, p->adj.data(), p->adj.size(), hipMemcpyHostToDevice,
+                           s));
+    HIP_TRY(hipMemcpyAsync(p->ws + p->off_cls, p->rootcls.data(), p->rootcls.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+
+    mcs::SearchParams &sp = p->sp;
+    sp = mcs::SearchParams{};
+    sp.inst = (const mcs::DevInst *)(p->ws + p->off_inst);
+    sp.adj = p->ws + p->off_adj;
+    sp.rootcls = p->ws + p->off_cls;
+    sp.inc = (int *)(p->ws + p->off_inc);
+    sp.open = (int *)(p->ws + p->off_open);
+    sp.nodes = (unsigned long long *)(p->ws + p->off_nodes);
+    sp.t_best = (unsigned long long *)(p->ws + p->off_tbest);
+    sp.t_proof = (unsigned long long *)(p->ws + p->off_tproof);
+    sp.maps = (uint16_t *)(p->ws + p->off_maps);
+    sp.g = (mcs::DevGlobals *)(p->ws + p->off_glob);
+    sp.seq = (unsigned long long *)(p->ws + p->off_seq);
+    sp.slots = p->ws + p->off_slots;
+    sp.count = p->count;
+    sp.ring_slots = p->ring_slots;
+    sp.slot_bytes = p->slot_bytes;
+    sp.cap_classes = p->cap_classes;
+    sp.lds_per_wave = p->lds_per_wave;
+    int cm = p->tun.children_per_wave;
+    sp.cmax = (cm == 1 || cm == 2 || cm == 4 || cm == 8) ? cm : 8;
+    sp.donate_low = p->tun.donate_low > 0 ? p->tun.donate_low : p->waves;
+    sp.check_interval = p->tun.check_interval > 0 ? p->tun.check_interval : 16;
+    sp.reprune = p->tun.no_reprune ? 0 : 1;
+    sp.single_wave = p->tun.single_wave ? 1 : 0;
+    double ticks = p->time_limit_s * p->tick_hz;
+    sp.limit_ticks = ticks > 9e18 ? (unsigned long long)9e18 : (unsigned long long)ticks;
+    sp.node_limit = p->node_limit;
+
+    mcs::ResetParams &rp = p->rp;
+    rp.inst = sp.inst;
+    rp.inc = sp.inc;
+    rp.open = sp.open;
+    rp.nodes = sp.nodes;
+    rp.t_best = sp.t_best;
+    rp.t_proof = sp.t_proof;
+    rp.g = sp.g;
+    rp.seq = sp.seq;
+    rp.count = p->count;
+    rp.ring_slots = p->ring_slots;
+    p->uploaded = true;
+    return MCS_OK;
+}
+
+static mcs_status launch_direct(mcs_plan *p, hipStream_t s) {
+    const void *kr = mcs_internal_reset_kernel();
+    const void *ks = mcs_internal_search_kernel(p->word_bytes, p->directed);
+    int n = std::max(p->count, p->ring_slots);
+    int rb = std::min(1024, (n + 255) / 256);
+    void *ra[] = {&p->rp};
+    HIP_TRY(hipLaunchKernel(kr, dim3(rb), dim3(256), ra, 0, s));
+    if (p->ev0)
+        HIP_TRY(hipEventRecord(p->ev0, s));
+    void *sa[] = {&p->sp};
+    HIP_TRY(hipLaunchKernel(ks, dim3(p->blocks), dim3(64 * p->waves_per_block), sa,
+                            (size_t)p->lds_per_block, s));
+    if (p->ev1)
+        HIP_TRY(hipEventRecord(p->ev1, s));
+    return MCS_OK;
+}
+
+static mcs_status build_graph(mcs_plan *p) {
+    HIP_TRY(hipGraphCreate(&p->graph, 0));
+    hipGraphNode_t nr = nullptr, ns = nullptr;
+    int n = std::max(p->count, p->ring_slots);
+    void *ra[] = {&p->rp};
+    void *sa[] = {&p->sp};
+    hipKernelNodeParams kp{};
+    kp.func = mcs_internal_reset_kernel();
+    kp.gridDim = dim3(std::min(1024, (n + 255) / 256));
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = ra;
+    kp.extra = nullptr;
+    HIP_TRY(hipGraphAddKernelNode(&nr, p->graph, nullptr, 0, &kp));
+    hipKernelNodeParams ks{};
+    ks.func = mcs_internal_search_kernel(p->word_bytes, p->directed);
+    ks.gridDim = dim3(p->blocks);
+    ks.blockDim = dim3(64 * p->waves_per_block);
+    ks.sharedMemBytes = (unsigned)p->lds_per_block;
+    ks.kernelParams = sa;
+    ks.extra = nullptr;
+    HIP_TRY(hipGraphAddKernelNode(&ns, p->graph, &nr, 1, &ks));
+    HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+    return MCS_OK;
+}
+
+mcs_status mcs_plan_run(mcs_plan *p, void *stream) {
+    g_err.clear();
+    if (!p)
+        return fail(MCS_E_INVALID, "plan is NULL");
+    if (!p->uploaded)
+        return fail(MCS_E_WORKSPACE, "mcs_plan_upload has not been called");
+    hipStream_t s = as_stream(stream);
+    if (!p->ev0) {
+        HIP_TRY(hipEventCreate(&p->ev0));
+        HIP_TRY(hipEventCreate(&p->ev1));
+    }
+    p->have_results = false;
+    if (p->tun.use_graph) {
+        if (!p->gexec) {
+            mcs_status st = build_graph(p);
+            if (st != MCS_OK)
+                return st;
+        }
+        HIP_TRY(hipEventRecord(p->ev0, s));
+        HIP_TRY(hipGraphLaunch(p->gexec, s));
+        HIP_TRY(hipEventRecord(p->ev1, s));
+    } else {
+        mcs_status st = launch_direct(p, s);
+        if (st != MCS_OK)
+            return st;
+    }
+    p->launched = true;
+    return MCS_OK;
+}
+
+mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
+    g_err.clear();
+    if (!p)
+        return fail(MCS_E_INVALID, "plan is NULL");
+    if (!p->launched)
+        return fail(MCS_E_INVALID, "mcs_plan_run has not been called");
+    hipStream_t s = as_stream(stream);
+    int n = p->count;
+    p->h_inc.resize(n);
+    p->h_open.resize(n);
+    p->h_nodes.resize(n);
+    p->h_tbest.resize(n);
+    p->h_tproof.resize(n);
+    p->h_maps.resize(p->map_pairs);
+    HIP_TRY(hipMemcpyAsync(p->h_inc.data(), p->ws + p->off_inc, sizeof(int) * n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_open.data(), p->ws + p->off_open, sizeof(int) * n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_nodes.data(), p->ws + p->off_nodes, 8 * (size_t)n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_tbest.data(), p->ws + p->off_tbest, 8 * (size_t)n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_tproof.data(), p->ws + p->off_tproof, 8 * (size_t)n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p->h_maps.data(), p->ws + p->off_maps, 2 * p->map_pairs,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&p->h_glob, p->ws + p->off_glob, sizeof(mcs::DevGlobals),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    if (p->ev0 && hipEventElapsedTime(&p->last_ms, p->ev0, p->ev1) != hipSuccess) {
+        (void)hipGetLastError();
+        p->last_ms = 0.f;
+    }
+    p->have_results = true;
+    if (p->h_glob.error)
+        return fail(MCS_E_INTERNAL, "a search wavefront hit an internal capacity check");
+
+    const unsigned long long mask48 = 0xFFFFFFFFFFFFull;
+    const unsigned long long t0 = p->h_glob.t0;
+    bool all_proven = true;
+    for (int i = 0; i < n; i++) {
+        mcs_result &r = res[i];
+        int size = p->h_inc[i];
+        bool proven = p->h_tproof[i] != 0 && p->h_open[i] == 0;
+        all_proven = all_proven && proven;
+        r.size = size;
+        r.optimal = proven ? 1 : 0;
+        r.nodes = (int64_t)p->h_nodes[i];
+        unsigned long long kb = p->h_tbest[i];
+        r.t_best_s = kb ? (double)(((kb & mask48) - (t0 & mask48)) & mask48) / p->tick_hz : 0.0;
+        r.t_proof_s = proven ? (double)(p->h_tproof[i] - t0) / p->tick_hz : 0.0;
+        if (size > p->inst[i].lb && size > 0) {
+            size_t off = p->inst[i].map_off + (size_t)size * (size - 1) / 2;
+            for (int j = 0; j < size; j++) {
+                uint16_t e = p->h_maps[off + j];
+                int pg = e & 0xFF, ph = e >> 8;
+                if (r.map_g)
+                    r.map_g[j] = p->ordG[i][pg];
+                if (r.map_h)
+                    r.map_h[j] = p->ordH[i][ph];
+            }
+        }
+    }
+    return all_proven ? MCS_OK : MCS_LIMIT;
+}
+
+mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
+    if (!p || !st)
+        return fail(MCS_E_INVALID, "NULL argument");
+    if (!p->have_results)
+        return fail(MCS_E_INVALID, "no results yet");
+    mcs_stats z{};
+    for (int i = 0; i < p->count; i++)
+        z.nodes += (int64_t)p->h_nodes[i];
+    z.batches = (int64_t)p->h_glob.batches;
+    z.children = (int64_t)p->h_glob.children;
+    z.lane_slots = (int64_t)p->h_glob.lane_slots;
+    z.donations = (int64_t)p->h_glob.donations;
+    z.pops = (int64_t)p->h_glob.pops;
+    z.waves = p->waves;
+    z.blocks = p->blocks;
+    z.lds_per_wave = p->lds_per_wave;
+    z.stopped = p->h_glob.stop ? 1 : 0;
+    z.kernel_ms = p->last_ms;
+    *st = z;
+    return MCS_OK;
+}
+
+void mcs_plan_destroy(mcs_plan *p) { delete p; }
+
+size_t mcs_workspace_size(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                          const mcs_opts *opts) {
+    mcs_plan *p = nullptr;
+    if (mcs_plan_create(count, G, H, opts, &p) != MCS_OK)
+        return 0;
+    size_t b = p->ws_bytes;
+    mcs_plan_destroy(p);
+    return b;
+}
+
+mcs_status mcs_solve_batch(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                           const mcs_opts *opts, void *workspace, size_t bytes, void *stream,
+                           mcs_result *results) {
+    if (results && count > 0)
+        for (int i = 0; i < count; i++)
+            results[i].size = -1;
+    if (!results)
+        return fail(MCS_E_INVALID, "results is NULL");
+    mcs_plan *p = nullptr;
+    mcs_status s = mcs_plan_create(count, G, H, opts, &p);
+    if (s != MCS_OK)
+        return s;
+    s = mcs_plan_upload(p, workspace, bytes, stream);
+    if (s == MCS_OK)
+        s = mcs_plan_run(p, stream);
+    if (s == MCS_OK)
+        s = mcs_plan_results(p, results, stream);
+    if (s < 0)
+        for (int i = 0; i < count; i++)
+            results[i].size = -1;
+    mcs_plan_destroy(p);
+    return s;
+}
+
+mcs_status mcs_solve(const mcs_graph *G, const mcs_graph *H, const mcs_opts *opts, void *workspace,
+                     size_t bytes, void *stream, mcs_result *result) {
+    return mcs_solve_batch(1, G, H, opts, workspace, bytes, stream, result);
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Device-side data layout shared by the host driver (mcs_host.cpp) and the
+// search kernels (mcs_search.hip).
+#pragma once
+#include <stdint.h>
+
+namespace mcs {
+
+// One instance, as the kernels see it.  Vertices are already in descending
+// degree order; adjacency rows and root classes live in separate arrays.
+struct DevInst {
+    uint8_t nG, nH, K0, pad;
+    uint32_t cls_off;  // first root class in the root-class array
+    uint32_t map_off;  // first mapping pair of this instance's per-size slots
+    int32_t lb;        // initial incumbent size (0: none)
+};
+
+// Counters shared by every wavefront of a launch.
+struct DevGlobals {
+    unsigned long long head;        // node queue: next ticket to take
+    unsigned long long tail;        // node queue: next ticket to fill
+    unsigned long long t0;          // earliest wavefront start (realtime ticks)
+    unsigned long long node_total;  // nodes flushed so far (for the node limit)
+    int open_total;                 // live work units: queued nodes + busy wavefronts
+    unsigned next_inst;             // next instance whose root is not yet taken
+    unsigned stop;                  // 1: a limit was hit, every wavefront leaves
+    unsigned error;                 // nonzero: a capacity check fired
+    int idle;                       // wavefronts currently looking for work
+    int pad0;
+    unsigned long long batches;     // statistics
+    unsigned long long children;
+    unsigned long long lane_slots;
+    unsigned long long donations;
+    unsigned long long pops;
+};
+
+struct SearchParams {
+    const DevInst *inst;
+    const void *adj;      // [count][R][NB] words, R = 2 (G, H) or 4 (G out, H out, G in, H in)
+    const void *rootcls;  // [sum K0] (L, R) word pairs
+    int *inc;             // [count] incumbent size
+    int *open;            // [count] live work units of the instance
+    unsigned long long *nodes;    // [count]
+    unsigned long long *t_best;   // [count] (size << 48) | (realtime & 2^48-1)
+    unsigned long long *t_proof;  // [count] realtime ticks when open reached 0
+    uint16_t *maps;               // per instance, per size s: s pairs (g | h << 8)
+    DevGlobals *g;
+    unsigned long long *seq;      // [ring_slots] queue slot sequence numbers
+    uint8_t *slots;               // [ring_slots][slot_bytes]
+    int count;
+    int ring_slots;
+    int slot_bytes;
+    int cap_classes;      // LDS class capacity of one wavefront's stack
+    int lds_per_wave;     // bytes
+    int cmax;             // children per batch (1, 2, 4, 8)
+    int donate_low;
+    int check_interval;
+    int reprune;
+    int single_wave;
+    unsigned long long limit_ticks;  // time limit in realtime ticks
+    long long node_limit;            // 0: none
+};
+
+struct ResetParams {
+    const DevInst *inst;
+    int *inc;
+    int *open;
+    unsigned long long *nodes;
+    unsigned long long *t_best;
+    unsigned long long *t_proof;
+    DevGlobals *g;
+    unsigned long long *seq;
+    int count;
+    int ring_slots;
+};
+
+// Record of a donated node in the queue: a 32-byte header, the mapping
+// (NB pairs of bytes) and the classes.
+constexpr int kRecHeader = 32;
+
+template <typename W>
+constexpr int bits_of() { return 8 * (int)sizeof(W); }
+
+template <typename W>
+constexpr int rec_map_off() { return kRecHeader; }
+
+template <typename W>
+constexpr int rec_cls_off() { return kRecHeader + 2 * bits_of<W>(); }
+
+// LDS of one wavefront, in this order, each part 16-byte aligned:
+//   classes   [cap_classes] (L, R) word pairs
+//   adjacency [R][NB] words
+//   mapping   [NB] byte pairs
+//   headers   [NB + 1] frame headers (24 bytes for 64-bit words, 16 for 32-bit)
+struct LdsLayout {
+    int cls, adj, map, hdr, total;
+};
+
+inline constexpr int align16(int x) { return (x + 15) & ~15; }
+
+inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_classes) {
+    int nb = 8 * word_bytes;
+    int rows = directed ? 4 : 2;
+    int hdr_bytes = word_bytes == 8 ? 24 : 16;
+    LdsLayout L{0, 0, 0, 0, 0};
+    L.cls = 0;
+    L.adj = align16(cap_classes * 2 * word_bytes);
+    L.map = align16(L.adj + rows * nb * word_bytes);
+    L.hdr = align16(L.map + 2 * nb);
+    L.total = align16(L.hdr + (nb + 1) * hdr_bytes);
+    return L;
+}
+
+inline int slot_bytes_for(int word_bytes, int mmax) {
+    int b = kRecHeader + 2 * 8 * word_bytes + mmax * 2 * word_bytes;
+    return (b + 63) & ~63;
+}
+
+}  // namespace mcs

@@ -1,0 +1,937 @@
+// McSplit search kernels for gfx950 (CDNA4, wave64).
+//
+// The work of one search node is the paper's Solve body (Sec. II.B,
+// Algorithm 1): split every label class by adjacency to v (G side) and to w
+// (H side) -- filterDomain -- and bound the child with Eq. 1,
+//     bound = |M| + sum over classes of min(|L|, |R|),
+// pruning it when the bound cannot beat the incumbent.
+//
+// GPU mapping (ours, not the paper's CUDA design):
+//   * One wavefront runs one depth-first search at a time.  Classes are
+//     bitsets (L, R) of one machine word each (32-bit rows for graphs of at
+//     most 32 vertices, 64-bit otherwise); lane k holds class k.  A node has
+//     at most min(|V_G|, |V_H|) <= 64 classes, so one wave64 always holds it.
+//   * A batch evaluates up to 8 sibling children at once: lanes are split in
+//     segments of S = 8/16/32/64 lanes, each segment a copy of the classes and
+//     its own w.  Split, popcounts and the min() of Eq. 1 are per lane; the
+//     per-segment sum is a DPP reduction.  Prune decisions are wave-uniform,
+//     so the bound test never diverges.
+//   * A surviving child's classes are compacted (ballot + mbcnt) into the
+//     wave's LDS stack.  Stack frames hold the classes of each open node on
+//     the current path; the "v unmatched" child rewrites its parent frame in
+//     place, so the stack never needs more than m(m+1)/2 classes
+//     (m = min(|V_G|, |V_H|)).
+//   * Work sharing: a bounded lock-free ring of node records in HBM (Vyukov
+//     sequence numbers).  A busy wave donates the shallowest frame that still
+//     has unexplored children (as the paper's thread pool hands out shallow
+//     tasks first) when few records wait; idle waves take records or new
+//     instance roots.  The paper's shared loop index becomes the donated
+//     frame's remaining-children mask.
+//   * Incumbents: one int per instance, atomicMax at agent scope; the mapping
+//     of size s is written to a per-size slot by the unique wave that raised
+//     the incumbent to s.
+//   * Termination: a count of live work units (queued records plus busy
+//     waves), per instance and in total; every wave also leaves at the time
+//     limit, so the grid always drains.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mcs_layout.h"
+
+namespace mcs {
+
+#define DEV static __device__ __forceinline__
+
+template <typename W>
+struct Cls {
+    W L, R;
+};
+
+template <typename W>
+struct Hdr {
+    W rrem;         // children (w of the selected class) not yet taken
+    uint16_t base;  // first class of the frame in the LDS class stack
+    uint8_t K, d, v, sel, bound, flags, lsel, rsel;
+};
+
+template <typename W>
+struct RecHdr {
+    uint32_t inst;
+    uint8_t K, d, v, sel, bound, flags, lsel, rsel;
+    uint8_t pad[4];
+    W rrem;
+};
+
+static_assert(sizeof(Hdr<uint64_t>) == 24 && sizeof(Hdr<uint32_t>) == 16, "header layout");
+static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>) <= kRecHeader,
+              "record header layout");
+
+constexpr int kFlagUnmatched = 1;  // the "v unmatched" child is still to do
+
+// ---- bit helpers -----------------------------------------------------------
+
+DEV int popc(uint32_t x) { return __builtin_popcount(x); }
+DEV int popc(uint64_t x) { return __builtin_popcountll(x); }
+DEV int ctz(uint32_t x) { return __builtin_ctz(x); }
+DEV int ctz(uint64_t x) { return __builtin_ctzll(x); }
+
+// ---- wave helpers ----------------------------------------------------------
+
+DEV int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+DEV int sc(int x) { return __builtin_amdgcn_readfirstlane(x); }
+DEV uint32_t sc(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+DEV uint64_t sc(uint64_t x) {
+    uint32_t lo = sc((uint32_t)x), hi = sc((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+DEV int rl(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+DEV uint32_t rl(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+DEV uint64_t rl(uint64_t x, int l) {
+    uint32_t lo = rl((uint32_t)x, l), hi = rl((uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+DEV unsigned long long rl_ull(unsigned long long x, int l) { return (unsigned long long)rl((uint64_t)x, l); }
+
+DEV uint64_t ballot(bool p) { return __ballot(p); }
+DEV int mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+template <int CTRL>
+DEV int dpp(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
+
+// quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140: all lanes of an 8-lane
+// (resp. 16-lane) group end with the group's sum.
+DEV int sum8(int x) {
+    x += dpp<0xB1>(x);
+    x += dpp<0x4E>(x);
+    x += dpp<0x141>(x);
+    return x;
+}
+DEV int sum16(int x) {
+    x = sum8(x);
+    x += dpp<0x140>(x);
+    return x;
+}
+DEV int wave_sum(int x) {
+    int s = sum16(x);
+    return rl(s, 0) + rl(s, 16) + rl(s, 32) + rl(s, 48);
+}
+DEV uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+DEV uint32_t wave_min(uint32_t x) {
+    x = umin(x, (uint32_t)dpp<0xB1>((int)x));
+    x = umin(x, (uint32_t)dpp<0x4E>((int)x));
+    x = umin(x, (uint32_t)dpp<0x141>((int)x));
+    x = umin(x, (uint32_t)dpp<0x140>((int)x));
+    return umin(umin(rl(x, 0), rl(x, 16)), umin(rl(x, 32), rl(x, 48)));
+}
+
+// Orders LDS traffic between lanes of one wave (LDS executes a wave's
+// operations in order; this keeps the compiler from moving them).
+DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- device-scope atomics ----------------------------------------------------
+
+DEV int a_add(int *p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV unsigned a_addu(unsigned *p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV unsigned long long a_add64(unsigned long long *p, unsigned long long v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV int a_max(int *p, int v) {
+    return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void a_max64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void a_min64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+DEV T ld_acq(T *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+DEV T ld_rlx(T *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+DEV void st_rel(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); }
+DEV bool cas64(unsigned long long *p, unsigned long long expect, unsigned long long want) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_ACQ_REL,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+DEV unsigned long long now_ticks() { return wall_clock64(); }
+
+// ---- one wavefront's search ------------------------------------------------
+
+template <typename W, bool DIR>
+struct Searcher {
+    static constexpr int NB = bits_of<W>();  // vertices per row word
+    static constexpr int NR = DIR ? 4 : 2;   // adjacency row sets per instance
+
+    const SearchParams &P;
+    int lane;
+    W *sadj;        // [NR][NB]: G rows, H rows (out), then G, H in-rows
+    uint16_t *smap; // [NB] current path: g | h << 8
+    Hdr<W> *shdr;   // [NB + 1]
+    Cls<W> *scls;   // [cap_classes]
+
+    int inst, map_off;
+    // top frame, wave-uniform
+    int t, base, K, d, v, sel, bound, flags, lsel, rsel;
+    W rrem;
+    int logS;
+    // this lane's copy of class (lane mod S) of the top frame
+    W cL, cR;
+    int inc;
+    bool stop;
+    int since_check;
+    unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops;
+
+    __device__ Searcher(const SearchParams &p, uint8_t *lds) : P(p) {
+        lane = lane_id();
+        const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes);
+        scls = (Cls<W> *)(lds + L.cls);
+        sadj = (W *)(lds + L.adj);
+        smap = (uint16_t *)(lds + L.map);
+        shdr = (Hdr<W> *)(lds + L.hdr);
+        inst = -1;
+        map_off = 0;
+        stop = false;
+        since_check = 0;
+        pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = 0;
+        inc = 0;
+        t = -1;
+    }
+
+    __device__ void fail() {
+        if (lane == 0) {
+            __hip_atomic_store(&P.g->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        stop = true;
+    }
+
+    // -- frame registers -----------------------------------------------------
+
+    __device__ void load_regs() {
+        logS = K <= 8 ? 3 : K <= 16 ? 4 : K <= 32 ? 5 : 6;
+        int k = lane & ((1 << logS) - 1);
+        cL = 0;
+        cR = 0;
+        if (k < K) {
+            Cls<W> c = scls[base + k];
+            cL = c.L;
+            cR = c.R;
+        }
+    }
+
+    // selectLabelClass + selectVertex: the class with the smallest
+    // max(|L|, |R|), ties to the smallest vertex of L; v = that vertex.
+    __device__ void select() {
+        uint32_t key = 0xFFFFFFFFu;
+        if (lane < K) {
+            int nl = popc(cL), nr = popc(cR);
+            key = ((uint32_t)(nl > nr ? nl : nr) << 8) | (uint32_t)ctz(cL);
+        }
+        uint32_t mk = wave_min(key);
+        int who = ctz((uint64_t)ballot(key == mk));
+        sel = who;
+        v = (int)(mk & 0xFF);
+        rrem = rl(cR, who);
+        lsel = popc(rl(cL, who));
+        rsel = popc(rrem);
+    }
+
+    __device__ void save_top() {
+        if (lane == 0) {
+            Hdr<W> h;
+            h.rrem = rrem;
+            h.base = (uint16_t)base;
+            h.K = (uint8_t)K;
+            h.d = (uint8_t)d;
+            h.v = (uint8_t)v;
+            h.sel = (uint8_t)sel;
+            h.bound = (uint8_t)bound;
+            h.flags = (uint8_t)flags;
+            h.lsel = (uint8_t)lsel;
+            h.rsel = (uint8_t)rsel;
+            shdr[t] = h;
+        }
+    }
+
+    __device__ void read_hdr(int i) {
+        Hdr<W> h = shdr[i];
+        rrem = sc((W)h.rrem);
+        base = sc((int)h.base);
+        K = sc((int)h.K);
+        d = sc((int)h.d);
+        v = sc((int)h.v);
+        sel = sc((int)h.sel);
+        bound = sc((int)h.bound);
+        flags = sc((int)h.flags);
+        lsel = sc((int)h.lsel);
+        rsel = sc((int)h.rsel);
+    }
+
+    // -- instances -------------------------------------------------------------
+
+    __device__ void set_instance(int i) {
+        if (i != inst) {
+            const W *src = (const W *)P.adj + (size_t)i * NR * NB;
+            for (int j = lane; j < NR * NB; j += 64)
+                sadj[j] = src[j];
+            inst = i;
+            map_off = (int)P.inst[i].map_off;
+        }
+        int g = 0;
+        if (lane == 0)
+            g = ld_rlx(&P.inc[i]);
+        inc = rl(g, 0);
+        wave_sync();
+    }
+
+    __device__ void start_root(int i) {
+        set_instance(i);
+        DevInst di = P.inst[i];
+        K = sc((int)di.K0);
+        if (lane < K) {
+            const Cls<W> *rc = (const Cls<W> *)P.rootcls + sc((int)di.cls_off);
+            scls[lane] = rc[lane];
+        }
+        wave_sync();
+        t = 0;
+        base = 0;
+        d = 0;
+        load_regs();
+        int contrib = 0;
+        if (lane < K) {
+            int nl = popc(cL), nr = popc(cR);
+            contrib = nl < nr ? nl : nr;
+        }
+        bound = wave_sum(contrib);
+        pend_nodes += 1;  // the root
+        if (K == 0 || bound <= inc) {
+            rrem = 0;
+            flags = 0;
+            return;
+        }
+        flags = kFlagUnmatched;
+        select();
+    }
+
+    // -- incumbent ---------------------------------------------------------------
+
+    __device__ void improve(int size) {
+        int old = 0;
+        if (lane == 0)
+            old = a_max(&P.inc[inst], size);
+        old = rl(old, 0);
+        if (old < size) {
+            uint16_t *dst = P.maps + map_off + size * (size - 1) / 2;
+            if (lane < size)
+                dst[lane] = smap[lane];
+            if (lane == 0)
+                a_max64(&P.t_best[inst], ((unsigned long long)size << 48) |
+                                             (now_ticks() & 0xFFFFFFFFFFFFull));
+        }
+        inc = old > size ? old : size;
+    }
+
+    // -- one batch of sibling children -----------------------------------------
+
+    __device__ void batch() {
+        const int S = 1 << logS;
+        int C = popc(rrem);
+        if (C > P.cmax)
+            C = P.cmax;
+        if (C > (64 >> logS))
+            C = 64 >> logS;
+        const int seg = lane >> logS;
+
+        // w of this lane's segment: the seg-th remaining child
+        int myw = 0;
+        {
+            W rr = rrem;
+            for (int c = 0; c < C; ++c) {
+                int wc = ctz(rr);
+                if (seg == c)
+                    myw = wc;
+                rr &= rr - 1;
+            }
+        }
+        const bool act = seg < C;
+        const W vb = (W)1 << v;
+        const W Lx = cL & ~vb;
+        const W Rx = cR & ~((W)1 << myw);
+
+        // filterDomain: parts by adjacency letter
+        W pl[NR], pr[NR];
+        const W go = sadj[v], ho = sadj[NB + myw];
+        if (!DIR) {
+            pl[0] = Lx & ~go;
+            pr[0] = Rx & ~ho;
+            pl[1] = Lx & go;
+            pr[1] = Rx & ho;
+        } else {
+            const W gi = sadj[2 * NB + v], hi = sadj[3 * NB + myw];
+            pl[0] = Lx & ~go & ~gi;
+            pr[0] = Rx & ~ho & ~hi;
+            pl[1] = Lx & go & ~gi;
+            pr[1] = Rx & ho & ~hi;
+            pl[2] = Lx & ~go & gi;
+            pr[2] = Rx & ~ho & hi;
+            pl[3] = Lx & go & gi;
+            pr[3] = Rx & ho & hi;
+        }
+        int contrib = 0;
+#pragma unroll
+        for (int a = 0; a < NR; ++a) {
+            int nl = popc(pl[a]), nr = popc(pr[a]);
+            contrib += nl < nr ? nl : nr;
+        }
+        if (!act)
+            contrib = 0;
+
+        // Eq. 1 per segment
+        uint32_t surv = 0;
+        int first = -1, fb = 0;
+        if (logS == 6) {
+            int b = d + 1 + wave_sum(contrib);
+            if (b > inc) {
+                surv = 1;
+                first = 0;
+                fb = b;
+            }
+        } else {
+            int s = logS == 3 ? sum8(contrib) : sum16(contrib);
+            for (int c = 0; c < C; ++c) {
+                int sum = logS == 5 ? rl(s, c << 5) + rl(s, (c << 5) + 16) : rl(s, c << logS);
+                int b = d + 1 + sum;
+                if (b > inc) {
+                    surv |= 1u << c;
+                    if (first < 0) {
+                        first = c;
+                        fb = b;
+                    }
+                }
+            }
+        }
+        int nsurv = __builtin_popcount(surv);
+        pend_nodes += (unsigned long long)(C - nsurv + (nsurv ? 1 : 0));
+        n_batches += 1;
+        n_children += (unsigned long long)C;
+        n_lanes += (unsigned long long)(C * K);
+
+        // drop pruned children and the one we descend into
+        int wF = 0;
+        {
+            W rr = rrem;
+            for (int c = 0; c < C; ++c) {
+                int wc = ctz(rr);
+                rr &= rr - 1;
+                bool keep = ((surv >> c) & 1u) && c != first;
+                if (!keep)
+                    rrem &= ~((W)1 << wc);
+                if (c == first)
+                    wF = wc;
+            }
+        }
+        if (first < 0)
+            return;
+
+        // compact the surviving child's non-empty classes into a new frame
+        const bool inF = seg == first;
+        int pos[NR];
+        bool ne[NR];
+        int K2 = 0;
+#pragma unroll
+        for (int a = 0; a < NR; ++a) {
+            ne[a] = inF && pl[a] != 0 && pr[a] != 0;
+            uint64_t m = ballot(ne[a]);
+            pos[a] = K2 + mbcnt(m);
+            K2 += __builtin_popcountll(m);
+        }
+        const int nb = base + K;
+        if (nb + K2 > P.cap_classes) {
+            fail();
+            return;
+        }
+#pragma unroll
+        for (int a = 0; a < NR; ++a)
+            if (ne[a]) {
+                Cls<W> c;
+                c.L = pl[a];
+                c.R = pr[a];
+                scls[nb + pos[a]] = c;
+            }
+        if (lane == 0)
+            smap[d] = (uint16_t)(v | (wF << 8));
+        save_top();
+        wave_sync();
+        if (d + 1 > inc)
+            improve(d + 1);
+        if (K2 == 0)
+            return;  // a leaf: nothing left to split
+        t += 1;
+        base = nb;
+        K = K2;
+        d += 1;
+        bound = fb;
+        flags = kFlagUnmatched;
+        load_regs();
+        select();
+        (void)S;
+    }
+
+    // -- the "v unmatched" child, done in place on the top frame -----------------
+    // Its bound follows from the parent's: only the selected class loses v.
+    __device__ bool unmatched() {
+        flags = 0;
+        int ub = bound - (lsel <= rsel ? 1 : 0);
+        pend_nodes += 1;
+        if (ub <= inc)
+            return false;
+        const W vb = (W)1 << v;
+        if (lsel == 1) {
+            int last = K - 1;
+            if (sel != last && lane == last) {
+                Cls<W> c;
+                c.L = cL;
+                c.R = cR;
+                scls[base + sel] = c;
+            }
+            K = last;
+            wave_sync();
+            bound = ub;
+            if (K == 0)
+                return false;
+            load_regs();
+        } else {
+            int k = lane & ((1 << logS) - 1);
+            if (k == sel)
+                cL &= ~vb;
+            if (lane == sel)
+                scls[base + sel].L = cL;
+            wave_sync();
+            bound = ub;
+        }
+        select();
+        flags = kFlagUnmatched;
+        return true;
+    }
+
+    // Back to the parent frame; false when the stack is empty.
+    __device__ bool pop() {
+        for (;;) {
+            t -= 1;
+            if (t < 0)
+                return false;
+            read_hdr(t);
+            if (P.reprune && bound <= inc)
+                continue;
+            if (rrem == 0 && !(flags & kFlagUnmatched))
+                continue;
+            load_regs();
+            return true;
+        }
+    }
+
+    // -- work sharing ------------------------------------------------------------
+
+    __device__ bool reserve(unsigned long long &ticket) {
+        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+        int ok = 0;
+        unsigned long long tk = 0;
+        if (lane == 0) {
+            for (int tries = 0; tries < 16; ++tries) {
+                unsigned long long tl = ld_rlx(&P.g->tail);
+                unsigned long long s = ld_acq(&P.seq[tl & mask]);
+                if (s == tl) {
+                    if (cas64(&P.g->tail, tl, tl + 1)) {
+                        ok = 1;
+                        tk = tl;
+                        break;
+                    }
+                } else if (s < tl) {
+                    break;  // full
+                }
+            }
+        }
+        ok = rl(ok, 0);
+        ticket = rl_ull(tk, 0);
+        return ok != 0;
+    }
+
+    // Give the shallowest open frame's remaining children to the queue.
+    __device__ void donate() {
+        int b = -1;
+        W grr = 0;
+        int gfl = 0;
+        for (int i = 0; i < t; ++i) {
+            W r = sc((W)shdr[i].rrem);
+            int f = sc((int)shdr[i].flags);
+            if (r != 0 || (f & kFlagUnmatched)) {
+                b = i;
+                grr = r;
+                gfl = f & kFlagUnmatched;
+                break;
+            }
+        }
+        W keep_r = 0;
+        if (b < 0) {
+            int n = popc(rrem);
+            if (n >= 2) {
+                W r = rrem, kept = 0;
+                for (int c = 0; c < n - n / 2; ++c) {
+                    kept |= r & (~r + 1);
+                    r &= r - 1;
+                }
+                grr = r;
+                gfl = flags & kFlagUnmatched;
+                keep_r = kept;
+            } else if (n == 1 && (flags & kFlagUnmatched)) {
+                grr = 0;
+                gfl = kFlagUnmatched;
+                keep_r = rrem;
+            } else {
+                return;
+            }
+            b = t;
+        }
+        unsigned long long ticket;
+        if (!reserve(ticket))
+            return;
+        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+        uint8_t *slot = P.slots + (size_t)(ticket & mask) * (size_t)P.slot_bytes;
+        int fK, fd, fbase;
+        RecHdr<W> rh;
+        if (b == t) {
+            fK = K;
+            fd = d;
+            fbase = base;
+            rh.v = (uint8_t)v;
+            rh.sel = (uint8_t)sel;
+            rh.bound = (uint8_t)bound;
+            rh.lsel = (uint8_t)lsel;
+            rh.rsel = (uint8_t)rsel;
+        } else {
+            Hdr<W> h = shdr[b];
+            fK = sc((int)h.K);
+            fd = sc((int)h.d);
+            fbase = sc((int)h.base);
+            rh.v = h.v;
+            rh.sel = h.sel;
+            rh.bound = h.bound;
+            rh.lsel = h.lsel;
+            rh.rsel = h.rsel;
+        }
+        rh.inst = (uint32_t)inst;
+        rh.K = (uint8_t)fK;
+        rh.d = (uint8_t)fd;
+        rh.flags = (uint8_t)gfl;
+        rh.pad[0] = rh.pad[1] = rh.pad[2] = rh.pad[3] = 0;
+        rh.rrem = grr;
+        if (lane == 0)
+            *(RecHdr<W> *)slot = rh;
+        uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
+        if (lane < fd)
+            rmap[lane] = smap[lane];
+        Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
+        if (lane < fK)
+            rcls[lane] = scls[fbase + lane];
+        if (lane == 0) {
+            a_add(&P.open[inst], 1);
+            a_add(&P.g->open_total, 1);
+            st_rel(&P.seq[ticket & mask], ticket + 1);
+        }
+        if (b == t) {
+            rrem = keep_r;
+            flags = 0;
+        } else if (lane == 0) {
+            shdr[b].rrem = 0;
+            shdr[b].flags = 0;
+        }
+        wave_sync();
+        n_don += 1;
+    }
+
+    __device__ bool take_record() {
+        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+        int ok = 0;
+        unsigned long long hd = 0;
+        if (lane == 0) {
+            for (int tries = 0; tries < 16; ++tries) {
+                unsigned long long h = ld_rlx(&P.g->head);
+                unsigned long long s = ld_acq(&P.seq[h & mask]);
+                if (s == h + 1) {
+                    if (cas64(&P.g->head, h, h + 1)) {
+                        ok = 1;
+                        hd = h;
+                        break;
+                    }
+                } else if (s < h + 1) {
+                    break;  // empty, or its producer is still writing
+                }
+            }
+        }
+        ok = rl(ok, 0);
+        if (!ok)
+            return false;
+        hd = rl_ull(hd, 0);
+        const uint8_t *slot = P.slots + (size_t)(hd & mask) * (size_t)P.slot_bytes;
+        RecHdr<W> rh = *(const RecHdr<W> *)slot;
+        int ri = sc((int)rh.inst);
+        K = sc((int)rh.K);
+        d = sc((int)rh.d);
+        v = sc((int)rh.v);
+        sel = sc((int)rh.sel);
+        bound = sc((int)rh.bound);
+        flags = sc((int)rh.flags);
+        lsel = sc((int)rh.lsel);
+        rsel = sc((int)rh.rsel);
+        rrem = sc((W)rh.rrem);
+        const uint16_t *rmap = (const uint16_t *)(slot + rec_map_off<W>());
+        const Cls<W> *rcls = (const Cls<W> *)(slot + rec_cls_off<W>());
+        uint16_t mp = 0;
+        Cls<W> cc;
+        cc.L = 0;
+        cc.R = 0;
+        if (lane < d)
+            mp = rmap[lane];
+        if (lane < K)
+            cc = rcls[lane];
+        // every lane's loads are done (waited on) before the slot is released
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0)
+            st_rel(&P.seq[hd & mask], hd + (unsigned long long)P.ring_slots);
+        set_instance(ri);
+        if (lane < d)
+            smap[lane] = mp;
+        if (lane < K)
+            scls[lane] = cc;
+        wave_sync();
+        t = 0;
+        base = 0;
+        load_regs();
+        if (bound <= inc) {
+            rrem = 0;
+            flags = 0;
+        }
+        n_pops += 1;
+        return true;
+    }
+
+    __device__ bool claim_instance() {
+        int i = -1;
+        if (lane == 0) {
+            unsigned nx = ld_acq(&P.g->next_inst);
+            if (nx < (unsigned)P.count) {
+                a_add(&P.g->open_total, 1);
+                unsigned x = a_addu(&P.g->next_inst, 1u);
+                if (x < (unsigned)P.count) {
+                    a_add(&P.open[x], 1);
+                    i = (int)x;
+                } else {
+                    a_add(&P.g->open_total, -1);
+                }
+            }
+        }
+        i = rl(i, 0);
+        if (i < 0)
+            return false;
+        start_root(i);
+        return true;
+    }
+
+    __device__ void flush_nodes() {
+        if (pend_nodes && inst >= 0 && lane == 0) {
+            a_add64(&P.nodes[inst], pend_nodes);
+            if (P.node_limit > 0) {
+                unsigned long long tot = a_add64(&P.g->node_total, pend_nodes) + pend_nodes;
+                if ((long long)tot > P.node_limit)
+                    __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        pend_nodes = 0;
+    }
+
+    // Periodic: refresh the incumbent, honour limits, feed the queue.
+    __device__ void check() {
+        since_check = 0;
+        unsigned long long hd = 0, tl = 0;
+        int gi = 0, hungry = 0;
+        unsigned st = 0;
+        if (lane == 0) {
+            tl = ld_rlx(&P.g->tail);
+            hd = ld_rlx(&P.g->head);
+            gi = ld_rlx(&P.inc[inst]);
+            st = ld_rlx(&P.g->stop);
+            hungry = ld_rlx(&P.g->idle);
+        }
+        gi = rl(gi, 0);
+        if (gi > inc)
+            inc = gi;
+        if (rl((int)st, 0)) {
+            stop = true;
+            return;
+        }
+        if (now_ticks() - t_start > P.limit_ticks) {
+            if (lane == 0)
+                __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            stop = true;
+            return;
+        }
+        if (P.node_limit > 0)
+            flush_nodes();
+        if (!P.single_wave) {
+            // donate while fewer nodes wait than wavefronts are hungry
+            long long waiting = (long long)(rl_ull(tl, 0) - rl_ull(hd, 0));
+            long long want = rl(hungry, 0);
+            if (want > P.donate_low)
+                want = P.donate_low;
+            if (waiting < want)
+                donate();
+        }
+    }
+
+    // Depth-first search from the frame loaded at level 0.
+    __device__ void run() {
+        while (!stop) {
+            if (rrem != 0) {
+                batch();
+            } else if (flags & kFlagUnmatched) {
+                if (!unmatched() && !pop())
+                    break;
+            } else if (!pop()) {
+                break;
+            }
+            if (++since_check >= P.check_interval)
+                check();
+        }
+    }
+
+    __device__ void finish_unit() {
+        flush_nodes();
+        if (!stop && lane == 0) {
+            int r = a_add(&P.open[inst], -1);
+            if (r == 1)
+                __hip_atomic_store(&P.t_proof[inst], now_ticks(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            a_add(&P.g->open_total, -1);
+        }
+    }
+
+    __device__ void main_loop() {
+        t_start = now_ticks();
+        if (lane == 0)
+            a_min64(&P.g->t0, t_start);
+        bool idle = false;
+        int backoff = 0;
+        for (;;) {
+            bool got = false;
+            if (!P.single_wave)
+                got = take_record();
+            if (!got)
+                got = claim_instance();
+            if (got) {
+                if (idle && lane == 0)
+                    a_add(&P.g->idle, -1);
+                idle = false;
+                backoff = 0;
+                run();
+                finish_unit();
+                if (stop)
+                    break;
+                continue;
+            }
+            if (!idle && lane == 0)
+                a_add(&P.g->idle, 1);
+            idle = true;
+            unsigned nx = 0, st = 0;
+            int ot = 0;
+            if (lane == 0) {
+                nx = ld_acq(&P.g->next_inst);
+                ot = ld_acq(&P.g->open_total);
+                st = ld_rlx(&P.g->stop);
+            }
+            nx = rl(nx, 0);
+            ot = rl(ot, 0);
+            st = rl(st, 0);
+            if (st)
+                break;
+            if (nx >= (unsigned)P.count && ot == 0)
+                break;
+            if (now_ticks() - t_start > P.limit_ticks) {
+                if (lane == 0)
+                    __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            // back off: 2, 4, ... 64 sleeps of 64 x 8 cycles
+            backoff = backoff < 64 ? (backoff ? 2 * backoff : 2) : 64;
+            for (int i = 0; i < backoff; ++i)
+                __builtin_amdgcn_s_sleep(8);
+        }
+        if (idle && lane == 0)
+            a_add(&P.g->idle, -1);
+        if (lane == 0) {
+            a_add64(&P.g->batches, n_batches);
+            a_add64(&P.g->children, n_children);
+            a_add64(&P.g->lane_slots, n_lanes);
+            a_add64(&P.g->donations, n_don);
+            a_add64(&P.g->pops, n_pops);
+        }
+    }
+};
+
+template <typename W, bool DIR>
+__global__ void __launch_bounds__(256) mcs_search_kernel(SearchParams P) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int wv = threadIdx.x >> 6;
+    if (P.single_wave && (blockIdx.x != 0 || wv != 0))
+        return;
+    Searcher<W, DIR> s(P, smem + (size_t)wv * (size_t)P.lds_per_wave);
+    s.main_loop();
+}
+
+// Clears the per-run state with plain stores (no memset nodes, so the pair
+// of kernels can be replayed from a HIP graph).
+__global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = tid; i < R.count; i += stride) {
+        R.inc[i] = R.inst[i].lb;
+        R.open[i] = 0;
+        R.nodes[i] = 0;
+        R.t_best[i] = 0;
+        R.t_proof[i] = 0;
+    }
+    for (int i = tid; i < R.ring_slots; i += stride)
+        R.seq[i] = (unsigned long long)i;
+    if (tid == 0) {
+        DevGlobals z = {};
+        z.t0 = ~0ull;
+        *R.g = z;
+    }
+}
+
+}  // namespace mcs
+
+// ---- launch entry points used by the host driver ---------------------------
+
+extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed) {
+    if (word_bytes == 4)
+        return directed ? (void *)mcs::mcs_search_kernel<uint32_t, true>
+                        : (void *)mcs::mcs_search_kernel<uint32_t, false>;
+    return directed ? (void *)mcs::mcs_search_kernel<uint64_t, true>
+                    : (void *)mcs::mcs_search_kernel<uint64_t, false>;
+}
+
+extern "C" void *mcs_internal_reset_kernel(void) { return (void *)mcs::mcs_reset_kernel; }

@@ -1,0 +1,134 @@
+"""The C ABI library without a GPU: it loads, exports every entry point that
+include/mcs.h declares, and rejects malformed input before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import mcs_instances as mi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(mcs_\w+)\s*\(", src))
+    return names
+
+
+def test_exports_every_declared_symbol(mcs_lib):
+    declared = _declared()
+    assert {"mcs_solve", "mcs_solve_batch", "mcs_plan_create", "mcs_plan_run",
+            "mcs_workspace_size", "mcs_status_string"} <= declared
+    for name in sorted(declared):
+        assert hasattr(mcs_lib, name), name
+
+
+def test_binding_covers_header(mcs_lib):
+    from paper_1908_06418_amd import _abi
+    assert {n for n, _, _ in _abi.SIGNATURES} == _declared()
+
+
+def test_struct_sizes_match_header():
+    """ctypes mirrors have the C layout (compiled probe of include/mcs.h)."""
+    import subprocess
+    import tempfile
+    from paper_1908_06418_amd import _abi
+    src = r'''
+#include <stdio.h>
+#include "mcs.h"
+int main(void) { printf("%zu %zu %zu %zu %zu\n", sizeof(mcs_graph), sizeof(mcs_tuning),
+  sizeof(mcs_opts), sizeof(mcs_result), sizeof(mcs_stats)); return 0; }
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "p.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "p")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        sizes = [int(x) for x in subprocess.check_output([exe]).split()]
+    assert sizes == [ctypes.sizeof(_abi.mcs_graph), ctypes.sizeof(_abi.mcs_tuning),
+                     ctypes.sizeof(_abi.mcs_opts), ctypes.sizeof(_abi.mcs_result),
+                     ctypes.sizeof(_abi.mcs_stats)]
+
+
+def _create(pairs):
+    from paper_1908_06418_amd import Plan
+    return Plan(pairs)
+
+
+def _status(exc):
+    return exc.value.status
+
+
+def test_status_strings(mcs_lib):
+    for s in (0, 1, -1, -2, -3, -4, -5):
+        assert mcs_lib.mcs_status_string(s)
+    assert b"unknown" in mcs_lib.mcs_status_string(42)
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda G, H: (dict(G, n=65, rows=[0] * 65), H), -2),
+    (lambda G, H: (dict(G, n=-1), H), -1),
+    (lambda G, H: (dict(G, rows=[G["rows"][0] | 1] + G["rows"][1:]), H), -1),   # self loop
+    (lambda G, H: (dict(G, rows=[G["rows"][0] | (1 << 20)] + G["rows"][1:]), H), -1),  # bit >= n
+    (lambda G, H: (dict(G, rows=[G["rows"][0] ^ 2] + G["rows"][1:]), H), -1),   # asymmetric
+    (lambda G, H: (dict(G, directed=True), H), -1),                             # mixed directed
+    (lambda G, H: (dict(G, label=[0] * G["n"]), H), -1),                        # label on one side
+])
+def test_validation_errors(mcs_lib, mutate, status):
+    from paper_1908_06418_amd import McsError
+    G = mi.er_graph(12, 0.4, 1)
+    H = mi.er_graph(12, 0.4, 2)
+    G, H = mutate(G, H)
+    with pytest.raises(McsError) as e:
+        _create([(G, H)])
+    assert _status(e) == status
+    assert mcs_lib.mcs_last_error()
+
+
+def test_null_and_count_errors(mcs_lib):
+    from paper_1908_06418_amd import _abi
+    h = ctypes.c_void_p()
+    assert mcs_lib.mcs_plan_create(0, None, None, None, ctypes.byref(h)) == _abi.MCS_E_INVALID
+    assert mcs_lib.mcs_plan_create(1, None, None, None, ctypes.byref(h)) == _abi.MCS_E_INVALID
+    res = (_abi.mcs_result * 1)()
+    res[0].size = 7
+    assert mcs_lib.mcs_solve(None, None, None, None, 0, None, res) == _abi.MCS_E_INVALID
+    assert res[0].size == -1
+
+
+def test_upload_rejects_small_workspace(mcs_lib):
+    from paper_1908_06418_amd import _abi
+    from paper_1908_06418_amd import _Marshal
+    m = _Marshal([(mi.er_graph(10, 0.3, 1), mi.er_graph(10, 0.3, 2))])
+    h = ctypes.c_void_p()
+    assert mcs_lib.mcs_plan_create(1, m.G, m.H, None, ctypes.byref(h)) == 0
+    need = mcs_lib.mcs_plan_workspace_size(h)
+    assert need > 0
+    assert mcs_lib.mcs_plan_upload(h, None, need, None) == _abi.MCS_E_WORKSPACE
+    assert mcs_lib.mcs_plan_upload(h, ctypes.c_void_p(256), need - 1, None) == _abi.MCS_E_WORKSPACE
+    assert mcs_lib.mcs_plan_upload(h, ctypes.c_void_p(257), need, None) == _abi.MCS_E_WORKSPACE
+    assert mcs_lib.mcs_plan_run(h, None) == _abi.MCS_E_WORKSPACE
+    mcs_lib.mcs_plan_destroy(h)
+
+
+def test_workspace_size_grows_with_batch(mcs_lib):
+    from paper_1908_06418_amd import workspace_size
+    one = workspace_size(mi.pairs_c4(1))
+    many = workspace_size(mi.pairs_c4(64))
+    assert 0 < one < many
+
+
+def test_product_package_never_imports_oracle():
+    pkg = os.path.join(ROOT, "paper_1908_06418_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in src and "from oracle" not in src, fn
+                assert "mcsplit_oracle" not in src and "liboracle" not in src, fn

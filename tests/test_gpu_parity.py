@@ -1,0 +1,274 @@
+"""GPU parity: the HIP search (through the C ABI) against the oracle.
+
+Sizes must be identical (integer search, exact); every returned mapping must be
+a valid common induced subgraph of its size.  Several optimal mappings can
+exist (the paper's Fig. 2), so mappings are checked for validity, not equality.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import mcs_instances as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _solve_batch(pairs, **kw):
+    from paper_1908_06418_amd import solve_batch
+    return solve_batch(pairs, **kw)
+
+
+def _check(pairs, res, expect=None):
+    for i, ((G, H), r) in enumerate(zip(pairs, res)):
+        errs = oracle.check.mapping_errors(G, H, r.mapping)
+        assert not errs, (i, errs[:3])
+        assert len(r.mapping) == r.size
+        if expect is not None:
+            assert r.size == expect[i], (i, r.size, expect[i])
+
+
+def test_c1_single_pair(gpu):
+    (G, H), = mi.pair_c1()
+    want = oracle.mcs(G, H)["size"]
+    for rep in range(3):
+        _say(f"c1 rep {rep}")
+        r = _solve_batch([(G, H)], time_limit_s=30)[0]
+        assert r.optimal and r.size == want
+        assert oracle.check.is_valid(G, H, r.mapping)
+
+
+@pytest.mark.parametrize("kind", ["undirected", "directed", "labelled", "directed_labelled"])
+def test_single_wave_reproduces_oracle_node_count(gpu, kind):
+    """One wavefront, one child per batch, no re-pruning: the GPU walks the
+    same tree as the sequential oracle, so even the node counts agree."""
+    rng = np.random.default_rng({"undirected": 1, "directed": 2, "labelled": 3,
+                                 "directed_labelled": 4}[kind])
+    directed = kind.startswith("directed")
+    nlab = 3 if "labelled" in kind else 0
+    pairs = []
+    for i in range(12):
+        n1, n2 = int(rng.integers(4, 19)), int(rng.integers(4, 19))
+        p = float(rng.uniform(0.1, 0.7))
+        pairs.append((mi.random_small(rng, n1, p, directed, nlab),
+                      mi.random_small(rng, n2, p, directed, nlab)))
+    if kind == "undirected":
+        pairs += mi.pair_c1()
+    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1}
+    _say(f"single-wave {kind}: {len(pairs)} pairs")
+    res = _solve_batch(pairs, tuning=tun, time_limit_s=60)
+    for (G, H), r in zip(pairs, res):
+        o = oracle.mcs(G, H)
+        assert r.size == o["size"]
+        assert r.optimal
+        assert r.nodes == o["nodes"], (r.nodes, o["nodes"])
+        assert oracle.check.is_valid(G, H, r.mapping)
+
+
+@pytest.mark.parametrize("directed,nlab", [(False, 0), (True, 0), (False, 4), (True, 3)])
+def test_random_sweep_batched(gpu, directed, nlab):
+    """Random pairs of every size from 0 to 24 vertices and densities 0..1,
+    solved in one batched launch."""
+    rng = np.random.default_rng(1000 + 10 * directed + nlab)
+    pairs = []
+    for i in range(160):
+        n1, n2 = int(rng.integers(0, 25)), int(rng.integers(0, 25))
+        p = float(rng.choice([0.0, 1.0, rng.uniform(0, 1), rng.uniform(0, 1)]))
+        pairs.append((mi.random_small(rng, n1, p, directed, nlab),
+                      mi.random_small(rng, n2, p, directed, nlab)))
+    # near-complete digraphs can take the oracle minutes (bound one above the
+    # optimum): keep the pairs it proves within a node budget
+    ora = [oracle.mcs(G, H, node_limit=2_000_000) for G, H in pairs]
+    pairs = [pq for pq, o in zip(pairs, ora) if o["complete"]]
+    want = [o["size"] for o in ora if o["complete"]]
+    assert len(pairs) >= 140
+    _say(f"sweep directed={directed} nlab={nlab}: {len(pairs)} pairs")
+    res = _solve_batch(pairs, time_limit_s=60)
+    _check(pairs, res, want)
+    assert all(r.optimal for r in res)
+
+
+def test_edge_cases(gpu):
+    rng = np.random.default_rng(5)
+    g64 = mi.random_small(rng, 64, 0.5)
+    g40 = mi.random_small(rng, 40, 0.2)
+    cases = [
+        (mi.empty_graph(0), mi.empty_graph(0), 0),
+        (mi.empty_graph(0), mi.complete_graph(5), 0),
+        (mi.empty_graph(1), mi.empty_graph(1), 1),
+        (mi.complete_graph(1), mi.empty_graph(7), 1),
+        (mi.complete_graph(5), mi.empty_graph(7), 1),
+        (mi.empty_graph(64), mi.empty_graph(64), 64),
+        (mi.complete_graph(64), mi.complete_graph(64), 64),
+        (mi.complete_graph(64), mi.complete_graph(3), 3),
+        (mi.empty_graph(33), mi.empty_graph(31), 31),
+        (g64, mi.permute(g64, list(rng.permutation(64))), 64),
+        (g40, mi.induced(g40, list(range(0, 40, 2))), 20),
+    ]
+    pairs = [(G, H) for G, H, _ in cases]
+    _say("edge cases")
+    res = _solve_batch(pairs, time_limit_s=60)
+    _check(pairs, res, [s for _, _, s in cases])
+    assert all(r.optimal for r in res)
+
+
+def test_word_size_boundary(gpu):
+    """32 vertices use 32-bit rows, 33 use 64-bit rows: same answers."""
+    rng = np.random.default_rng(8)
+    pairs = [(mi.random_small(rng, 32, 0.5), mi.random_small(rng, 20, 0.5)) for _ in range(4)]
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    _say("word size 32")
+    r32 = _solve_batch(pairs, time_limit_s=60)
+    big = pairs + [(mi.empty_graph(33), mi.empty_graph(1))]
+    _say("word size 64")
+    r64 = _solve_batch(big, time_limit_s=60)
+    _check(pairs, r32, want)
+    _check(big, r64, want + [1])
+
+
+def test_invariants_on_gpu(gpu):
+    rng = np.random.default_rng(9)
+    base = []
+    for i in range(12):
+        directed = bool(i % 2)
+        n = int(rng.integers(10, 22))
+        p = float(rng.uniform(0.2, 0.6))
+        base.append((mi.random_small(rng, n, p, directed),
+                     mi.random_small(rng, int(rng.integers(10, 22)), p, directed)))
+    swapped = [(H, G) for G, H in base]
+    comp = [(mi.complement(G), mi.complement(H)) for G, H in base]
+    perm = [(mi.permute(G, list(rng.permutation(G["n"]))),
+             mi.permute(H, list(rng.permutation(H["n"])))) for G, H in base]
+    _say("invariants")
+    res = _solve_batch(base + swapped + comp + perm, time_limit_s=60)
+    k = len(base)
+    sizes = [r.size for r in res]
+    assert sizes[:k] == sizes[k:2 * k] == sizes[2 * k:3 * k] == sizes[3 * k:]
+    _check(base + swapped + comp + perm, res)
+
+
+_TUNING_CASES = {}
+
+
+def _tuning_case():
+    if not _TUNING_CASES:
+        pairs = mi.pairs_c4(48, start=200)
+        want = [oracle.mcs(G, H, node_limit=3_000_000) for G, H in pairs]
+        keep = [i for i, w in enumerate(want) if w["complete"]]
+        _TUNING_CASES["pairs"] = [pairs[i] for i in keep]
+        _TUNING_CASES["sizes"] = [want[i]["size"] for i in keep]
+    return _TUNING_CASES["pairs"], _TUNING_CASES["sizes"]
+
+
+@pytest.mark.parametrize("tun", [
+    {"children_per_wave": 1},
+    {"children_per_wave": 2},
+    {"children_per_wave": 4},
+    {"children_per_wave": 8, "check_interval": 1},
+    {"ring_slots": 2, "check_interval": 1},
+    {"waves_per_cu": 1},
+    {"no_reprune": 1, "donate_low": 1},
+    {"use_graph": 1},
+])
+def test_tunings_do_not_change_sizes(gpu, tun):
+    pairs, sizes = _tuning_case()
+    _say(f"tuning {tun}: {len(pairs)} pairs")
+    res = _solve_batch(pairs, tuning=tun, time_limit_s=60)
+    _check(pairs, res, sizes)
+
+
+def test_graph_replays_match_eager(gpu):
+    """The HIP graph (reset kernel + search kernel) replayed several times,
+    with eager work between replays, gives the eager result every time."""
+    import torch
+    from paper_1908_06418_amd import Plan
+    pairs = [pq for pq in mi.pairs_c4(128, start=1000) if pq[0]["n"] <= 24][:64]
+    eager = _solve_batch(pairs, time_limit_s=60)
+    plan = Plan(pairs, time_limit_s=60, tuning={"use_graph": 1}).upload()
+    for rep in range(3):
+        _say(f"graph replay {rep}")
+        plan.run()
+        res = plan.results()
+        assert [r.size for r in res] == [r.size for r in eager]
+        _check(pairs, res)
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum()).item()
+    plan.close()
+
+
+def test_node_limit_gives_valid_partial_result(gpu):
+    from paper_1908_06418_amd import Plan, _abi
+    pairs = mi.pairs_c2(ns=(35,), ps=(0.3,), seeds=range(2))
+    plan = Plan(pairs, node_limit=20000, time_limit_s=60).upload()
+    _say("node limit")
+    plan.run()
+    res = plan.results()
+    assert plan.status == _abi.MCS_LIMIT
+    assert not all(r.optimal for r in res)
+    _check(pairs, res)
+    st = plan.stats()
+    assert st.stopped == 1
+    plan.close()
+
+
+def test_time_limit_gives_valid_partial_result(gpu):
+    from paper_1908_06418_amd import Plan, _abi
+    pairs = mi.pairs_c2(ns=(40,), ps=(0.3,), seeds=range(1))
+    plan = Plan(pairs, time_limit_s=0.2).upload()
+    _say("time limit")
+    plan.run()
+    res = plan.results()
+    assert plan.status == _abi.MCS_LIMIT
+    assert not res[0].optimal
+    _check(pairs, res)
+    assert res[0].size >= 10
+    plan.close()
+
+
+def _expected(name):
+    path = os.path.join(GOLDEN, f"expected_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _golden_parity(name, pairs, time_limit_s, tuning=None):
+    exp = _expected(name)
+    assert exp["digest"] == mi.workload_hash(pairs), "stored values are for other inputs"
+    _say(f"golden {name}: {len(pairs)} pairs")
+    res = _solve_batch(pairs, time_limit_s=time_limit_s, tuning=tuning)
+    proven = 0
+    for i, (r, e) in enumerate(zip(res, exp["pairs"])):
+        if e["complete"]:
+            assert r.size == e["size"], (i, r.size, e["size"])
+        else:
+            assert r.size >= e["size"], (i, r.size, e["size"])
+        proven += r.optimal
+    _check(pairs, res)
+    return res, proven
+
+
+def test_c3_directed_labelled_all(gpu):
+    res, proven = _golden_parity("c3", mi.pairs_c3(), 120)
+    assert proven == len(res)
+
+
+def test_c2_n30_all(gpu):
+    res, proven = _golden_parity("c2_n30", mi.pairs_c2(ns=(30,)), 300)
+    assert proven == len(res)
+
+
+def test_c4_first_1024(gpu):
+    res, proven = _golden_parity("c4_1024", mi.pairs_c4(1024), 300)
+    exp = _expected("c4_1024")
+    assert proven >= sum(1 for e in exp["pairs"] if e["complete"])
