@@ -1,0 +1,197 @@
+"""Benchmark: McSplit search throughput on one MI355X.
+
+A step is one pass of the whole search over one batch of synthetic pairs: the
+search kernel (class split, Eq. 1 bound, prune/spawn, work queue, incumbent,
+termination) plus the result copy-back and un-permuting.  Inputs are uploaded
+to HBM once, before the timed region.  Every step's sizes are checked against
+the oracle's stored sizes for the workload; a mismatch marks the line
+"exact": false.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2_n30]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "search nodes/sec + MCS instances/sec (batched) at exact size match"
+PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: int32 lane-ops/s
+
+# Algorithmic 32-bit lane operations per class per evaluated child: remove v
+# and w, split L and R by the adjacency letters, popcount every part, min()
+# per letter and the sum of Eq. 1 ("Roofline").
+OPS_PER_CLASS = {(4, False): 14, (8, False): 24, (4, True): 34, (8, True): 60}
+
+
+def workloads():
+    import mcs_instances as mi
+    return {
+        "c2_n30": ("60 undirected unlabelled pairs G(30,p), p in {0.1,0.3,0.5}, 20 seeds each, "
+                   "one batched launch", lambda: mi.pairs_c2(ns=(30,)), "expected_c2_n30.json"),
+        "c3": ("60 directed vertex-labelled pairs n in {40,50,60}, p=0.1, ceil(0.33n) labels, "
+               "one batched launch", lambda: mi.pairs_c3(), "expected_c3.json"),
+        "c4_1024": ("first 1024 pairs of the batched workload, n ~ U{10..35}, p ~ U[0.05,0.5)",
+                    lambda: mi.pairs_c4(1024), "expected_c4_1024.json"),
+        "c1": ("one undirected unlabelled pair G(16,0.3)", lambda: mi.pair_c1(), None),
+    }
+
+
+def expected_sizes(fname):
+    if fname is None:
+        return None
+    with open(os.path.join(ROOT, "tests", "golden", fname)) as f:
+        return json.load(f)
+
+
+def cpu_baseline(pairs, exp, budget_s=20.0):
+    """The oracle, as it stands, on a bounded sample of the workload: the
+    pairs the stored oracle run proved fastest, up to about budget_s seconds
+    of single-core work, one process per pair over the host's cores."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    import oracle
+    oracle._load()
+    cores = min(16, os.cpu_count() or 1)
+    idx = list(range(len(pairs)))
+    if exp is not None:
+        idx = sorted((i for i in idx if exp["pairs"][i]["complete"]),
+                     key=lambda i: exp["pairs"][i]["seconds"])
+        acc, keep = 0.0, []
+        for i in idx:
+            if acc + exp["pairs"][i]["seconds"] > budget_s and keep:
+                break
+            acc += exp["pairs"][i]["seconds"]
+            keep.append(i)
+        idx = keep
+    sample = [pairs[i] for i in idx]
+    t0 = time.time()
+    with ProcessPoolExecutor(cores) as ex:
+        out = list(ex.map(_oracle_one, [G for G, _ in sample], [H for _, H in sample]))
+    dt = time.time() - t0
+    nodes = sum(n for n, _ in out)
+    return {"value": nodes / dt, "unit": "nodes/s", "cores": cores, "kind": "oracle",
+            "instances_per_s": len(sample) / dt,
+            "sample": f"{len(sample)} of {len(pairs)} pairs of the same workload (those the "
+                      f"oracle proves fastest, about {budget_s:.0f} s of one-core work), solved "
+                      f"to optimality by the plain recursive C oracle, one process per pair on "
+                      f"{cores} host cores, {dt:.1f} s wall"}
+
+
+def _oracle_one(G, H):
+    import oracle
+    r = oracle.mcs(G, H)
+    return r["nodes"], r["complete"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2_n30")
+    ap.add_argument("--time-limit", type=float, default=120.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="", help="JSON dict of mcs_tuning fields")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this search runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1908_06418_amd import Plan, _abi, build
+    if not os.path.exists(_abi.LIB_PATH):
+        build.build()
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+
+    desc, factory, exp_file = workloads()[args.workload]
+    pairs = factory()
+    exp = expected_sizes(exp_file)
+    tuning = json.loads(args.tuning) if args.tuning else None
+    plan = Plan(pairs, time_limit_s=args.time_limit, tuning=tuning).upload()
+
+    def step():
+        plan.run()
+        return plan.results()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    exact = True
+    nodes = 0
+    kernel_ms = 0.0
+    lane_slots = batches = children = 0
+    proven = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+        st = plan.stats()
+        nodes += st.nodes
+        kernel_ms += st.kernel_ms
+        lane_slots += st.lane_slots
+        batches += st.batches
+        children += st.children
+        proven += sum(r.optimal for r in res)
+        if exp is not None:
+            for r, e in zip(res, exp["pairs"]):
+                if (e["complete"] and r.size != e["size"]) or r.size < e["size"]:
+                    exact = False
+        if not all(r.optimal for r in res):
+            exact = False
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    K = args.steps
+    word = 4 if max(max(G["n"], H["n"]) for G, H in pairs) <= 32 else 8
+    directed = bool(pairs[0][0]["directed"])
+    ops = lane_slots * OPS_PER_CLASS[(word, directed)]
+    kern_s = kernel_ms / 1e3
+    achieved = ops / kern_s / 1e12 if kern_s > 0 else 0.0
+    peak = PEAK_INT32_OPS / 1e12
+    line = {
+        "metric": METRIC,
+        "value": nodes / elapsed,
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64" if word == 8 else "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "pairs": len(pairs),
+                   "word_bits": 8 * word, "directed": directed},
+        "instances_per_s": len(pairs) * K / elapsed,
+        "exact": exact,
+        "proven_per_step": proven / K,
+        "kernel_ms_per_step": kernel_ms / K,
+        "nodes_per_step": nodes / K,
+        "active_lane_frac": lane_slots / (64.0 * batches) if batches else 0.0,
+        "children_per_batch": children / batches if batches else 0.0,
+        "waves": st.waves,
+        "lds_per_wave": st.lds_per_wave,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
+                     "frac": achieved / peak if peak else 0.0, "traffic": None,
+                     "kernel": "mcs_search_kernel",
+                     "per_unit": f"{OPS_PER_CLASS[(word, directed)]} int32 lane-ops per class "
+                                 "per evaluated child"},
+    }
+    plan.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pairs, exp)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

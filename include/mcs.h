@@ -23,6 +23,10 @@
  *   - A negative status means no result was written except size = -1 in each
  *     result; mcs_last_error() then names the cause.
  *   - Vertex ids in results are the caller's original ids.
+ *   - libmcs.so links no HIP runtime of its own: it uses the one the process
+ *     already has (link the program with -lamdhip64, or load that runtime
+ *     with RTLD_GLOBAL before libmcs.so), so streams and device memory passed
+ *     in belong to the same runtime that launches the kernels.
  */
 #ifndef MCS_H
 #define MCS_H
@@ -50,7 +54,9 @@ typedef enum {
 /* One graph.  adj holds n rows of 64-bit words: bit j of adj[i] is set iff
  * the arc i -> j exists.  Undirected graphs must be symmetric.  No self loops
  * (diagonal bits) and no bits at or above n.  label is NULL (unlabelled) or n
- * vertex labels; G and H of a pair must agree on directed and on labelled. */
+ * vertex labels; G and H of a pair must agree on directed and on labelled.
+ * One batch may mix directed and undirected pairs, and labelled and
+ * unlabelled ones. */
 typedef struct {
     int32_t n;
     int32_t directed;
@@ -67,7 +73,11 @@ typedef struct {
                                   evaluate at once (1, 2, 4 or 8; 0: 8) */
     int32_t ring_slots;        /* capacity of the device node queue (0: auto) */
     int32_t donate_low;        /* a busy wavefront donates its shallowest open
-                                  node when fewer nodes than this wait (0: auto) */
+                                  node when fewer nodes than this wait and some
+                                  wavefront is idle (0: auto; < 0: never) */
+    int32_t donate_depth;      /* only nodes with |M| <= this are donated, as the
+                                  paper delegates only above PART_LEVEL
+                                  (0: a third of the largest min(nG, nH)) */
     int32_t check_interval;    /* child batches between queue/limit checks (0: 16) */
     int32_t no_reprune;        /* 1: do not re-test a frame's bound against the
                                   incumbent when the search returns to it */

@@ -41,6 +41,7 @@ class Tuning:
     children_per_wave: int = 0
     ring_slots: int = 0
     donate_low: int = 0
+    donate_depth: int = 0
     check_interval: int = 0
     no_reprune: int = 0
     single_wave: int = 0
@@ -48,8 +49,8 @@ class Tuning:
 
     def to_c(self) -> _abi.mcs_tuning:
         return _abi.mcs_tuning(self.waves_per_cu, self.children_per_wave, self.ring_slots,
-                               self.donate_low, self.check_interval, self.no_reprune,
-                               self.single_wave, self.use_graph)
+                               self.donate_low, self.donate_depth, self.check_interval,
+                               self.no_reprune, self.single_wave, self.use_graph)
 
 
 class _Marshal:

@@ -26,6 +26,7 @@ class mcs_graph(ctypes.Structure):
 class mcs_tuning(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("children_per_wave", ctypes.c_int32),
                 ("ring_slots", ctypes.c_int32), ("donate_low", ctypes.c_int32),
+                ("donate_depth", ctypes.c_int32),
                 ("check_interval", ctypes.c_int32), ("no_reprune", ctypes.c_int32),
                 ("single_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
@@ -77,6 +78,27 @@ SIGNATURES = [
 ]
 
 _lib = None
+_runtime = None
+
+
+def hip_runtime():
+    """Make the process's HIP runtime visible to libmcs.so, which links none of
+    its own: torch's bundled libamdhip64 when torch is importable (so device
+    memory, streams and kernels share one runtime), else the system one."""
+    global _runtime
+    if _runtime is None:
+        path = None
+        try:
+            import torch
+            cand = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+            if os.path.exists(cand):
+                path = cand
+        except ImportError:
+            pass
+        if path is None:
+            path = "libamdhip64.so.7"
+        _runtime = ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+    return _runtime
 
 
 def load():
@@ -87,6 +109,7 @@ def load():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with paper_1908_06418_amd.build.build() "
                 "(hipcc, gfx950); the search has no CPU fallback")
+        hip_runtime()
         lib = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(lib, name)

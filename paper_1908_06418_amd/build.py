@@ -33,7 +33,11 @@ def build(verbose: bool = False) -> str:
             _run(cmd, verbose)
             objs.append(obj)
         out = os.path.join(tmp, "libmcs.so")
-        _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", out] + objs, verbose)
+        # No HIP runtime is linked in: the library binds to the runtime the
+        # host process already has (torch's under Python, -lamdhip64 in C),
+        # so one process never holds two HIP runtimes.
+        _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-no-hip-rt", "-o", out] + objs,
+             verbose)
         os.replace(out, LIB + ".tmp")
     os.replace(LIB + ".tmp", LIB)
     return LIB

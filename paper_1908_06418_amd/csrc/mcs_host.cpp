@@ -227,7 +227,10 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         return fail(MCS_E_INVALID, "count must be positive");
     if (!G || !H)
         return fail(MCS_E_INVALID, "G or H is NULL");
-    int directed = G[0].directed;
+    // One launch runs one kernel variant: if any pair is directed, all pairs
+    // go through the four-way (arc pair) split, which on an undirected graph
+    // (in-rows equal to out-rows) gives the same classes as the two-way one.
+    int directed = 0;
     for (int i = 0; i < count; i++) {
         mcs_status s = validate(G[i], "G", i);
         if (s != MCS_OK)
@@ -239,8 +242,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
             return fail(MCS_E_INVALID, "G and H of a pair differ in directedness");
         if ((G[i].label == nullptr) != (H[i].label == nullptr))
             return fail(MCS_E_INVALID, "G and H of a pair differ in having labels");
-        if (G[i].directed != directed)
-            return fail(MCS_E_INVALID, "all pairs of one call must share directedness");
+        directed |= G[i].directed;
     }
 
     mcs_plan *p = new mcs_plan();
@@ -443,7 +445,10 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.lds_per_wave = p->lds_per_wave;
     int cm = p->tun.children_per_wave;
     sp.cmax = (cm == 1 || cm == 2 || cm == 4 || cm == 8) ? cm : 8;
-    sp.donate_low = p->tun.donate_low > 0 ? p->tun.donate_low : p->waves;
+    sp.donate_low = p->tun.donate_low > 0 ? p->tun.donate_low
+                                          : (p->tun.donate_low < 0 ? -1 : p->waves);
+    sp.donate_depth = p->tun.donate_depth > 0 ? p->tun.donate_depth
+                                              : std::max(1, p->mmax / 3);
     sp.check_interval = p->tun.check_interval > 0 ? p->tun.check_interval : 16;
     sp.reprune = p->tun.no_reprune ? 0 : 1;
     sp.single_wave = p->tun.single_wave ? 1 : 0;

@@ -14,17 +14,25 @@ struct DevInst {
     int32_t lb;        // initial incumbent size (0: none)
 };
 
-// Counters shared by every wavefront of a launch.
+// Counters shared by every wavefront of a launch.  The ones every wavefront
+// polls or updates each sit on a cache line of their own.
 struct DevGlobals {
     unsigned long long head;        // node queue: next ticket to take
+    uint8_t pad_head[120];
     unsigned long long tail;        // node queue: next ticket to fill
+    uint8_t pad_tail[120];
+    int open_total;                 // work units alive: instances not yet claimed,
+                                    // queued nodes and busy wavefronts
+    uint8_t pad_open[124];
+    unsigned next_inst;             // next instance whose root is not yet taken
+    uint8_t pad_next[124];
+    unsigned stop;                  // 1: a limit was hit, every wavefront leaves
+    uint8_t pad_stop[124];
+    int idle;                       // wavefronts currently looking for work
+    uint8_t pad_idle[124];
     unsigned long long t0;          // earliest wavefront start (realtime ticks)
     unsigned long long node_total;  // nodes flushed so far (for the node limit)
-    int open_total;                 // live work units: queued nodes + busy wavefronts
-    unsigned next_inst;             // next instance whose root is not yet taken
-    unsigned stop;                  // 1: a limit was hit, every wavefront leaves
     unsigned error;                 // nonzero: a capacity check fired
-    int idle;                       // wavefronts currently looking for work
     int pad0;
     unsigned long long batches;     // statistics
     unsigned long long children;
@@ -38,7 +46,7 @@ struct SearchParams {
     const void *adj;      // [count][R][NB] words, R = 2 (G, H) or 4 (G out, H out, G in, H in)
     const void *rootcls;  // [sum K0] (L, R) word pairs
     int *inc;             // [count] incumbent size
-    int *open;            // [count] live work units of the instance
+    int *open;            // [count] live work units of the instance (1 while unclaimed)
     unsigned long long *nodes;    // [count]
     unsigned long long *t_best;   // [count] (size << 48) | (realtime & 2^48-1)
     unsigned long long *t_proof;  // [count] realtime ticks when open reached 0
@@ -52,7 +60,8 @@ struct SearchParams {
     int cap_classes;      // LDS class capacity of one wavefront's stack
     int lds_per_wave;     // bytes
     int cmax;             // children per batch (1, 2, 4, 8)
-    int donate_low;
+    int donate_low;       // < 0: never donate
+    int donate_depth;     // only frames with |M| <= this are donated
     int check_interval;
     int reprune;
     int single_wave;

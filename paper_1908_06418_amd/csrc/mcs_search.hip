@@ -138,11 +138,13 @@ DEV void wave_sync() {
 
 // ---- device-scope atomics ----------------------------------------------------
 
-DEV int a_add(int *p, int v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+// Counters are relaxed: the only data handed between wavefronts is a queued
+// node record, ordered by the release/acquire pair on its slot's sequence.
+DEV int a_add_rlx(int *p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 DEV unsigned a_addu(unsigned *p, unsigned v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 DEV unsigned long long a_add64(unsigned long long *p, unsigned long long v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -156,8 +158,6 @@ DEV void a_max64(unsigned long long *p, unsigned long long v) {
 DEV void a_min64(unsigned long long *p, unsigned long long v) {
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <typename T>
-DEV T ld_acq(T *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT); }
 template <typename T>
 DEV T ld_rlx(T *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 template <typename T>
@@ -553,7 +553,7 @@ struct Searcher {
         if (lane == 0) {
             for (int tries = 0; tries < 16; ++tries) {
                 unsigned long long tl = ld_rlx(&P.g->tail);
-                unsigned long long s = ld_acq(&P.seq[tl & mask]);
+                unsigned long long s = ld_rlx(&P.seq[tl & mask]);
                 if (s == tl) {
                     if (cas64(&P.g->tail, tl, tl + 1)) {
                         ok = 1;
@@ -565,6 +565,8 @@ struct Searcher {
                 }
             }
         }
+        // the slot's last reader has released it; order our writes after that
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         ok = rl(ok, 0);
         ticket = rl_ull(tk, 0);
         return ok != 0;
@@ -578,6 +580,8 @@ struct Searcher {
         for (int i = 0; i < t; ++i) {
             W r = sc((W)shdr[i].rrem);
             int f = sc((int)shdr[i].flags);
+            if (sc((int)shdr[i].d) > P.donate_depth)
+                return;  // deeper frames hold too little work to hand out
             if (r != 0 || (f & kFlagUnmatched)) {
                 b = i;
                 grr = r;
@@ -587,6 +591,8 @@ struct Searcher {
         }
         W keep_r = 0;
         if (b < 0) {
+            if (d > P.donate_depth)
+                return;
             int n = popc(rrem);
             if (n >= 2) {
                 W r = rrem, kept = 0;
@@ -648,8 +654,8 @@ struct Searcher {
         if (lane < fK)
             rcls[lane] = scls[fbase + lane];
         if (lane == 0) {
-            a_add(&P.open[inst], 1);
-            a_add(&P.g->open_total, 1);
+            a_add_rlx(&P.open[inst], 1);
+            a_add_rlx(&P.g->open_total, 1);
             st_rel(&P.seq[ticket & mask], ticket + 1);
         }
         if (b == t) {
@@ -670,7 +676,7 @@ struct Searcher {
         if (lane == 0) {
             for (int tries = 0; tries < 16; ++tries) {
                 unsigned long long h = ld_rlx(&P.g->head);
-                unsigned long long s = ld_acq(&P.seq[h & mask]);
+                unsigned long long s = ld_rlx(&P.seq[h & mask]);
                 if (s == h + 1) {
                     if (cas64(&P.g->head, h, h + 1)) {
                         ok = 1;
@@ -685,6 +691,8 @@ struct Searcher {
         ok = rl(ok, 0);
         if (!ok)
             return false;
+        // pairs with the producer's release store of the slot's sequence number
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         hd = rl_ull(hd, 0);
         const uint8_t *slot = P.slots + (size_t)(hd & mask) * (size_t)P.slot_bytes;
         RecHdr<W> rh = *(const RecHdr<W> *)slot;
@@ -729,19 +737,16 @@ struct Searcher {
         return true;
     }
 
+    // Take the next unclaimed instance.  Its work unit was counted in
+    // open_total and open[i] by the reset, so nothing is added here.
     __device__ bool claim_instance() {
         int i = -1;
         if (lane == 0) {
-            unsigned nx = ld_acq(&P.g->next_inst);
+            unsigned nx = ld_rlx(&P.g->next_inst);
             if (nx < (unsigned)P.count) {
-                a_add(&P.g->open_total, 1);
                 unsigned x = a_addu(&P.g->next_inst, 1u);
-                if (x < (unsigned)P.count) {
-                    a_add(&P.open[x], 1);
+                if (x < (unsigned)P.count)
                     i = (int)x;
-                } else {
-                    a_add(&P.g->open_total, -1);
-                }
             }
         }
         i = rl(i, 0);
@@ -791,7 +796,7 @@ struct Searcher {
         }
         if (P.node_limit > 0)
             flush_nodes();
-        if (!P.single_wave) {
+        if (!P.single_wave && P.donate_low >= 0) {
             // donate while fewer nodes wait than wavefronts are hungry
             long long waiting = (long long)(rl_ull(tl, 0) - rl_ull(hd, 0));
             long long want = rl(hungry, 0);
@@ -821,11 +826,11 @@ struct Searcher {
     __device__ void finish_unit() {
         flush_nodes();
         if (!stop && lane == 0) {
-            int r = a_add(&P.open[inst], -1);
+            int r = a_add_rlx(&P.open[inst], -1);
             if (r == 1)
                 __hip_atomic_store(&P.t_proof[inst], now_ticks(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            a_add(&P.g->open_total, -1);
+            a_add_rlx(&P.g->open_total, -1);
         }
     }
 
@@ -843,7 +848,7 @@ struct Searcher {
                 got = claim_instance();
             if (got) {
                 if (idle && lane == 0)
-                    a_add(&P.g->idle, -1);
+                    a_add_rlx(&P.g->idle, -1);
                 idle = false;
                 backoff = 0;
                 run();
@@ -853,21 +858,17 @@ struct Searcher {
                 continue;
             }
             if (!idle && lane == 0)
-                a_add(&P.g->idle, 1);
+                a_add_rlx(&P.g->idle, 1);
             idle = true;
-            unsigned nx = 0, st = 0;
+            unsigned st = 0;
             int ot = 0;
             if (lane == 0) {
-                nx = ld_acq(&P.g->next_inst);
-                ot = ld_acq(&P.g->open_total);
+                ot = ld_rlx(&P.g->open_total);
                 st = ld_rlx(&P.g->stop);
             }
-            nx = rl(nx, 0);
             ot = rl(ot, 0);
             st = rl(st, 0);
-            if (st)
-                break;
-            if (nx >= (unsigned)P.count && ot == 0)
+            if (st || ot == 0)
                 break;
             if (now_ticks() - t_start > P.limit_ticks) {
                 if (lane == 0)
@@ -880,7 +881,7 @@ struct Searcher {
                 __builtin_amdgcn_s_sleep(8);
         }
         if (idle && lane == 0)
-            a_add(&P.g->idle, -1);
+            a_add_rlx(&P.g->idle, -1);
         if (lane == 0) {
             a_add64(&P.g->batches, n_batches);
             a_add64(&P.g->children, n_children);
@@ -908,7 +909,7 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
     const int stride = gridDim.x * blockDim.x;
     for (int i = tid; i < R.count; i += stride) {
         R.inc[i] = R.inst[i].lb;
-        R.open[i] = 0;
+        R.open[i] = 1;  // the unclaimed root
         R.nodes[i] = 0;
         R.t_best[i] = 0;
         R.t_proof[i] = 0;
@@ -918,6 +919,7 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
     if (tid == 0) {
         DevGlobals z = {};
         z.t0 = ~0ull;
+        z.open_total = R.count;
         *R.g = z;
     }
 }

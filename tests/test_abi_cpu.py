@@ -132,3 +132,13 @@ def test_product_package_never_imports_oracle():
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in src and "from oracle" not in src, fn
                 assert "mcsplit_oracle" not in src and "liboracle" not in src, fn
+
+
+def test_mixed_batch_accepted(mcs_lib):
+    """Directed and undirected, labelled and unlabelled pairs share one call."""
+    pairs = [(mi.er_graph(12, 0.3, 1), mi.er_graph(12, 0.3, 2)),
+             (mi.er_graph(12, 0.3, 3, directed=True), mi.er_graph(12, 0.3, 4, directed=True)),
+             (mi.er_graph(12, 0.3, 5, labelled=True), mi.er_graph(12, 0.3, 6, labelled=True))]
+    p = _create(pairs)
+    assert p.workspace_bytes > 0
+    p.close()

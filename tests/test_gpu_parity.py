@@ -272,3 +272,20 @@ def test_c4_first_1024(gpu):
     res, proven = _golden_parity("c4_1024", mi.pairs_c4(1024), 300)
     exp = _expected("c4_1024")
     assert proven >= sum(1 for e in exp["pairs"] if e["complete"])
+
+
+def test_side_stream_single_runtime(gpu):
+    """The library runs on a torch side stream: one HIP runtime serves torch's
+    memory, torch's stream and the search kernels."""
+    import torch
+    from paper_1908_06418_amd import Plan
+    pairs = [pq for pq in mi.pairs_c4(64, start=2000) if pq[0]["n"] <= 22][:24]
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = Plan(pairs, time_limit_s=60).upload(stream=s)
+        _say("side stream run")
+        plan.run()
+        res = plan.results()
+    _check(pairs, res, want)
+    plan.close()
