@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--time-limit", type=float, default=120.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="", help="JSON dict of mcs_tuning fields")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (outside the timed region), "
+                         "so HBM byte counters can be scaled against a known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this search runs on one GPU; --gpus {args.gpus} is not supported "
@@ -113,6 +116,13 @@ def main():
         build.build()
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+
+    if args.calibrate_copy:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     desc, factory, exp_file = workloads()[args.workload]
     pairs = factory()

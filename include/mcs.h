@@ -67,8 +67,9 @@ typedef struct {
 /* Launch and scheduling knobs of the search kernel; zero fields take the
  * defaults the library derives from the instance sizes. */
 typedef struct {
-    int32_t waves_per_cu;      /* resident search wavefronts per CU (0: as many
-                                  as the LDS stack size allows) */
+    int32_t waves_per_cu;      /* resident search wavefronts per CU (0: about
+                                  16 per instance, between 1 and 4 per CU;
+                                  capped by what LDS and registers allow) */
     int32_t children_per_wave; /* how many sibling children one wavefront may
                                   evaluate at once (1, 2, 4 or 8; 0: 8) */
     int32_t ring_slots;        /* capacity of the device node queue (0: auto) */
@@ -78,7 +79,7 @@ typedef struct {
     int32_t donate_depth;      /* only nodes with |M| <= this are donated, as the
                                   paper delegates only above PART_LEVEL
                                   (0: a third of the largest min(nG, nH)) */
-    int32_t check_interval;    /* child batches between queue/limit checks (0: 16) */
+    int32_t check_interval;    /* search steps between queue/limit checks (0: 64) */
     int32_t no_reprune;        /* 1: do not re-test a frame's bound against the
                                   incumbent when the search returns to it */
     int32_t single_wave;       /* 1: whole search on one wavefront, in the

@@ -1,0 +1,121 @@
+"""Autotuner for the search kernel's launch and scheduling knobs.
+
+The knobs (mcs_tuning in include/mcs.h) change only speed, never answers:
+resident wavefronts per CU, how many sibling children a wavefront evaluates at
+once, which nodes may be donated to the shared queue (the paper's PART_LEVEL
+idea), how often a busy wavefront looks at the queue, and the queue capacity.
+The tuner times candidate settings on a sample of the workload through the C
+ABI, rejects any setting whose sizes differ from the others (they must agree:
+the search is exact), and caches the fastest per workload class in a JSON
+file ($MCS_TUNING_FILE, else ~/.cache/mcs_tuning.json).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+DEFAULT_CANDIDATES = [
+    {"waves_per_cu": w, "children_per_wave": c, "donate_depth": dd, "check_interval": ci}
+    for w in (4, 8, 16)
+    for c in (4, 8)
+    for dd in (0, 6)
+    for ci in (16, 64)
+]
+
+
+def cache_path() -> str:
+    return os.environ.get("MCS_TUNING_FILE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "mcs_tuning.json"))
+
+
+def workload_key(pairs) -> str:
+    """Workload class: row word size, directed, largest n (to 8), mean
+    density (to 0.1), labelled, batch size (to a power of two)."""
+    nmax = max(max(G["n"], H["n"]) for G, H in pairs)
+    directed = any(G["directed"] for G, _ in pairs)
+    labelled = any(G.get("label") is not None for G, _ in pairs)
+    dens = []
+    for G, H in pairs:
+        for g in (G, H):
+            n = g["n"]
+            if n > 1:
+                e = sum(bin(r).count("1") for r in g["rows"])
+                dens.append(e / (n * (n - 1)))
+    p = sum(dens) / len(dens) if dens else 0.0
+    bits = 32 if nmax <= 32 else 64
+    nb = 8 * math.ceil(max(nmax, 1) / 8)
+    batch = 1 << max(0, math.ceil(math.log2(len(pairs))))
+    return (f"w{bits}-{'d' if directed else 'u'}{'l' if labelled else ''}-n{nb}"
+            f"-p{round(p, 1):.1f}-b{batch}")
+
+
+def load_cache(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(data: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def pick(measurements: list) -> dict:
+    """Fastest candidate among those that proved every pair with the common
+    sizes.  measurements: dicts {tuning, kernel_ms, sizes, proven}."""
+    ok = [m for m in measurements if m["proven"]]
+    if not ok:
+        raise RuntimeError("no candidate proved every sample pair within the time limit")
+    ref = ok[0]["sizes"]
+    for m in ok:
+        if m["sizes"] != ref:
+            raise RuntimeError(f"tunings disagree on sizes: {m['tuning']}")
+    return min(ok, key=lambda m: m["kernel_ms"])
+
+
+def tune(pairs, candidates=None, time_limit_s: float = 30.0, reps: int = 1, log=None) -> dict:
+    """Time every candidate on pairs (GPU); returns the winning measurement
+    with the whole table under 'table'."""
+    from . import Plan
+    table = []
+    for cand in candidates or DEFAULT_CANDIDATES:
+        plan = Plan(pairs, time_limit_s=time_limit_s, tuning=cand).upload()
+        best_ms = None
+        for _ in range(reps):
+            plan.run()
+            res = plan.results()
+            st = plan.stats()
+            best_ms = st.kernel_ms if best_ms is None else min(best_ms, st.kernel_ms)
+        m = {"tuning": cand, "kernel_ms": best_ms, "sizes": [r.size for r in res],
+             "proven": all(r.optimal for r in res), "nodes": st.nodes}
+        plan.close()
+        table.append(m)
+        if log:
+            log(m)
+    best = dict(pick(table))
+    best["table"] = table
+    return best
+
+
+def tuned(pairs, path: str | None = None) -> dict | None:
+    """Cached tuning for this workload class, or None (library defaults)."""
+    entry = load_cache(path).get(workload_key(pairs))
+    return dict(entry["tuning"]) if entry else None
+
+
+def tune_and_store(pairs, sample=None, path: str | None = None, **kw) -> dict:
+    best = tune(sample or pairs, **kw)
+    data = load_cache(path)
+    data[workload_key(pairs)] = {"tuning": best["tuning"], "kernel_ms": best["kernel_ms"],
+                                 "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    save_cache(data, path)
+    return best

@@ -364,11 +364,19 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         (void)hipGetLastError();
         per_cu = 1;
     }
+    // Default: about 16 wavefronts per instance, between one per CU and one
+    // per SIMD.  The search is bound by each CU's shared scalar unit and LDS,
+    // so more than one wavefront per SIMD adds no throughput; and wavefronts
+    // beyond what the instances can keep busy only add queue traffic.
     p->blocks = per_cu * cus;
-    if (p->tun.single_wave)
+    if (p->tun.single_wave) {
         p->blocks = 1;
-    else if (p->tun.waves_per_cu > 0)
-        p->blocks = std::max(1, std::min(p->blocks, (p->tun.waves_per_cu * cus + wpb - 1) / wpb));
+    } else {
+        int want = p->tun.waves_per_cu > 0
+                       ? p->tun.waves_per_cu * cus
+                       : std::max(cus, std::min(4 * cus, 16 * count));
+        p->blocks = std::max(1, std::min(p->blocks, (want + wpb - 1) / wpb));
+    }
     p->waves = p->blocks * wpb;
 
     p->ring_slots = p->tun.ring_slots > 0 ? next_pow2(p->tun.ring_slots)
@@ -449,7 +457,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
                                           : (p->tun.donate_low < 0 ? -1 : p->waves);
     sp.donate_depth = p->tun.donate_depth > 0 ? p->tun.donate_depth
                                               : std::max(1, p->mmax / 3);
-    sp.check_interval = p->tun.check_interval > 0 ? p->tun.check_interval : 16;
+    sp.check_interval = p->tun.check_interval > 0 ? p->tun.check_interval : 64;
     sp.reprune = p->tun.no_reprune ? 0 : 1;
     sp.single_wave = p->tun.single_wave ? 1 : 0;
     double ticks = p->time_limit_s * p->tick_hz;

@@ -21,13 +21,14 @@ struct DevGlobals {
     uint8_t pad_head[120];
     unsigned long long tail;        // node queue: next ticket to fill
     uint8_t pad_tail[120];
+    // open_total and stop share one 8-byte word, so an idle wavefront reads
+    // both with one load
     int open_total;                 // work units alive: instances not yet claimed,
                                     // queued nodes and busy wavefronts
-    uint8_t pad_open[124];
+    unsigned stop;                  // 1: a limit was hit, every wavefront leaves
+    uint8_t pad_state[120];
     unsigned next_inst;             // next instance whose root is not yet taken
     uint8_t pad_next[124];
-    unsigned stop;                  // 1: a limit was hit, every wavefront leaves
-    uint8_t pad_stop[124];
     int idle;                       // wavefronts currently looking for work
     uint8_t pad_idle[124];
     unsigned long long t0;          // earliest wavefront start (realtime ticks)

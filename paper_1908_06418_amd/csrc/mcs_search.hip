@@ -192,6 +192,8 @@ struct Searcher {
     W cL, cR;
     int inc;
     bool stop;
+    bool roots_left;  // false once every instance root has been claimed
+    int d0;           // depth of the unit's first frame (the shallowest)
     int since_check;
     unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops;
 
@@ -205,6 +207,8 @@ struct Searcher {
         inst = -1;
         map_off = 0;
         stop = false;
+        roots_left = true;
+        d0 = 0;
         since_check = 0;
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = 0;
         inc = 0;
@@ -310,6 +314,7 @@ struct Searcher {
         t = 0;
         base = 0;
         d = 0;
+        d0 = 0;
         load_regs();
         int contrib = 0;
         if (lane < K) {
@@ -728,6 +733,7 @@ struct Searcher {
         wave_sync();
         t = 0;
         base = 0;
+        d0 = d;
         load_regs();
         if (bound <= inc) {
             rrem = 0;
@@ -740,6 +746,8 @@ struct Searcher {
     // Take the next unclaimed instance.  Its work unit was counted in
     // open_total and open[i] by the reset, so nothing is added here.
     __device__ bool claim_instance() {
+        if (!roots_left)
+            return false;
         int i = -1;
         if (lane == 0) {
             unsigned nx = ld_rlx(&P.g->next_inst);
@@ -750,8 +758,10 @@ struct Searcher {
             }
         }
         i = rl(i, 0);
-        if (i < 0)
+        if (i < 0) {
+            roots_left = false;
             return false;
+        }
         start_root(i);
         return true;
     }
@@ -771,20 +781,23 @@ struct Searcher {
     // Periodic: refresh the incumbent, honour limits, feed the queue.
     __device__ void check() {
         since_check = 0;
-        unsigned long long hd = 0, tl = 0;
+        // the queue is read only when some frame of this unit may be donated
+        const bool may_donate = !P.single_wave && P.donate_low >= 0 && d0 <= P.donate_depth;
+        unsigned long long hd = 0, tl = 0, state = 0;
         int gi = 0, hungry = 0;
-        unsigned st = 0;
         if (lane == 0) {
-            tl = ld_rlx(&P.g->tail);
-            hd = ld_rlx(&P.g->head);
             gi = ld_rlx(&P.inc[inst]);
-            st = ld_rlx(&P.g->stop);
-            hungry = ld_rlx(&P.g->idle);
+            state = ld_rlx((unsigned long long *)&P.g->open_total);
+            if (may_donate) {
+                tl = ld_rlx(&P.g->tail);
+                hd = ld_rlx(&P.g->head);
+                hungry = ld_rlx(&P.g->idle);
+            }
         }
         gi = rl(gi, 0);
         if (gi > inc)
             inc = gi;
-        if (rl((int)st, 0)) {
+        if (rl((uint32_t)(rl_ull(state, 0) >> 32), 0)) {
             stop = true;
             return;
         }
@@ -796,7 +809,7 @@ struct Searcher {
         }
         if (P.node_limit > 0)
             flush_nodes();
-        if (!P.single_wave && P.donate_low >= 0) {
+        if (may_donate) {
             // donate while fewer nodes wait than wavefronts are hungry
             long long waiting = (long long)(rl_ull(tl, 0) - rl_ull(hd, 0));
             long long want = rl(hungry, 0);
@@ -860,14 +873,12 @@ struct Searcher {
             if (!idle && lane == 0)
                 a_add_rlx(&P.g->idle, 1);
             idle = true;
-            unsigned st = 0;
-            int ot = 0;
-            if (lane == 0) {
-                ot = ld_rlx(&P.g->open_total);
-                st = ld_rlx(&P.g->stop);
-            }
-            ot = rl(ot, 0);
-            st = rl(st, 0);
+            unsigned long long state = 0;
+            if (lane == 0)
+                state = ld_rlx((unsigned long long *)&P.g->open_total);
+            state = rl_ull(state, 0);
+            const int ot = (int)(uint32_t)state;
+            const unsigned st = (unsigned)(state >> 32);
             if (st || ot == 0)
                 break;
             if (now_ticks() - t_start > P.limit_ticks) {
@@ -875,10 +886,10 @@ struct Searcher {
                     __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
-            // back off: 2, 4, ... 64 sleeps of 64 x 8 cycles
-            backoff = backoff < 64 ? (backoff ? 2 * backoff : 2) : 64;
+            // back off: 1, 2, 4, ... 32 sleeps of about 8k cycles (3.4 us)
+            backoff = backoff ? (backoff < 32 ? 2 * backoff : 32) : 1;
             for (int i = 0; i < backoff; ++i)
-                __builtin_amdgcn_s_sleep(8);
+                __builtin_amdgcn_s_sleep(127);
         }
         if (idle && lane == 0)
             a_add_rlx(&P.g->idle, -1);
