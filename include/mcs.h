@@ -92,6 +92,13 @@ typedef struct {
     int64_t node_limit;        /* stop after about this many nodes (0: none) */
     double time_limit_s;       /* stop after this much kernel time (<= 0: 600 s) */
     const mcs_tuning *tuning;  /* NULL: all defaults */
+    const uint16_t *policy;    /* device pointer to the learned branching policy's
+                                  half-precision parameters (mcs_policy_pack_half),
+                                  or NULL: branch on the smallest vertex index
+                                  (descending degree) and try partners in index
+                                  order */
+    int32_t policy_depth;      /* the policy orders choices at nodes with
+                                  |M| <= policy_depth (ignored if policy is NULL) */
 } mcs_opts;
 
 /* Per-instance result.  map_g/map_h are caller-owned arrays of capacity
@@ -172,6 +179,45 @@ mcs_status mcs_solve_batch(int32_t count, const mcs_graph *G, const mcs_graph *H
 /* One pair: mcs_solve_batch with count = 1. */
 mcs_status mcs_solve(const mcs_graph *G, const mcs_graph *H, const mcs_opts *opts,
                      void *workspace, size_t bytes, void *stream, mcs_result *result);
+
+/* ---- learned branching policy -------------------------------------------
+ * A 16 -> 64 -> 64 -> 1 ReLU network scores a candidate vertex from 16
+ * features of the search node (degrees, class sizes, depth, neighbours per
+ * class-size bucket).  At nodes with |M| <= policy_depth the search branches
+ * on the best-scored vertex of the selected class and tries its partners best
+ * first.  Order only: every child is still explored or bounded by Eq. 1, so
+ * results are the same as without the policy (the paper has no learned part;
+ * its Solve leaves both choices to "some heuristic", Sec. II.B).
+ *
+ * Parameters: float32, packed W1[64][16], b1[64], W2[64][64], b2[64], w3[64],
+ * b3 (mcs_policy_param_count() values).  Rows: 16 half-precision features.
+ * Every pointer below is device memory owned by the caller; calls are
+ * asynchronous on stream.  Multiplies use the half-rounded weights with
+ * float32 accumulation, as the search does. */
+
+/* Number of float parameters (5313). */
+int32_t mcs_policy_param_count(void);
+
+/* Device bytes of workspace mcs_policy_grad needs for rows rows. */
+size_t mcs_policy_workspace_size(int32_t rows);
+
+/* logits[r] = network(x[r]) for r < rows.  Errors: MCS_E_INVALID. */
+mcs_status mcs_policy_forward(const uint16_t *x, int32_t rows, const float *params,
+                              float *logits, void *stream);
+
+/* grads = gradient of the mean binary cross-entropy of sigmoid(logit) against
+ * labels y (0/1 floats) over rows rows; *loss (device, may be NULL) = the
+ * mean loss.  Deterministic (fixed reduction order).  Errors: MCS_E_INVALID,
+ * MCS_E_WORKSPACE. */
+mcs_status mcs_policy_grad(const uint16_t *x, const float *y, int32_t rows, const float *params,
+                           float *grads, float *loss, void *workspace, size_t bytes,
+                           void *stream);
+
+/* params -= lr * grads. */
+mcs_status mcs_policy_sgd(float *params, const float *grads, float lr, void *stream);
+
+/* half_params = params rounded to half precision (the form mcs_opts.policy takes). */
+mcs_status mcs_policy_pack_half(const float *params, uint16_t *half_params, void *stream);
 
 /* Static description of a status code. */
 const char *mcs_status_string(mcs_status s);

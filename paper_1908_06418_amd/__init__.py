@@ -80,13 +80,20 @@ class _Marshal:
                               rows.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), lab)
 
 
-def _opts(node_limit, time_limit_s, tuning):
+def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0):
+    """policy: a torch half tensor of packed parameters on the device (or an
+    object with .half_params, see policy.Policy)."""
     t = None
     tc = None
     if tuning is not None:
         tc = tuning.to_c() if isinstance(tuning, Tuning) else Tuning(**tuning).to_c()
         t = ctypes.pointer(tc)
-    o = _abi.mcs_opts(int(node_limit or 0), float(time_limit_s or 0.0), t)
+    ptr = None
+    if policy is not None:
+        hp = getattr(policy, "half_params", policy)
+        ptr = ctypes.c_void_p(hp.data_ptr())
+    o = _abi.mcs_opts(int(node_limit or 0), float(time_limit_s or 0.0), t, ptr,
+                      int(policy_depth))
     return o, tc
 
 
@@ -128,11 +135,13 @@ class Plan:
     torch-allocated workspace (mcs_plan_upload), then run any number of times
     (mcs_plan_run) -- inputs stay resident in HBM between runs."""
 
-    def __init__(self, pairs, node_limit=0, time_limit_s=0.0, tuning=None):
+    def __init__(self, pairs, node_limit=0, time_limit_s=0.0, tuning=None, policy=None,
+                 policy_depth=2):
         self.lib = _abi.load()
         self.pairs = list(pairs)
         self._m = _Marshal(self.pairs)
-        self._o, self._t = _opts(node_limit, time_limit_s, tuning)
+        self._policy = policy  # keeps the device parameters alive
+        self._o, self._t = _opts(node_limit, time_limit_s, tuning, policy, policy_depth)
         h = ctypes.c_void_p()
         st = self.lib.mcs_plan_create(len(self.pairs), self._m.G, self._m.H,
                                       ctypes.byref(self._o), ctypes.byref(h))
@@ -210,9 +219,10 @@ class Plan:
             pass
 
 
-def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=False):
+def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=False,
+                policy=None, policy_depth=2):
     """MCS of every pair in one launch.  Returns a list of Result (and Stats)."""
-    p = Plan(pairs, node_limit, time_limit_s, tuning).upload()
+    p = Plan(pairs, node_limit, time_limit_s, tuning, policy, policy_depth).upload()
     p.run()
     res = p.results()
     st = p.stats() if with_stats else None

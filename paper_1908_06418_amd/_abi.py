@@ -33,7 +33,8 @@ class mcs_tuning(ctypes.Structure):
 
 class mcs_opts(ctypes.Structure):
     _fields_ = [("node_limit", ctypes.c_int64), ("time_limit_s", ctypes.c_double),
-                ("tuning", ctypes.POINTER(mcs_tuning))]
+                ("tuning", ctypes.POINTER(mcs_tuning)),
+                ("policy", ctypes.c_void_p), ("policy_depth", ctypes.c_int32)]
 
 
 class mcs_result(ctypes.Structure):
@@ -73,6 +74,13 @@ SIGNATURES = [
     ("mcs_solve", ctypes.c_int, [ctypes.POINTER(mcs_graph), ctypes.POINTER(mcs_graph),
                                  ctypes.POINTER(mcs_opts), _P, ctypes.c_size_t, _P,
                                  ctypes.POINTER(mcs_result)]),
+    ("mcs_policy_param_count", ctypes.c_int32, []),
+    ("mcs_policy_workspace_size", ctypes.c_size_t, [ctypes.c_int32]),
+    ("mcs_policy_forward", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    ("mcs_policy_grad", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P,
+                                       ctypes.c_size_t, _P]),
+    ("mcs_policy_sgd", ctypes.c_int, [_P, _P, ctypes.c_float, _P]),
+    ("mcs_policy_pack_half", ctypes.c_int, [_P, _P, _P]),
     ("mcs_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("mcs_last_error", ctypes.c_char_p, []),
 ]

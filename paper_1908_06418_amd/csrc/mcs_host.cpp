@@ -12,7 +12,7 @@
 #include "mcs.h"
 #include "mcs_layout.h"
 
-extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed);
+extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed, int policy);
 extern "C" void *mcs_internal_reset_kernel(void);
 
 namespace {
@@ -130,6 +130,8 @@ struct mcs_plan {
     mcs_tuning tun{};
     int64_t node_limit = 0;
     double time_limit_s = 600.0;
+    const uint16_t *policy = nullptr;
+    int policy_depth = 0, policy_levels = 0;
 
     std::vector<mcs::DevInst> inst;
     std::vector<uint8_t> adj;      // packed rows, word_bytes each
@@ -251,6 +253,15 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     if (opts) {
         if (opts->tuning)
             p->tun = *opts->tuning;
+        if (opts->policy) {
+            if (opts->policy_depth < 0 || opts->policy_depth > 8) {
+                delete p;
+                return fail(MCS_E_INVALID, "policy_depth must be in 0..8");
+            }
+            p->policy = opts->policy;
+            p->policy_depth = opts->policy_depth;
+            p->policy_levels = opts->policy_depth + 1;
+        }
         p->node_limit = opts->node_limit > 0 ? opts->node_limit : 0;
         if (opts->time_limit_s > 0)
             p->time_limit_s = opts->time_limit_s;
@@ -343,7 +354,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         clock_khz = 100000;
     (void)hipGetLastError();
     p->tick_hz = (double)clock_khz * 1000.0;
-    p->lds_per_wave = mcs::lds_layout(p->word_bytes, directed, p->cap_classes).total;
+    p->lds_per_wave =
+        mcs::lds_layout(p->word_bytes, directed, p->cap_classes, p->policy_levels).total;
     int wpb = 4;
     while (wpb > 1 && wpb * p->lds_per_wave > max_lds_block)
         wpb >>= 1;
@@ -353,7 +365,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     }
     p->waves_per_block = wpb;
     p->lds_per_block = wpb * p->lds_per_wave;
-    const void *kern = mcs_internal_search_kernel(p->word_bytes, directed);
+    const void *kern = mcs_internal_search_kernel(p->word_bytes, directed, p->policy != nullptr);
     int per_cu = 0;
     if (p->lds_per_block > 65536)
         (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -460,6 +472,9 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.check_interval = p->tun.check_interval > 0 ? p->tun.check_interval : 64;
     sp.reprune = p->tun.no_reprune ? 0 : 1;
     sp.single_wave = p->tun.single_wave ? 1 : 0;
+    sp.policy = p->policy;
+    sp.policy_depth = p->policy_depth;
+    sp.policy_levels = p->policy_levels;
     double ticks = p->time_limit_s * p->tick_hz;
     sp.limit_ticks = ticks > 9e18 ? (unsigned long long)9e18 : (unsigned long long)ticks;
     sp.node_limit = p->node_limit;
@@ -481,7 +496,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
 
 static mcs_status launch_direct(mcs_plan *p, hipStream_t s) {
     const void *kr = mcs_internal_reset_kernel();
-    const void *ks = mcs_internal_search_kernel(p->word_bytes, p->directed);
+    const void *ks = mcs_internal_search_kernel(p->word_bytes, p->directed, p->policy != nullptr);
     int n = std::max(p->count, p->ring_slots);
     int rb = std::min(1024, (n + 255) / 256);
     void *ra[] = {&p->rp};
@@ -511,7 +526,7 @@ static mcs_status build_graph(mcs_plan *p) {
     kp.extra = nullptr;
     HIP_TRY(hipGraphAddKernelNode(&nr, p->graph, nullptr, 0, &kp));
     hipKernelNodeParams ks{};
-    ks.func = mcs_internal_search_kernel(p->word_bytes, p->directed);
+    ks.func = mcs_internal_search_kernel(p->word_bytes, p->directed, p->policy != nullptr);
     ks.gridDim = dim3(p->blocks);
     ks.blockDim = dim3(64 * p->waves_per_block);
     ks.sharedMemBytes = (unsigned)p->lds_per_block;

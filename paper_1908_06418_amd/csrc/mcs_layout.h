@@ -66,6 +66,9 @@ struct SearchParams {
     int check_interval;
     int reprune;
     int single_wave;
+    const uint16_t *policy;  // half-precision policy parameters, or null
+    int policy_depth;        // policy orders frames with |M| <= this
+    int policy_levels;       // LDS partner-order lists per wavefront (0 without policy)
     unsigned long long limit_ticks;  // time limit in realtime ticks
     long long node_limit;            // 0: none
 };
@@ -101,22 +104,25 @@ constexpr int rec_cls_off() { return kRecHeader + 2 * bits_of<W>(); }
 //   adjacency [R][NB] words
 //   mapping   [NB] byte pairs
 //   headers   [NB + 1] frame headers (24 bytes for 64-bit words, 16 for 32-bit)
+//   orders    [policy levels][64] partner order of policy-ordered frames
 struct LdsLayout {
-    int cls, adj, map, hdr, total;
+    int cls, adj, map, hdr, ord, total;
 };
 
 inline constexpr int align16(int x) { return (x + 15) & ~15; }
 
-inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_classes) {
+inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_classes,
+                                      int policy_levels = 0) {
     int nb = 8 * word_bytes;
     int rows = directed ? 4 : 2;
     int hdr_bytes = word_bytes == 8 ? 24 : 16;
-    LdsLayout L{0, 0, 0, 0, 0};
+    LdsLayout L{0, 0, 0, 0, 0, 0};
     L.cls = 0;
     L.adj = align16(cap_classes * 2 * word_bytes);
     L.map = align16(L.adj + rows * nb * word_bytes);
     L.hdr = align16(L.map + 2 * nb);
-    L.total = align16(L.hdr + (nb + 1) * hdr_bytes);
+    L.ord = align16(L.hdr + (nb + 1) * hdr_bytes);
+    L.total = align16(L.ord + policy_levels * 64);
     return L;
 }
 

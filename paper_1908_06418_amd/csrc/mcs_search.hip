@@ -36,7 +36,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <hip/hip_fp16.h>
+
 #include "mcs_layout.h"
+#include "mcs_policy.h"
 
 namespace mcs {
 
@@ -67,6 +70,7 @@ static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>)
               "record header layout");
 
 constexpr int kFlagUnmatched = 1;  // the "v unmatched" child is still to do
+constexpr int kFlagOrdered = 2;    // partners are tried in the policy's order
 
 // ---- bit helpers -----------------------------------------------------------
 
@@ -169,9 +173,11 @@ DEV bool cas64(unsigned long long *p, unsigned long long expect, unsigned long l
 
 DEV unsigned long long now_ticks() { return wall_clock64(); }
 
+DEV float hf(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+
 // ---- one wavefront's search ------------------------------------------------
 
-template <typename W, bool DIR>
+template <typename W, bool DIR, bool POL>
 struct Searcher {
     static constexpr int NB = bits_of<W>();  // vertices per row word
     static constexpr int NR = DIR ? 4 : 2;   // adjacency row sets per instance
@@ -183,7 +189,8 @@ struct Searcher {
     Hdr<W> *shdr;   // [NB + 1]
     Cls<W> *scls;   // [cap_classes]
 
-    int inst, map_off;
+    uint8_t *sord;  // [policy levels][64]: partner order of policy-ordered frames
+    int inst, map_off, nG, nH;
     // top frame, wave-uniform
     int t, base, K, d, v, sel, bound, flags, lsel, rsel;
     W rrem;
@@ -199,13 +206,16 @@ struct Searcher {
 
     __device__ Searcher(const SearchParams &p, uint8_t *lds) : P(p) {
         lane = lane_id();
-        const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes);
+        const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes,
+                                       p.policy_levels);
         scls = (Cls<W> *)(lds + L.cls);
         sadj = (W *)(lds + L.adj);
         smap = (uint16_t *)(lds + L.map);
         shdr = (Hdr<W> *)(lds + L.hdr);
+        sord = lds + L.ord;
         inst = -1;
         map_off = 0;
+        nG = nH = 1;
         stop = false;
         roots_left = true;
         d0 = 0;
@@ -252,6 +262,115 @@ struct Searcher {
         rrem = rl(cR, who);
         lsel = popc(rl(cL, who));
         rsel = popc(rrem);
+        flags &= ~kFlagOrdered;
+        if constexpr (POL) {
+            if (d <= P.policy_depth && t < P.policy_levels) {
+                // learned choice of v within the class, and of the partners' order
+                float sg = policy_score(0, rl(cL, who));
+                v = argmax_lane(sg, rl(cL, who));
+                order_partners(rrem);
+            }
+        }
+    }
+
+    // -- learned branching policy ----------------------------------------------
+    // Lane u scores vertex u of one side (u in cand) from the 16 features the
+    // policy reference defines, with the half-precision network.
+
+    // Not inlined: it runs only at shallow frames, and keeping its registers
+    // out of the main loop keeps the loop's own allocation small.
+    __device__ __attribute__((noinline)) float policy_score(int side, W cand) {
+        const int u = lane;
+        const bool is_cand = u < NB && ((cand >> (u & (NB - 1))) & 1);
+        const int off = side ? NB : 0;
+        W row = sadj[off + (u & (NB - 1))];
+        if (DIR)
+            row |= sadj[2 * NB + off + (u & (NB - 1))];
+        const int n = side ? nH : nG;
+        const float inv = 1.f / (float)(n > 0 ? n : 1);
+        const int deg = popc(row);
+        float x[kPolicyF];
+#pragma unroll
+        for (int f = 0; f < kPolicyF; ++f)
+            x[f] = 0.f;
+        int tot = 0;
+        for (int k = 0; k < K; ++k) {
+            Cls<W> c = scls[base + k];
+            int m = popc(c.L) < popc(c.R) ? popc(c.L) : popc(c.R);
+            int b = m <= 1 ? 0 : m == 2 ? 1 : m <= 4 ? 2 : m <= 8 ? 3 : m <= 16 ? 4 : 5;
+            int cnt = popc(row & (side ? c.R : c.L));
+            tot += cnt;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                if (q == b)
+                    x[6 + q] += (float)cnt;
+        }
+        uint32_t dk = is_cand ? (uint32_t)deg : 0u;
+        uint32_t dmax = ~wave_min(~dk);
+        x[0] = deg * inv;
+        x[1] = lsel * inv;
+        x[2] = rsel * inv;
+        x[3] = d * inv;
+        x[4] = K * inv;
+        x[5] = tot * inv;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            x[6 + q] *= inv;
+        x[12] = (float)side;
+        x[13] = (uint32_t)deg == dmax ? 1.f : 0.f;
+        x[15] = 1.f;
+        const uint16_t *w = P.policy;
+        float h1[kPolicyH];
+#pragma unroll
+        for (int j = 0; j < kPolicyH; ++j) {
+            float acc = hf(w[kOffB1 + j]);
+#pragma unroll
+            for (int f = 0; f < kPolicyF; ++f)
+                acc += hf(w[kOffW1 + j * kPolicyF + f]) * x[f];
+            h1[j] = acc > 0.f ? acc : 0.f;
+        }
+        float z = hf(w[kOffB3]);
+#pragma unroll 1
+        for (int j = 0; j < kPolicyH; ++j) {
+            float acc = hf(w[kOffB2 + j]);
+            const uint16_t *row = w + kOffW2 + j * kPolicyH;
+#pragma unroll
+            for (int i = 0; i < kPolicyH; ++i)
+                acc += hf(row[i]) * h1[i];
+            z += hf(w[kOffW3 + j]) * (acc > 0.f ? acc : 0.f);
+        }
+        return z;
+    }
+
+    // Highest-scoring candidate lane (lowest index among equal scores).
+    __device__ int argmax_lane(float score, W cand) {
+        const bool is_cand = lane < NB && ((cand >> (lane & (NB - 1))) & 1);
+        // order-preserving map of floats to unsigned ints
+        uint32_t b = __float_as_uint(score);
+        uint32_t key = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+        key = is_cand ? key : 0u;
+        uint32_t best = ~wave_min(~key);
+        return ctz((uint64_t)ballot(is_cand && key == best));
+    }
+
+    // sord[t][r] = the r-th best partner among cand (ties by index).
+    __device__ void order_partners(W cand) {
+        float s = policy_score(1, cand);
+        const bool is_cand = lane < NB && ((cand >> (lane & (NB - 1))) & 1);
+        uint32_t b = __float_as_uint(s);
+        uint32_t key = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+        int rank = 0;
+        W rest = cand;
+        while (rest) {
+            int c = ctz(rest);
+            rest &= rest - 1;
+            uint32_t kc = rl(key, c);
+            rank += (kc > key || (kc == key && c < lane)) ? 1 : 0;
+        }
+        if (is_cand)
+            sord[t * 64 + rank] = (uint8_t)lane;
+        wave_sync();
+        flags |= kFlagOrdered;
     }
 
     __device__ void save_top() {
@@ -294,6 +413,8 @@ struct Searcher {
                 sadj[j] = src[j];
             inst = i;
             map_off = (int)P.inst[i].map_off;
+            nG = (int)P.inst[i].nG;
+            nH = (int)P.inst[i].nH;
         }
         int g = 0;
         if (lane == 0)
@@ -361,17 +482,34 @@ struct Searcher {
             C = 64 >> logS;
         const int seg = lane >> logS;
 
-        // w of this lane's segment: the seg-th remaining child
-        int myw = 0;
+        // the next C partners w: lowest indices first, or the policy's order
+        int wl[8];
         {
             W rr = rrem;
-            for (int c = 0; c < C; ++c) {
-                int wc = ctz(rr);
-                if (seg == c)
-                    myw = wc;
-                rr &= rr - 1;
+            int pos = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                wl[c] = 0;
+                if (c < C) {
+                    int wc;
+                    if (POL && (flags & kFlagOrdered)) {
+                        while (pos < 63 && !((rr >> sord[t * 64 + pos]) & 1))
+                            ++pos;
+                        wc = sc((int)sord[t * 64 + pos]);
+                        ++pos;
+                    } else {
+                        wc = ctz(rr);
+                    }
+                    rr &= ~((W)1 << wc);
+                    wl[c] = wc;
+                }
             }
         }
+        int myw = 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (seg == c)
+                myw = wl[c];
         const bool act = seg < C;
         const W vb = (W)1 << v;
         const W Lx = cL & ~vb;
@@ -437,16 +575,14 @@ struct Searcher {
 
         // drop pruned children and the one we descend into
         int wF = 0;
-        {
-            W rr = rrem;
-            for (int c = 0; c < C; ++c) {
-                int wc = ctz(rr);
-                rr &= rr - 1;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (c < C) {
                 bool keep = ((surv >> c) & 1u) && c != first;
                 if (!keep)
-                    rrem &= ~((W)1 << wc);
+                    rrem &= ~((W)1 << wl[c]);
                 if (c == first)
-                    wF = wc;
+                    wF = wl[c];
             }
         }
         if (first < 0)
@@ -528,8 +664,8 @@ struct Searcher {
             wave_sync();
             bound = ub;
         }
-        select();
         flags = kFlagUnmatched;
+        select();
         return true;
     }
 
@@ -590,7 +726,7 @@ struct Searcher {
             if (r != 0 || (f & kFlagUnmatched)) {
                 b = i;
                 grr = r;
-                gfl = f & kFlagUnmatched;
+                gfl = f & (kFlagUnmatched | kFlagOrdered);
                 break;
             }
         }
@@ -606,11 +742,11 @@ struct Searcher {
                     r &= r - 1;
                 }
                 grr = r;
-                gfl = flags & kFlagUnmatched;
+                gfl = flags & (kFlagUnmatched | kFlagOrdered);
                 keep_r = kept;
             } else if (n == 1 && (flags & kFlagUnmatched)) {
                 grr = 0;
-                gfl = kFlagUnmatched;
+                gfl = kFlagUnmatched | (flags & kFlagOrdered);
                 keep_r = rrem;
             } else {
                 return;
@@ -665,7 +801,7 @@ struct Searcher {
         }
         if (b == t) {
             rrem = keep_r;
-            flags = 0;
+            flags &= kFlagOrdered;
         } else if (lane == 0) {
             shdr[b].rrem = 0;
             shdr[b].flags = 0;
@@ -738,6 +874,11 @@ struct Searcher {
         if (bound <= inc) {
             rrem = 0;
             flags = 0;
+        } else if (POL && (flags & kFlagOrdered)) {
+            if constexpr (POL)
+                order_partners(rrem);
+        } else {
+            flags &= ~kFlagOrdered;
         }
         n_pops += 1;
         return true;
@@ -903,13 +1044,13 @@ struct Searcher {
     }
 };
 
-template <typename W, bool DIR>
+template <typename W, bool DIR, bool POL>
 __global__ void __launch_bounds__(256) mcs_search_kernel(SearchParams P) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int wv = threadIdx.x >> 6;
     if (P.single_wave && (blockIdx.x != 0 || wv != 0))
         return;
-    Searcher<W, DIR> s(P, smem + (size_t)wv * (size_t)P.lds_per_wave);
+    Searcher<W, DIR, POL> s(P, smem + (size_t)wv * (size_t)P.lds_per_wave);
     s.main_loop();
 }
 
@@ -939,12 +1080,20 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
 
 // ---- launch entry points used by the host driver ---------------------------
 
-extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed) {
-    if (word_bytes == 4)
-        return directed ? (void *)mcs::mcs_search_kernel<uint32_t, true>
-                        : (void *)mcs::mcs_search_kernel<uint32_t, false>;
-    return directed ? (void *)mcs::mcs_search_kernel<uint64_t, true>
-                    : (void *)mcs::mcs_search_kernel<uint64_t, false>;
+extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed, int policy) {
+    using namespace mcs;
+    if (word_bytes == 4) {
+        if (policy)
+            return directed ? (void *)mcs_search_kernel<uint32_t, true, true>
+                            : (void *)mcs_search_kernel<uint32_t, false, true>;
+        return directed ? (void *)mcs_search_kernel<uint32_t, true, false>
+                        : (void *)mcs_search_kernel<uint32_t, false, false>;
+    }
+    if (policy)
+        return directed ? (void *)mcs_search_kernel<uint64_t, true, true>
+                        : (void *)mcs_search_kernel<uint64_t, false, true>;
+    return directed ? (void *)mcs_search_kernel<uint64_t, true, false>
+                    : (void *)mcs_search_kernel<uint64_t, false, false>;
 }
 
 extern "C" void *mcs_internal_reset_kernel(void) { return (void *)mcs::mcs_reset_kernel; }

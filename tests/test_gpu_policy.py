@@ -1,0 +1,173 @@
+"""GPU tests of the learned branching policy: forward and gradient kernels
+against the float64 reference (oracle/policy.py), training, exactness of the
+search with the policy on, and what the trained policy gains."""
+import json
+import os
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+
+import mcs_instances as mi
+import oracle
+from oracle import policy as ref
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _half(a):
+    return np.asarray(a, dtype=np.float16).astype(np.float64)
+
+
+def _data(seed, rows):
+    rng = np.random.default_rng(seed)
+    X = _half(rng.uniform(0, 1, (rows, ref.F)))
+    X[:, 15] = 1.0
+    y = (rng.uniform(0, 1, rows) < 0.4).astype(np.float64)
+    return X, y
+
+
+def test_forward_matches_reference(gpu):
+    import torch
+    from paper_1908_06418_amd.policy import Policy
+    P = Policy(seed=3)
+    v = _half(P.numpy())
+    X, _ = _data(1, 1000)
+    got = P.forward(torch.from_numpy(X.astype(np.float16)).cuda()).cpu().numpy()
+    want, _ = ref.forward(ref.unflat(v), X)
+    assert np.allclose(got, want, rtol=1e-4, atol=1e-4), np.abs(got - want).max()
+
+
+def test_gradients_match_reference(gpu):
+    """fp32 accumulation over half-rounded weights and inputs against float64
+    on the same rounded values: relative error well under 1e-4."""
+    import torch
+    from paper_1908_06418_amd.policy import Policy
+    P = Policy(seed=4)
+    v = _half(P.numpy())
+    for rows in (1, 63, 64, 1000):
+        X, y = _data(rows, rows)
+        loss, g = P.grad(torch.from_numpy(X.astype(np.float16)).cuda(),
+                         torch.from_numpy(y.astype(np.float32)).cuda())
+        wl, wg = ref.loss_and_grads(ref.unflat(v), X, y)
+        gv = g.cpu().numpy().astype(np.float64)
+        ref_flat = ref.flat(wg)
+        scale = np.abs(ref_flat).max()
+        assert np.abs(gv - ref_flat).max() <= 1e-4 * scale + 1e-7, rows
+        assert abs(float(loss.item()) - wl) <= 1e-4 * max(1.0, wl)
+
+
+def test_sgd_and_pack(gpu):
+    import torch
+    from paper_1908_06418_amd.policy import Policy
+    P = Policy(seed=5)
+    before = P.numpy()
+    X, y = _data(7, 256)
+    loss, g = P.grad(torch.from_numpy(X.astype(np.float16)).cuda(),
+                     torch.from_numpy(y.astype(np.float32)).cuda())
+    P.sgd(g, 0.1)
+    after = P.numpy()
+    assert np.allclose(after, before - 0.1 * g.cpu().numpy(), atol=1e-6)
+    P.pack()
+    assert np.array_equal(P.half_params.cpu().numpy(), after.astype(np.float16))
+
+
+def _rows_of(args):
+    i, G, H = args
+    from oracle import traces
+    return traces.pair_rows(G, H, np.random.default_rng(i))
+
+
+def _training_set(count, start=0):
+    pairs = mi.pairs_c5(count, start=start, train=True)
+    with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        parts = list(ex.map(_rows_of, [(start + i, G, H) for i, (G, H) in enumerate(pairs)]))
+    X = np.array([r for Xa, _ in parts for r in Xa]).reshape(-1, ref.F)
+    y = np.array([v for _, ya in parts for v in ya])
+    return X, y
+
+
+_TRAINED = {}
+
+
+def _trained_policy():
+    if "p" not in _TRAINED:
+        from paper_1908_06418_amd.policy import Policy
+        _say("policy: generating oracle traces")
+        X, y = _training_set(160)
+        _say(f"policy: {len(y)} rows, {y.mean():.2f} positive; training on the GPU")
+        P = Policy(seed=0)
+        curve = P.train(X, y, steps=400, lr=0.5)
+        _TRAINED.update(p=P, curve=curve, rows=len(y))
+    return _TRAINED["p"], _TRAINED["curve"]
+
+
+def test_training_reduces_loss(gpu):
+    _, curve = _trained_policy()
+    assert curve[-1] < curve[0] * 0.9, (curve[0], curve[-1])
+
+
+@pytest.mark.parametrize("trained", [False, True])
+def test_policy_search_is_exact(gpu, trained):
+    """Ordering changes nothing but the order: sizes equal the oracle's."""
+    from paper_1908_06418_amd import solve_batch
+    from paper_1908_06418_amd.policy import Policy
+    P = _trained_policy()[0] if trained else Policy(seed=9)
+    rng = np.random.default_rng(77)
+    pairs = [pq for pq in mi.pairs_c4(200, start=3000) if pq[0]["n"] <= 26][:60]
+    pairs += mi.pairs_c3(ns=(40,), seeds=range(6))
+    pairs += [(mi.random_small(rng, 14, 0.5, True, 2), mi.random_small(rng, 15, 0.5, True, 2))
+              for _ in range(10)]
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    for depth in (0, 2):
+        _say(f"policy search trained={trained} depth={depth}")
+        res = solve_batch(pairs, time_limit_s=60, policy=P, policy_depth=depth)
+        for (G, H), r, w in zip(pairs, res, want):
+            assert r.optimal and r.size == w
+            assert oracle.check.is_valid(G, H, r.mapping)
+    _say("policy search single wave")
+    res = solve_batch(pairs[:20], time_limit_s=60, policy=P, policy_depth=2,
+                      tuning={"single_wave": 1})
+    assert [r.size for r in res] == want[:20]
+
+
+def test_policy_gain_report(gpu):
+    """What the trained policy gains over degree ordering, on held-out pairs
+    of the training distribution (single wavefront: node counts are
+    deterministic) and on a sample of the n = 35..50 evaluation workload."""
+    from paper_1908_06418_amd import solve_batch
+    P, curve = _trained_policy()
+    held = [pq for pq in mi.pairs_c5(80, start=5000, train=True) if pq[0]["n"] <= 24][:40]
+    tun = {"single_wave": 1}
+    _say("gain: held-out, degree ordering")
+    base = solve_batch(held, time_limit_s=100, tuning=tun)
+    _say("gain: held-out, learned ordering")
+    lrn = solve_batch(held, time_limit_s=100, tuning=tun, policy=P, policy_depth=2)
+    both = [(b, l) for b, l in zip(base, lrn) if b.optimal and l.optimal]
+    assert len(both) >= 30
+    assert all(b.size == l.size for b, l in both)
+    ratios = [l.nodes / b.nodes for b, l in both]
+    total = sum(l.nodes for _, l in both) / sum(b.nodes for b, _ in both)
+    evalp = mi.pairs_c5(24)
+    _say("gain: evaluation sample, degree ordering")
+    eb = solve_batch(evalp, time_limit_s=30)
+    _say("gain: evaluation sample, learned ordering")
+    el = solve_batch(evalp, time_limit_s=30, policy=P, policy_depth=2)
+    pr = [(b, l) for b, l in zip(eb, el) if b.optimal and l.optimal]
+    assert all(b.size == l.size for b, l in pr)
+    report = {"held_out_pairs": len(both), "nodes_ratio_total": total,
+              "nodes_ratio_median": float(np.median(ratios)),
+              "eval_pairs_proven_both": len(pr), "eval_pairs": len(evalp),
+              "eval_proof_time_ratio_median": float(np.median(
+                  [l.t_proof_s / b.t_proof_s for b, l in pr])) if pr else None,
+              "eval_proven_degree": sum(b.optimal for b in eb),
+              "eval_proven_learned": sum(l.optimal for l in el),
+              "train_loss_first_last": [curve[0], curve[-1]]}
+    _say("policy gain: " + json.dumps(report))
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "policy_gain.json"), "w") as f:
+        json.dump(report, f, indent=1)
