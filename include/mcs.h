@@ -68,11 +68,12 @@ typedef struct {
  * defaults the library derives from the instance sizes. */
 typedef struct {
     int32_t waves_per_cu;      /* resident search wavefronts per CU (0: about
-                                  16 per instance, between 1 and 4 per CU;
+                                  16 per instance, between 1 and 8 per CU;
                                   capped by what LDS and registers allow) */
     int32_t children_per_wave; /* how many sibling children one wavefront may
                                   evaluate at once (1, 2, 4 or 8; 0: 8) */
-    int32_t ring_slots;        /* capacity of the device node queue (0: auto) */
+    int32_t ring_slots;        /* total capacity of the device node queue, split
+                                  over 8 per-XCD rings (0: auto) */
     int32_t donate_low;        /* a busy wavefront donates its shallowest open
                                   node when fewer nodes than this wait and some
                                   wavefront is idle (0: auto; < 0: never) */

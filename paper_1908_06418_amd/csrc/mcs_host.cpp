@@ -376,23 +376,26 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         (void)hipGetLastError();
         per_cu = 1;
     }
-    // Default: about 16 wavefronts per instance, between one per CU and one
-    // per SIMD.  The search is bound by each CU's shared scalar unit and LDS,
-    // so more than one wavefront per SIMD adds no throughput; and wavefronts
-    // beyond what the instances can keep busy only add queue traffic.
+    // Default: about 16 wavefronts per instance, between one per CU and two
+    // per SIMD.  One wavefront's search is a long dependent chain, so a
+    // second one per SIMD adds throughput when there is work for it; but
+    // wavefronts beyond what the instances can keep busy only split the work
+    // into ever smaller donations.
     p->blocks = per_cu * cus;
     if (p->tun.single_wave) {
         p->blocks = 1;
     } else {
         int want = p->tun.waves_per_cu > 0
                        ? p->tun.waves_per_cu * cus
-                       : std::max(cus, std::min(4 * cus, 16 * count));
+                       : std::max(cus, std::min(8 * cus, 16 * count));
         p->blocks = std::max(1, std::min(p->blocks, (want + wpb - 1) / wpb));
     }
     p->waves = p->blocks * wpb;
 
-    p->ring_slots = p->tun.ring_slots > 0 ? next_pow2(p->tun.ring_slots)
-                                          : next_pow2(std::max(1024, 2 * p->waves));
+    {
+        int total = p->tun.ring_slots > 0 ? p->tun.ring_slots : std::max(1024, 2 * p->waves);
+        p->ring_slots = next_pow2(std::max(2, (total + mcs::kRings - 1) / mcs::kRings));
+    }
     p->slot_bytes = mcs::slot_bytes_for(p->word_bytes, p->mmax);
 
     // workspace layout
@@ -412,8 +415,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     p->off_tproof = take(sizeof(unsigned long long) * count);
     p->off_maps = take(sizeof(uint16_t) * p->map_pairs);
     p->off_glob = take(sizeof(mcs::DevGlobals));
-    p->off_seq = take(sizeof(unsigned long long) * p->ring_slots);
-    p->off_slots = take((size_t)p->slot_bytes * p->ring_slots);
+    p->off_seq = take(sizeof(unsigned long long) * mcs::kRings * p->ring_slots);
+    p->off_slots = take((size_t)p->slot_bytes * mcs::kRings * p->ring_slots);
     p->ws_bytes = o;
     *out = p;
     return MCS_OK;
@@ -497,7 +500,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
 static mcs_status launch_direct(mcs_plan *p, hipStream_t s) {
     const void *kr = mcs_internal_reset_kernel();
     const void *ks = mcs_internal_search_kernel(p->word_bytes, p->directed, p->policy != nullptr);
-    int n = std::max(p->count, p->ring_slots);
+    int n = std::max(p->count, mcs::kRings * p->ring_slots);
     int rb = std::min(1024, (n + 255) / 256);
     void *ra[] = {&p->rp};
     HIP_TRY(hipLaunchKernel(kr, dim3(rb), dim3(256), ra, 0, s));
@@ -514,7 +517,7 @@ static mcs_status launch_direct(mcs_plan *p, hipStream_t s) {
 static mcs_status build_graph(mcs_plan *p) {
     HIP_TRY(hipGraphCreate(&p->graph, 0));
     hipGraphNode_t nr = nullptr, ns = nullptr;
-    int n = std::max(p->count, p->ring_slots);
+    int n = std::max(p->count, mcs::kRings * p->ring_slots);
     void *ra[] = {&p->rp};
     void *sa[] = {&p->sp};
     hipKernelNodeParams kp{};

@@ -14,13 +14,22 @@ struct DevInst {
     int32_t lb;        // initial incumbent size (0: none)
 };
 
+// The node queue is sharded into one ring per XCD (workgroup i runs on XCD
+// i mod 8): a wavefront donates into its own XCD's ring and takes from it
+// first, stealing from the other rings only when its own is empty.
+constexpr int kRings = 8;
+
+struct RingCtl {
+    unsigned long long head;  // next ticket to take
+    uint8_t pad_head[120];
+    unsigned long long tail;  // next ticket to fill
+    uint8_t pad_tail[120];
+};
+
 // Counters shared by every wavefront of a launch.  The ones every wavefront
 // polls or updates each sit on a cache line of their own.
 struct DevGlobals {
-    unsigned long long head;        // node queue: next ticket to take
-    uint8_t pad_head[120];
-    unsigned long long tail;        // node queue: next ticket to fill
-    uint8_t pad_tail[120];
+    RingCtl ring[kRings];
     // open_total and stop share one 8-byte word, so an idle wavefront reads
     // both with one load
     int open_total;                 // work units alive: instances not yet claimed,
@@ -53,10 +62,10 @@ struct SearchParams {
     unsigned long long *t_proof;  // [count] realtime ticks when open reached 0
     uint16_t *maps;               // per instance, per size s: s pairs (g | h << 8)
     DevGlobals *g;
-    unsigned long long *seq;      // [ring_slots] queue slot sequence numbers
-    uint8_t *slots;               // [ring_slots][slot_bytes]
+    unsigned long long *seq;      // [kRings][ring_slots] queue slot sequence numbers
+    uint8_t *slots;               // [kRings][ring_slots][slot_bytes]
     int count;
-    int ring_slots;
+    int ring_slots;               // slots per ring (a power of two)
     int slot_bytes;
     int cap_classes;      // LDS class capacity of one wavefront's stack
     int lds_per_wave;     // bytes

@@ -200,6 +200,8 @@ struct Searcher {
     int inc;
     bool stop;
     bool roots_left;  // false once every instance root has been claimed
+    int my_ring;      // this workgroup's XCD ring
+    int steal_from;   // the other ring tried next when idle
     int d0;           // depth of the unit's first frame (the shallowest)
     int since_check;
     unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops;
@@ -218,6 +220,8 @@ struct Searcher {
         nG = nH = 1;
         stop = false;
         roots_left = true;
+        my_ring = (int)(blockIdx.x & (kRings - 1));
+        steal_from = my_ring;
         d0 = 0;
         since_check = 0;
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = 0;
@@ -687,28 +691,36 @@ struct Searcher {
 
     // -- work sharing ------------------------------------------------------------
 
-    __device__ bool reserve(unsigned long long &ticket) {
+    // A free slot in this XCD's ring, else in the next rings; false if all
+    // are full (the donation is then skipped: the work stays local).
+    __device__ bool reserve(int &ring, unsigned long long &ticket) {
         const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
-        int ok = 0;
+        int ok = 0, rr = 0;
         unsigned long long tk = 0;
         if (lane == 0) {
-            for (int tries = 0; tries < 16; ++tries) {
-                unsigned long long tl = ld_rlx(&P.g->tail);
-                unsigned long long s = ld_rlx(&P.seq[tl & mask]);
-                if (s == tl) {
-                    if (cas64(&P.g->tail, tl, tl + 1)) {
-                        ok = 1;
-                        tk = tl;
-                        break;
+            for (int k = 0; k < kRings && !ok; ++k) {
+                const int r = (my_ring + k) & (kRings - 1);
+                unsigned long long *sq = P.seq + (size_t)r * P.ring_slots;
+                for (int tries = 0; tries < 4; ++tries) {
+                    unsigned long long tl = ld_rlx(&P.g->ring[r].tail);
+                    unsigned long long s = ld_rlx(&sq[tl & mask]);
+                    if (s == tl) {
+                        if (cas64(&P.g->ring[r].tail, tl, tl + 1)) {
+                            ok = 1;
+                            rr = r;
+                            tk = tl;
+                            break;
+                        }
+                    } else if (s < tl) {
+                        break;  // this ring is full
                     }
-                } else if (s < tl) {
-                    break;  // full
                 }
             }
         }
         // the slot's last reader has released it; order our writes after that
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         ok = rl(ok, 0);
+        ring = rl(rr, 0);
         ticket = rl_ull(tk, 0);
         return ok != 0;
     }
@@ -754,10 +766,12 @@ struct Searcher {
             b = t;
         }
         unsigned long long ticket;
-        if (!reserve(ticket))
+        int ring;
+        if (!reserve(ring, ticket))
             return;
         const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
-        uint8_t *slot = P.slots + (size_t)(ticket & mask) * (size_t)P.slot_bytes;
+        const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
+        uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
         int fK, fd, fbase;
         RecHdr<W> rh;
         if (b == t) {
@@ -797,7 +811,7 @@ struct Searcher {
         if (lane == 0) {
             a_add_rlx(&P.open[inst], 1);
             a_add_rlx(&P.g->open_total, 1);
-            st_rel(&P.seq[ticket & mask], ticket + 1);
+            st_rel(&P.seq[idx], ticket + 1);
         }
         if (b == t) {
             rrem = keep_r;
@@ -810,22 +824,32 @@ struct Searcher {
         n_don += 1;
     }
 
+    // Take a queued node: from this XCD's ring, else (steal) from one other
+    // ring, a different one on each call.
     __device__ bool take_record() {
         const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
-        int ok = 0;
+        int ok = 0, rr = 0;
         unsigned long long hd = 0;
         if (lane == 0) {
-            for (int tries = 0; tries < 16; ++tries) {
-                unsigned long long h = ld_rlx(&P.g->head);
-                unsigned long long s = ld_rlx(&P.seq[h & mask]);
-                if (s == h + 1) {
-                    if (cas64(&P.g->head, h, h + 1)) {
-                        ok = 1;
-                        hd = h;
-                        break;
+            steal_from = (steal_from + 1) & (kRings - 1);
+            if (steal_from == my_ring)
+                steal_from = (steal_from + 1) & (kRings - 1);
+            for (int k = 0; k < 2 && !ok; ++k) {
+                const int r = k == 0 ? my_ring : steal_from;
+                unsigned long long *sq = P.seq + (size_t)r * P.ring_slots;
+                for (int tries = 0; tries < 4; ++tries) {
+                    unsigned long long h = ld_rlx(&P.g->ring[r].head);
+                    unsigned long long s = ld_rlx(&sq[h & mask]);
+                    if (s == h + 1) {
+                        if (cas64(&P.g->ring[r].head, h, h + 1)) {
+                            ok = 1;
+                            rr = r;
+                            hd = h;
+                            break;
+                        }
+                    } else if (s < h + 1) {
+                        break;  // empty, or its producer is still writing
                     }
-                } else if (s < h + 1) {
-                    break;  // empty, or its producer is still writing
                 }
             }
         }
@@ -835,7 +859,9 @@ struct Searcher {
         // pairs with the producer's release store of the slot's sequence number
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         hd = rl_ull(hd, 0);
-        const uint8_t *slot = P.slots + (size_t)(hd & mask) * (size_t)P.slot_bytes;
+        const int ring = rl(rr, 0);
+        const size_t idx = (size_t)ring * P.ring_slots + (size_t)(hd & mask);
+        const uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
         RecHdr<W> rh = *(const RecHdr<W> *)slot;
         int ri = sc((int)rh.inst);
         K = sc((int)rh.K);
@@ -860,7 +886,7 @@ struct Searcher {
         // every lane's loads are done (waited on) before the slot is released
         __builtin_amdgcn_s_waitcnt(0);
         if (lane == 0)
-            st_rel(&P.seq[hd & mask], hd + (unsigned long long)P.ring_slots);
+            st_rel(&P.seq[idx], hd + (unsigned long long)P.ring_slots);
         set_instance(ri);
         if (lane < d)
             smap[lane] = mp;
@@ -930,8 +956,8 @@ struct Searcher {
             gi = ld_rlx(&P.inc[inst]);
             state = ld_rlx((unsigned long long *)&P.g->open_total);
             if (may_donate) {
-                tl = ld_rlx(&P.g->tail);
-                hd = ld_rlx(&P.g->head);
+                tl = ld_rlx(&P.g->ring[my_ring].tail);
+                hd = ld_rlx(&P.g->ring[my_ring].head);
                 hungry = ld_rlx(&P.g->idle);
             }
         }
@@ -1066,8 +1092,8 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
         R.t_best[i] = 0;
         R.t_proof[i] = 0;
     }
-    for (int i = tid; i < R.ring_slots; i += stride)
-        R.seq[i] = (unsigned long long)i;
+    for (int i = tid; i < kRings * R.ring_slots; i += stride)
+        R.seq[i] = (unsigned long long)(i % R.ring_slots);
     if (tid == 0) {
         DevGlobals z = {};
         z.t0 = ~0ull;
