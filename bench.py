@@ -25,6 +25,14 @@ sys.path.insert(0, ROOT)
 METRIC = "search nodes/sec + MCS instances/sec (batched) at exact size match"
 PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: int32 lane-ops/s
 
+# HBM bytes per launch of the search kernel, from the copy-calibrated
+# FETCH_SIZE / WRITE_SIZE runs recorded in profiles/ (see the design doc); reported
+# only while the kernel source is the one those counters were taken on.
+TRAFFIC = {
+    "c2_n30": {"kernel_sha256_16": "e777008e4536f54c", "bytes": (596196 * 2 + 426942) * 1024,
+               "profile": "profiles/mcs_search_kernel_c2_n30.md"},
+}
+
 # Algorithmic 32-bit lane operations per class per evaluated child: remove v
 # and w, split L and R by the adjacency letters, popcount every part, min()
 # per letter and the sum of Eq. 1 ("Roofline").
@@ -42,6 +50,20 @@ def workloads():
                     lambda: mi.pairs_c4(1024), "expected_c4_1024.json"),
         "c1": ("one undirected unlabelled pair G(16,0.3)", lambda: mi.pair_c1(), None),
     }
+
+
+def kernel_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1908_06418_amd", "csrc", "mcs_search.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(workload: str, launches: int):
+    t = TRAFFIC.get(workload)
+    if not t or t["kernel_sha256_16"] != kernel_hash():
+        return None
+    return t["bytes"] * launches
 
 
 def expected_sizes(fname):
@@ -192,7 +214,8 @@ def main():
         "waves": st.waves,
         "lds_per_wave": st.lds_per_wave,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
-                     "frac": achieved / peak if peak else 0.0, "traffic": None,
+                     "frac": achieved / peak if peak else 0.0,
+                     "traffic": traffic_for(args.workload, 1),
                      "kernel": "mcs_search_kernel",
                      "per_unit": f"{OPS_PER_CLASS[(word, directed)]} int32 lane-ops per class "
                                  "per evaluated child"},
