@@ -987,9 +987,30 @@ struct Searcher {
         }
     }
 
+    // The frame state is the same in every lane; saying so lets the
+    // compiler keep it in scalar registers and the per-child bookkeeping on
+    // the scalar unit (its divergence analysis cannot see through the loop).
+    __device__ void uniformize() {
+        t = sc(t);
+        base = sc(base);
+        K = sc(K);
+        d = sc(d);
+        v = sc(v);
+        sel = sc(sel);
+        bound = sc(bound);
+        flags = sc(flags);
+        lsel = sc(lsel);
+        rsel = sc(rsel);
+        rrem = sc(rrem);
+        logS = sc(logS);
+        inc = sc(inc);
+        since_check = sc(since_check);
+    }
+
     // Depth-first search from the frame loaded at level 0.
     __device__ void run() {
         while (!stop) {
+            uniformize();
             if (rrem != 0) {
                 batch();
             } else if (flags & kFlagUnmatched) {
