@@ -357,6 +357,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     p->lds_per_wave =
         mcs::lds_layout(p->word_bytes, directed, p->cap_classes, p->policy_levels).total;
     int wpb = 4;
+    max_lds_block -= 256;  // the kernel's static LDS (its parameter copy)
     while (wpb > 1 && wpb * p->lds_per_wave > max_lds_block)
         wpb >>= 1;
     if (p->lds_per_wave > max_lds_block) {

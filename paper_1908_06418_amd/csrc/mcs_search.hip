@@ -182,7 +182,8 @@ struct Searcher {
     static constexpr int NB = bits_of<W>();  // vertices per row word
     static constexpr int NR = DIR ? 4 : 2;   // adjacency row sets per instance
 
-    const SearchParams &P;
+    const SearchParams &P;  // a copy in LDS: cold fields are read when needed
+    int cmax, cap_classes, check_interval, reprune;  // hot knobs, kept in registers
     int lane;
     W *sadj;        // [NR][NB]: G rows, H rows (out), then G, H in-rows
     uint16_t *smap; // [NB] current path: g | h << 8
@@ -208,6 +209,10 @@ struct Searcher {
 
     __device__ Searcher(const SearchParams &p, uint8_t *lds) : P(p) {
         lane = lane_id();
+        cmax = sc(p.cmax);
+        cap_classes = sc(p.cap_classes);
+        check_interval = sc(p.check_interval);
+        reprune = sc(p.reprune);
         const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes,
                                        p.policy_levels);
         scls = (Cls<W> *)(lds + L.cls);
@@ -480,8 +485,8 @@ struct Searcher {
     __device__ void batch() {
         const int S = 1 << logS;
         int C = popc(rrem);
-        if (C > P.cmax)
-            C = P.cmax;
+        if (C > cmax)
+            C = cmax;
         if (C > (64 >> logS))
             C = 64 >> logS;
         const int seg = lane >> logS;
@@ -605,7 +610,7 @@ struct Searcher {
             K2 += __builtin_popcountll(m);
         }
         const int nb = base + K;
-        if (nb + K2 > P.cap_classes) {
+        if (nb + K2 > cap_classes) {
             fail();
             return;
         }
@@ -680,7 +685,7 @@ struct Searcher {
             if (t < 0)
                 return false;
             read_hdr(t);
-            if (P.reprune && bound <= inc)
+            if (reprune && bound <= inc)
                 continue;
             if (rrem == 0 && !(flags & kFlagUnmatched))
                 continue;
@@ -1019,7 +1024,7 @@ struct Searcher {
             } else if (!pop()) {
                 break;
             }
-            if (++since_check >= P.check_interval)
+            if (++since_check >= check_interval)
                 check();
         }
     }
@@ -1092,12 +1097,19 @@ struct Searcher {
 };
 
 template <typename W, bool DIR, bool POL>
-__global__ void __launch_bounds__(256) mcs_search_kernel(SearchParams P) {
+__global__ void __launch_bounds__(256) mcs_search_kernel(SearchParams Pk) {
     extern __shared__ __align__(16) uint8_t smem[];
+    // The parameters live in LDS, not in scalar registers for the whole
+    // kernel: the search loop needs few of them, and scalar registers are
+    // what its state lives in.
+    __shared__ SearchParams P;
+    if (threadIdx.x == 0)
+        P = Pk;
+    __syncthreads();
     const int wv = threadIdx.x >> 6;
-    if (P.single_wave && (blockIdx.x != 0 || wv != 0))
+    if (Pk.single_wave && (blockIdx.x != 0 || wv != 0))
         return;
-    Searcher<W, DIR, POL> s(P, smem + (size_t)wv * (size_t)P.lds_per_wave);
+    Searcher<W, DIR, POL> s(P, smem + (size_t)wv * (size_t)Pk.lds_per_wave);
     s.main_loop();
 }
 
