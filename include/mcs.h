@@ -100,6 +100,9 @@ typedef struct {
                                   order */
     int32_t policy_depth;      /* the policy orders choices at nodes with
                                   |M| <= policy_depth (ignored if policy is NULL) */
+    int32_t policy_mode;       /* bit 0: the policy picks v within the selected
+                                  class; bit 1: it orders the partners w
+                                  (0: order the partners only) */
 } mcs_opts;
 
 /* Per-instance result.  map_g/map_h are caller-owned arrays of capacity
@@ -184,9 +187,9 @@ mcs_status mcs_solve(const mcs_graph *G, const mcs_graph *H, const mcs_opts *opt
 /* ---- learned branching policy -------------------------------------------
  * A 16 -> 64 -> 64 -> 1 ReLU network scores a candidate vertex from 16
  * features of the search node (degrees, class sizes, depth, neighbours per
- * class-size bucket).  At nodes with |M| <= policy_depth the search branches
- * on the best-scored vertex of the selected class and tries its partners best
- * first.  Order only: every child is still explored or bounded by Eq. 1, so
+ * class-size bucket).  At nodes with |M| <= policy_depth the search tries the
+ * partners w of v best-scored first and, if asked (policy_mode bit 0),
+ * branches on the best-scored vertex v of the selected class.  Order only: every child is still explored or bounded by Eq. 1, so
  * results are the same as without the policy (the paper has no learned part;
  * its Solve leaves both choices to "some heuristic", Sec. II.B).
  *

@@ -72,6 +72,16 @@ def _load():
         if not os.path.exists(_LIB):
             build()
         lib = _bind(ctypes.CDLL(_LIB))
+        lib.oracle_extend.restype = ctypes.c_int32
+        lib.oracle_extend.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Graph),
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_branch_cost.restype = ctypes.c_int64
+        lib.oracle_branch_cost.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Graph),
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int64]
         lib.oracle_path.restype = ctypes.c_int32
         lib.oracle_path.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Graph),
                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -158,6 +168,42 @@ def path(G: dict, H: dict, steps) -> dict:
         classes.append((frozenset(i for i in range(G["n"]) if clg[i] == c),
                         frozenset(i for i in range(H["n"]) if clh[i] == c)))
     return {"bounds": [int(b) for b in bounds], "classes": classes}
+
+
+def extend(G: dict, H: dict, steps, target: int, node_limit: int = 0):
+    """True/False: does a common induced subgraph of size >= target contain
+    the pairs in steps (original ids, a legal sequence of McSplit steps)?
+    None if node_limit stopped the search; raises on an illegal path."""
+    lib = _load()
+    keep: list = []
+    cg, ch = _cgraph(G, keep), _cgraph(H, keep)
+    k = len(steps)
+    pg = np.array([s[0] for s in steps] or [0], np.int32)
+    ph = np.array([s[1] for s in steps] or [0], np.int32)
+    nodes = ctypes.c_int64(0)
+    r = lib.oracle_extend(ctypes.byref(cg), ctypes.byref(ch), k, _p32(pg), _p32(ph),
+                          int(target), int(node_limit), ctypes.byref(nodes))
+    if r == -1:
+        raise ValueError("illegal path")
+    return None if r == -2 else bool(r)
+
+
+def branch_cost(G: dict, H: dict, steps, v_first: int, incumbent: int,
+                node_limit: int = 0):
+    """Nodes the search spends below the node reached by steps when it
+    branches on v_first there (incumbent fixed): None if node_limit was hit;
+    raises if steps or v_first are not legal there."""
+    lib = _load()
+    keep: list = []
+    cg, ch = _cgraph(G, keep), _cgraph(H, keep)
+    k = len(steps)
+    pg = np.array([s[0] for s in steps] or [0], np.int32)
+    ph = np.array([s[1] for s in steps] or [0], np.int32)
+    r = lib.oracle_branch_cost(ctypes.byref(cg), ctypes.byref(ch), k, _p32(pg), _p32(ph),
+                               int(v_first), int(incumbent), int(node_limit))
+    if r == -1:
+        raise ValueError("illegal path or branching vertex")
+    return None if r == -2 else int(r)
 
 
 from . import brute, check, clique, labels  # noqa: E402,F401

@@ -49,3 +49,52 @@ def mcs_size(G: dict, H: dict) -> int:
 
     rec(0, 0)
     return best
+
+
+def mcs_size_with(G: dict, H: dict, forced) -> int:
+    """Largest valid injective map that contains the pairs in forced (which
+    must themselves be consistent), by the same exhaustive enumeration."""
+    A, B = _matrix(G), _matrix(H)
+    nG, nH = G["n"], H["n"]
+    lg, lh = G.get("label"), H.get("label")
+    fixed = dict(forced)
+    f = [-1] * nG
+    used = [False] * nH
+    for u, h in fixed.items():
+        f[u], used[h] = h, True
+    best = 0
+
+    def ok(u, h):
+        if lg is not None and lg[u] != lh[h]:
+            return False
+        for x in range(nG):
+            y = f[x]
+            if x != u and y >= 0 and (A[u][x] != B[h][y] or A[x][u] != B[y][h]):
+                return False
+        return True
+
+    for u, h in fixed.items():
+        f[u] = -1
+        if not ok(u, h):
+            return -1
+        f[u] = h
+
+    def rec(u, size):
+        nonlocal best
+        if u == nG:
+            best = max(best, size)
+            return
+        if size + (nG - u) <= best:
+            return
+        if u in fixed:
+            rec(u + 1, size + 1)
+            return
+        for h in range(nH):
+            if not used[h] and ok(u, h):
+                f[u], used[h] = h, True
+                rec(u + 1, size + 1)
+                f[u], used[h] = -1, False
+        rec(u + 1, size)
+
+    rec(0, 0)
+    return best

@@ -84,6 +84,7 @@ typedef struct {
     int best;
     int64_t nodes, node_limit;
     int aborted;
+    int target; /* > 0: stop as soon as a mapping of this size is found */
 } search_ctx;
 
 /* ---- degree ordering (Sec. IV.A) ------------------------------------- */
@@ -214,6 +215,10 @@ static void solve(search_ctx *s, int level, int m, const bidomain *C, int K)
         s->best = m;
         memcpy(s->bg, s->mg, sizeof(int) * (size_t)m);
         memcpy(s->bh, s->mh, sizeof(int) * (size_t)m);
+        if (s->target > 0 && m >= s->target) {
+            s->aborted = 1; /* found what was asked for */
+            return;
+        }
     }
     if (eq1_bound(m, C, K) <= s->best)
         return;
@@ -473,6 +478,159 @@ int32_t oracle_path(const oracle_graph *G, const oracle_graph *H, int32_t k,
         }
         ret = K;
     }
+    ctx_free(&s);
+    return ret;
+}
+
+/*
+ * Does some common induced subgraph of size >= target contain the pairs of a
+ * given path?  Replays the class split along the path (original ids; every
+ * step must map v and w of one class), then searches on from there exactly
+ * as Solve does, with the incumbent set to target - 1 so that only larger
+ * mappings count, stopping at the first one found.  Returns 1 (yes), 0 (no),
+ * -1 (the path is not a legal sequence of steps) or -2 (node_limit > 0 was
+ * reached first).
+ */
+int32_t oracle_extend(const oracle_graph *G, const oracle_graph *H, int32_t k,
+                      const int32_t *path_g, const int32_t *path_h, int32_t target,
+                      int64_t node_limit, int64_t *nodes)
+{
+    if (k < 0 || k > G->n || k > H->n)
+        return -1;
+    search_ctx s;
+    ctx_init(&s, G, H, 0);
+    int K = root_classes(&s, G, H);
+    bidomain *C = s.lev[0].cls;
+    for (int t = 0; t < k; t++) {
+        int v = path_g[t], w = path_h[t];
+        int found = -1;
+        for (int c = 0; c < K; c++)
+            for (int i = 0; i < C[c].nl; i++)
+                if (C[c].l[i] == v)
+                    for (int j = 0; j < C[c].nr; j++)
+                        if (C[c].r[j] == w)
+                            found = c;
+        if (found < 0) {
+            ctx_free(&s);
+            return -1;
+        }
+        level_buf *nb = &s.lev[t + 1];
+        K = filter_domains(&s, C, K, v, w, nb->cls, nb->verts);
+        s.mg[t] = v;
+        s.mh[t] = w;
+        C = nb->cls;
+    }
+    s.best = target - 1;
+    s.target = target;
+    s.node_limit = node_limit;
+    solve(&s, k, k, C, K);
+    int ret;
+    if (s.best >= target)
+        ret = 1;
+    else if (s.aborted)
+        ret = -2;
+    else
+        ret = 0;
+    if (nodes)
+        *nodes = s.nodes;
+    ctx_free(&s);
+    return ret;
+}
+
+/*
+ * Proof cost of branching on a chosen vertex: replay the path (original
+ * ids, in the descending-degree numbering the search uses), then expand that
+ * node as Solve does but with v_first as the branching vertex (it must lie in
+ * the class the node would select), the incumbent fixed at `incumbent` (so
+ * nothing improves and only refutation work is counted), and count every
+ * entry into Solve.  Returns the node count, -1 for an illegal path or
+ * v_first, or -2 if node_limit > 0 was reached.
+ */
+int64_t oracle_branch_cost(const oracle_graph *G, const oracle_graph *H, int32_t k,
+                           const int32_t *path_g, const int32_t *path_h, int32_t v_first,
+                           int32_t incumbent, int64_t node_limit)
+{
+    if (k < 0 || k > G->n || k > H->n)
+        return -1;
+    search_ctx s;
+    ctx_init(&s, G, H, 1);
+    int nG = G->n, nH = H->n;
+    int *invG = (int *)malloc(sizeof(int) * (size_t)(nG ? nG : 1));
+    int *invH = (int *)malloc(sizeof(int) * (size_t)(nH ? nH : 1));
+    for (int i = 0; i < nG; i++)
+        invG[s.ordG[i]] = i;
+    for (int i = 0; i < nH; i++)
+        invH[s.ordH[i]] = i;
+    int K = root_classes(&s, G, H);
+    bidomain *C = s.lev[0].cls;
+    int64_t ret = 0;
+    for (int t = 0; t < k && ret == 0; t++) {
+        int v = invG[path_g[t]], w = invH[path_h[t]];
+        int found = -1;
+        for (int c = 0; c < K; c++)
+            for (int i = 0; i < C[c].nl; i++)
+                if (C[c].l[i] == v)
+                    for (int j = 0; j < C[c].nr; j++)
+                        if (C[c].r[j] == w)
+                            found = c;
+        if (found < 0) {
+            ret = -1;
+            break;
+        }
+        level_buf *nb = &s.lev[t + 1];
+        K = filter_domains(&s, C, K, v, w, nb->cls, nb->verts);
+        s.mg[t] = v;
+        s.mh[t] = w;
+        C = nb->cls;
+    }
+    int vf = (v_first >= 0 && v_first < nG) ? invG[v_first] : -1;
+    int sel = K > 0 ? select_class(C, K) : -1;
+    int ok = 0;
+    if (ret == 0 && sel >= 0)
+        for (int i = 0; i < C[sel].nl; i++)
+            if (C[sel].l[i] == vf)
+                ok = 1;
+    if (ret == 0 && !ok)
+        ret = -1;
+    if (ret == 0) {
+        s.best = incumbent;
+        s.node_limit = node_limit;
+        s.nodes = 1; /* the node itself */
+        int m = k;
+        if (eq1_bound(m, C, K) > s.best) {
+            level_buf *nb = &s.lev[k + 1];
+            for (int i = 0; i < C[sel].nr && !s.aborted; i++) {
+                int w = C[sel].r[i];
+                int K2 = filter_domains(&s, C, K, vf, w, nb->cls, nb->verts);
+                s.mg[m] = vf;
+                s.mh[m] = w;
+                solve(&s, k + 1, m + 1, nb->cls, K2);
+            }
+            if (!s.aborted) {
+                int K2 = 0, used = 0;
+                for (int c = 0; c < K; c++) {
+                    int *l = nb->verts + used, nl = 0;
+                    for (int i = 0; i < C[c].nl; i++)
+                        if (C[c].l[i] != vf)
+                            l[nl++] = C[c].l[i];
+                    if (nl == 0)
+                        continue;
+                    int *r = l + nl;
+                    memcpy(r, C[c].r, sizeof(int) * (size_t)C[c].nr);
+                    nb->cls[K2].l = l;
+                    nb->cls[K2].nl = nl;
+                    nb->cls[K2].r = r;
+                    nb->cls[K2].nr = C[c].nr;
+                    K2++;
+                    used += nl + C[c].nr;
+                }
+                solve(&s, k + 1, m, nb->cls, K2);
+            }
+        }
+        ret = s.aborted ? -2 : s.nodes;
+    }
+    free(invG);
+    free(invH);
     ctx_free(&s);
     return ret;
 }

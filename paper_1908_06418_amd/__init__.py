@@ -80,7 +80,7 @@ class _Marshal:
                               rows.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), lab)
 
 
-def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0):
+def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0, policy_mode=0):
     """policy: a torch half tensor of packed parameters on the device (or an
     object with .half_params, see policy.Policy)."""
     t = None
@@ -93,7 +93,7 @@ def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0):
         hp = getattr(policy, "half_params", policy)
         ptr = ctypes.c_void_p(hp.data_ptr())
     o = _abi.mcs_opts(int(node_limit or 0), float(time_limit_s or 0.0), t, ptr,
-                      int(policy_depth))
+                      int(policy_depth), int(policy_mode))
     return o, tc
 
 
@@ -136,12 +136,13 @@ class Plan:
     (mcs_plan_run) -- inputs stay resident in HBM between runs."""
 
     def __init__(self, pairs, node_limit=0, time_limit_s=0.0, tuning=None, policy=None,
-                 policy_depth=2):
+                 policy_depth=1, policy_mode=0):
         self.lib = _abi.load()
         self.pairs = list(pairs)
         self._m = _Marshal(self.pairs)
         self._policy = policy  # keeps the device parameters alive
-        self._o, self._t = _opts(node_limit, time_limit_s, tuning, policy, policy_depth)
+        self._o, self._t = _opts(node_limit, time_limit_s, tuning, policy, policy_depth,
+                                 policy_mode)
         h = ctypes.c_void_p()
         st = self.lib.mcs_plan_create(len(self.pairs), self._m.G, self._m.H,
                                       ctypes.byref(self._o), ctypes.byref(h))
@@ -220,9 +221,9 @@ class Plan:
 
 
 def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=False,
-                policy=None, policy_depth=2):
+                policy=None, policy_depth=1, policy_mode=0):
     """MCS of every pair in one launch.  Returns a list of Result (and Stats)."""
-    p = Plan(pairs, node_limit, time_limit_s, tuning, policy, policy_depth).upload()
+    p = Plan(pairs, node_limit, time_limit_s, tuning, policy, policy_depth, policy_mode).upload()
     p.run()
     res = p.results()
     st = p.stats() if with_stats else None

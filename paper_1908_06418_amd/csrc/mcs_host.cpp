@@ -131,7 +131,7 @@ struct mcs_plan {
     int64_t node_limit = 0;
     double time_limit_s = 600.0;
     const uint16_t *policy = nullptr;
-    int policy_depth = 0, policy_levels = 0;
+    int policy_depth = 0, policy_levels = 0, policy_mode = 0;
 
     std::vector<mcs::DevInst> inst;
     std::vector<uint8_t> adj;      // packed rows, word_bytes each
@@ -260,6 +260,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
             }
             p->policy = opts->policy;
             p->policy_depth = opts->policy_depth;
+            p->policy_mode = opts->policy_mode ? (opts->policy_mode & 3) : 2;
             p->policy_levels = opts->policy_depth + 1;
         }
         p->node_limit = opts->node_limit > 0 ? opts->node_limit : 0;
@@ -479,6 +480,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.policy = p->policy;
     sp.policy_depth = p->policy_depth;
     sp.policy_levels = p->policy_levels;
+    sp.policy_mode = p->policy_mode;
     double ticks = p->time_limit_s * p->tick_hz;
     sp.limit_ticks = ticks > 9e18 ? (unsigned long long)9e18 : (unsigned long long)ticks;
     sp.node_limit = p->node_limit;

@@ -77,6 +77,7 @@ struct SearchParams {
     int single_wave;
     const uint16_t *policy;  // half-precision policy parameters, or null
     int policy_depth;        // policy orders frames with |M| <= this
+    int policy_mode;         // bit 0: policy picks v; bit 1: policy orders partners
     int policy_levels;       // LDS partner-order lists per wavefront (0 without policy)
     unsigned long long limit_ticks;  // time limit in realtime ticks
     long long node_limit;            // 0: none

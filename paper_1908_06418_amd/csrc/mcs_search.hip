@@ -275,9 +275,13 @@ struct Searcher {
         if constexpr (POL) {
             if (d <= P.policy_depth && t < P.policy_levels) {
                 // learned choice of v within the class, and of the partners' order
-                float sg = policy_score(0, rl(cL, who));
-                v = argmax_lane(sg, rl(cL, who));
-                order_partners(rrem);
+                const int mode = P.policy_mode;
+                if (mode & 1) {
+                    float sg = policy_score(0, rl(cL, who));
+                    v = argmax_lane(sg, rl(cL, who));
+                }
+                if (mode & 2)
+                    order_partners(rrem);
             }
         }
     }

@@ -77,15 +77,20 @@ def test_sgd_and_pack(gpu):
 
 
 def _rows_of(args):
-    i, G, H = args
+    G, H = args
     from oracle import traces
-    return traces.pair_rows(G, H, np.random.default_rng(i))
+    Xb, yb = traces.branch_pair_rows(G, H)
+    Xv, yv = traces.value_pair_rows(G, H)
+    return Xb + Xv, yb + yv
 
 
-def _training_set(count, start=0):
-    pairs = mi.pairs_c5(count, start=start, train=True)
+def _training_set(count):
+    """Rows from the training workload's pairs of up to 24 vertices:
+    branching-vertex rows (proof-cost labels) and partner-order rows
+    (reachability labels), both from the oracle."""
+    pairs = [pq for pq in mi.pairs_c5(3 * count, train=True) if pq[0]["n"] <= 24][:count]
     with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-        parts = list(ex.map(_rows_of, [(start + i, G, H) for i, (G, H) in enumerate(pairs)]))
+        parts = list(ex.map(_rows_of, pairs))
     X = np.array([r for Xa, _ in parts for r in Xa]).reshape(-1, ref.F)
     y = np.array([v for _, ya in parts for v in ya])
     return X, y
@@ -98,10 +103,10 @@ def _trained_policy():
     if "p" not in _TRAINED:
         from paper_1908_06418_amd.policy import Policy
         _say("policy: generating oracle traces")
-        X, y = _training_set(160)
+        X, y = _training_set(120)
         _say(f"policy: {len(y)} rows, {y.mean():.2f} positive; training on the GPU")
         P = Policy(seed=0)
-        curve = P.train(X, y, steps=400, lr=0.5)
+        curve = P.train(X, y, steps=600, lr=0.5)
         _TRAINED.update(p=P, curve=curve, rows=len(y))
     return _TRAINED["p"], _TRAINED["curve"]
 
@@ -123,49 +128,66 @@ def test_policy_search_is_exact(gpu, trained):
     pairs += [(mi.random_small(rng, 14, 0.5, True, 2), mi.random_small(rng, 15, 0.5, True, 2))
               for _ in range(10)]
     want = [oracle.mcs(G, H)["size"] for G, H in pairs]
-    for depth in (0, 2):
-        _say(f"policy search trained={trained} depth={depth}")
-        res = solve_batch(pairs, time_limit_s=60, policy=P, policy_depth=depth)
+    for depth, mode in ((0, 3), (2, 1), (2, 2), (1, 3)):
+        _say(f"policy search trained={trained} depth={depth} mode={mode}")
+        res = solve_batch(pairs, time_limit_s=60, policy=P, policy_depth=depth,
+                          policy_mode=mode)
         for (G, H), r, w in zip(pairs, res, want):
             assert r.optimal and r.size == w
             assert oracle.check.is_valid(G, H, r.mapping)
     _say("policy search single wave")
-    res = solve_batch(pairs[:20], time_limit_s=60, policy=P, policy_depth=2,
+    res = solve_batch(pairs[:20], time_limit_s=60, policy=P, policy_depth=2, policy_mode=3,
                       tuning={"single_wave": 1})
     assert [r.size for r in res] == want[:20]
 
 
 def test_policy_gain_report(gpu):
-    """What the trained policy gains over degree ordering, on held-out pairs
-    of the training distribution (single wavefront: node counts are
-    deterministic) and on a sample of the n = 35..50 evaluation workload."""
-    from paper_1908_06418_amd import solve_batch
+    """What the trained policy gains over the plain rule (smallest vertex in
+    descending-degree order, partners in index order) at |M| <= 1: node
+    counts on held-out pairs of the training distribution (one wavefront, so
+    counts are deterministic) for each policy mode, and time-to-proof on the
+    60 pairs of G(30,p) (parallel search) for the best mode."""
+    from paper_1908_06418_amd import Plan, solve_batch
     P, curve = _trained_policy()
-    held = [pq for pq in mi.pairs_c5(80, start=5000, train=True) if pq[0]["n"] <= 24][:40]
+    held = [pq for pq in mi.pairs_c5(200, start=5000, train=True) if pq[0]["n"] <= 24][:40]
     tun = {"single_wave": 1}
-    _say("gain: held-out, degree ordering")
+    _say("gain: held-out, plain rule")
     base = solve_batch(held, time_limit_s=100, tuning=tun)
-    _say("gain: held-out, learned ordering")
-    lrn = solve_batch(held, time_limit_s=100, tuning=tun, policy=P, policy_depth=2)
-    both = [(b, l) for b, l in zip(base, lrn) if b.optimal and l.optimal]
-    assert len(both) >= 30
-    assert all(b.size == l.size for b, l in both)
-    ratios = [l.nodes / b.nodes for b, l in both]
-    total = sum(l.nodes for _, l in both) / sum(b.nodes for b, _ in both)
-    evalp = mi.pairs_c5(24)
-    _say("gain: evaluation sample, degree ordering")
-    eb = solve_batch(evalp, time_limit_s=30)
-    _say("gain: evaluation sample, learned ordering")
-    el = solve_batch(evalp, time_limit_s=30, policy=P, policy_depth=2)
-    pr = [(b, l) for b, l in zip(eb, el) if b.optimal and l.optimal]
-    assert all(b.size == l.size for b, l in pr)
-    report = {"held_out_pairs": len(both), "nodes_ratio_total": total,
-              "nodes_ratio_median": float(np.median(ratios)),
-              "eval_pairs_proven_both": len(pr), "eval_pairs": len(evalp),
-              "eval_proof_time_ratio_median": float(np.median(
-                  [l.t_proof_s / b.t_proof_s for b, l in pr])) if pr else None,
-              "eval_proven_degree": sum(b.optimal for b in eb),
-              "eval_proven_learned": sum(l.optimal for l in el),
+    modes = {}
+    for mode in (1, 2, 3):
+        _say(f"gain: held-out, policy mode {mode}")
+        lrn = solve_batch(held, time_limit_s=100, tuning=tun, policy=P, policy_depth=1,
+                          policy_mode=mode)
+        both = [(b, l) for b, l in zip(base, lrn) if b.optimal and l.optimal]
+        assert len(both) >= 30
+        assert all(b.size == l.size for b, l in both)
+        modes[mode] = {"pairs": len(both),
+                       "nodes_ratio_total": sum(l.nodes for _, l in both) /
+                       sum(b.nodes for b, _ in both),
+                       "nodes_ratio_median": float(np.median([l.nodes / b.nodes
+                                                              for b, l in both]))}
+    best = min(modes, key=lambda m: modes[m]["nodes_ratio_total"])
+    c2 = mi.pairs_c2(ns=(30,))
+    times = {}
+    for name, kw in (("plain", {}), ("learned", {"policy": P, "policy_depth": 1,
+                                                 "policy_mode": best})):
+        plan = Plan(c2, time_limit_s=60, **kw).upload()
+        ms = []
+        for rep in range(3):
+            _say(f"gain: c2 n=30, {name}, run {rep}")
+            plan.run()
+            res = plan.results()
+            assert all(r.optimal for r in res)
+            ms.append(plan.stats().kernel_ms)
+        times[name] = (min(ms), [r.size for r in res], sum(r.nodes for r in res))
+        plan.close()
+    assert times["plain"][1] == times["learned"][1]
+    report = {"held_out_by_mode": modes, "best_mode": best,
+              "c2_n30_kernel_ms_plain": times["plain"][0],
+              "c2_n30_kernel_ms_learned": times["learned"][0],
+              "c2_n30_nodes_plain": times["plain"][2],
+              "c2_n30_nodes_learned": times["learned"][2],
+              "train_rows": _TRAINED["rows"],
               "train_loss_first_last": [curve[0], curve[-1]]}
     _say("policy gain: " + json.dumps(report))
     os.makedirs("gpurun_out", exist_ok=True)

@@ -243,3 +243,32 @@ def test_planted_oracle_mistakes_are_caught(plant, tmp_path):
         if oracle.mcs(G, H, lib=lib)["size"] != oracle.brute.mcs_size(G, H):
             wrong += 1
     assert wrong > 0
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_extend_matches_forced_brute_force(directed):
+    """oracle.extend(path, target) == (largest valid map containing the path
+    has at least target pairs), the latter by exhaustive search."""
+    rng = np.random.default_rng(60 + directed)
+    checked = 0
+    for trial in range(80):
+        n1, n2 = int(rng.integers(3, 8)), int(rng.integers(3, 8))
+        p = float(rng.uniform(0.2, 0.8))
+        G = mi.random_small(rng, n1, p, directed)
+        H = mi.random_small(rng, n2, p, directed)
+        best = oracle.mcs(G, H)
+        k = int(rng.integers(0, min(3, best["size"]) + 1))
+        # a legal path: k pairs of some valid map (the oracle's, or random)
+        pairs = best["map"][:k]
+        if rng.random() < 0.5 and k:
+            # replace the last pair by a random label-compatible one
+            steps = pairs[:-1]
+            r = oracle.path(G, H, steps)
+            cand = [(v, w) for L, R in r["classes"] for v in L for w in R]
+            if cand:
+                pairs = steps + [cand[int(rng.integers(len(cand)))]]
+        truth = oracle.brute.mcs_size_with(G, H, pairs)
+        for target in range(0, best["size"] + 2):
+            assert oracle.extend(G, H, pairs, target) == (truth >= target), (pairs, target)
+            checked += 1
+    assert checked > 200
