@@ -168,6 +168,20 @@ mcs_status mcs_plan_results(mcs_plan *plan, mcs_result *results, void *stream);
 /* Statistics of the last run (valid after mcs_plan_results). */
 mcs_status mcs_plan_stats(const mcs_plan *plan, mcs_stats *stats);
 
+/* Goal-directed runs (paper Sec. IV.A, top-down search and bound
+ * correction).  goal[i] > 0: the next run asks only whether instance i has a
+ * common induced subgraph of at least goal[i] vertices -- its incumbent starts
+ * at goal[i] - 1 and its search stops at the first such mapping (the result
+ * then has size >= goal[i] and optimal = 1 means the question was settled:
+ * either such a mapping was found, or, with size < goal[i], none exists).
+ * goal[i] == 0: plain search; goal[i] < 0: skip instance i.  Goals stay set
+ * until changed.  Errors: MCS_E_INVALID (a goal above min(nG, nH)),
+ * MCS_E_WORKSPACE, MCS_E_DEVICE. */
+mcs_status mcs_plan_set_goals(mcs_plan *plan, const int32_t *goal, void *stream);
+
+/* Eq. 1 at the root of each instance (an upper bound on its MCS size). */
+mcs_status mcs_plan_root_bounds(const mcs_plan *plan, int32_t *bounds);
+
 void mcs_plan_destroy(mcs_plan *plan);
 
 /* Workspace bytes mcs_solve_batch needs for these instances. */
@@ -179,6 +193,19 @@ size_t mcs_workspace_size(int32_t count, const mcs_graph *G, const mcs_graph *H,
 mcs_status mcs_solve_batch(int32_t count, const mcs_graph *G, const mcs_graph *H,
                            const mcs_opts *opts, void *workspace, size_t bytes,
                            void *stream, mcs_result *results);
+
+/* Goal-directed search over a batch, as the paper's top-down and
+ * bound-correction variants (Sec. IV.A).  strategy 0: goals root bound,
+ * root bound - 1, ...; the first goal reached is the optimum.  strategy 1:
+ * a plain run bounded by opts->node_limit gives a lower bound, then a binary
+ * search on the goal between it and the root bound.  Each launch gets the
+ * whole opts->time_limit_s; the call stops with MCS_LIMIT once their sum
+ * exceeds it.  results as for mcs_solve_batch (nodes summed over launches);
+ * *launches (may be NULL) = kernel launches used. */
+mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                           const mcs_opts *opts, int32_t strategy, void *workspace,
+                           size_t bytes, void *stream, mcs_result *results,
+                           int32_t *launches);
 
 /* One pair: mcs_solve_batch with count = 1. */
 mcs_status mcs_solve(const mcs_graph *G, const mcs_graph *H, const mcs_opts *opts,

@@ -17,8 +17,8 @@ import numpy as np
 
 from . import _abi
 
-__all__ = ["McsError", "Plan", "solve", "solve_batch", "workspace_size", "Tuning",
-           "status_string"]
+__all__ = ["McsError", "Plan", "solve", "solve_batch", "solve_goals", "workspace_size",
+           "Tuning", "status_string"]
 
 
 class McsError(RuntimeError):
@@ -229,6 +229,44 @@ def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=F
     st = p.stats() if with_stats else None
     p.close()
     return (res, st) if with_stats else res
+
+
+def solve_goals(pairs, strategy="top-down", node_limit=0, time_limit_s=0.0, tuning=None,
+                with_launches=False):
+    """Goal-directed search (mcs_solve_goals): strategy "top-down" asks for
+    the root bound, then one less, ...; "bisect" takes a node-limited plain
+    run's size as a lower bound and binary-searches the goal."""
+    import torch
+    lib = _abi.load()
+    _torch()
+    pairs = list(pairs)
+    m = _Marshal(pairs)
+    o, _t = _opts(node_limit, time_limit_s, tuning)
+    nbytes = int(lib.mcs_workspace_size(len(pairs), m.G, m.H, ctypes.byref(o)))
+    if nbytes == 0:
+        raise McsError(-1, _last_error())
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) & ~255
+    stream = torch.cuda.current_stream()
+    n = len(pairs)
+    res = (_abi.mcs_result * n)()
+    bufs = []
+    for i, (g, h) in enumerate(pairs):
+        cap = max(1, min(int(g["n"]), int(h["n"])))
+        mg, mh = (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)()
+        bufs.append((mg, mh))
+        res[i].map_g, res[i].map_h = mg, mh
+    launches = ctypes.c_int32(0)
+    strat = {"top-down": 0, "bisect": 1}[strategy]
+    st = lib.mcs_solve_goals(n, m.G, m.H, ctypes.byref(o), strat, ctypes.c_void_p(base), nbytes,
+                             ctypes.c_void_p(stream.cuda_stream), res, ctypes.byref(launches))
+    if st < 0:
+        raise McsError(st, _last_error())
+    out = [Result(int(r.size), bool(r.optimal),
+                  [(int(bufs[i][0][j]), int(bufs[i][1][j])) for j in range(max(r.size, 0))],
+                  int(r.nodes), float(r.t_best_s), float(r.t_proof_s))
+           for i, r in enumerate(res)]
+    return (out, int(launches.value)) if with_launches else out
 
 
 def solve(G, H, **kw):

@@ -66,7 +66,14 @@ SIGNATURES = [
     ("mcs_plan_run", ctypes.c_int, [_P, _P]),
     ("mcs_plan_results", ctypes.c_int, [_P, ctypes.POINTER(mcs_result), _P]),
     ("mcs_plan_stats", ctypes.c_int, [_P, ctypes.POINTER(mcs_stats)]),
+    ("mcs_plan_set_goals", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
+    ("mcs_plan_root_bounds", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     ("mcs_plan_destroy", None, [_P]),
+    ("mcs_solve_goals", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(mcs_graph),
+                                       ctypes.POINTER(mcs_graph), ctypes.POINTER(mcs_opts),
+                                       ctypes.c_int32, _P, ctypes.c_size_t, _P,
+                                       ctypes.POINTER(mcs_result),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     ("mcs_workspace_size", ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(mcs_graph),
                                              ctypes.POINTER(mcs_graph), ctypes.POINTER(mcs_opts)]),
     ("mcs_solve_batch", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(mcs_graph),

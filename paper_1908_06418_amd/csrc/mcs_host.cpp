@@ -138,6 +138,8 @@ struct mcs_plan {
     std::vector<uint8_t> rootcls;  // packed (L, R) pairs
     std::vector<std::vector<int>> ordG, ordH;
     std::vector<int> m;            // min(nG, nH) per instance
+    std::vector<int> K0;           // root class count per instance
+    std::vector<int> root_bound;   // Eq. 1 at the root per instance
     size_t map_pairs = 0;
 
     // device layout
@@ -334,7 +336,31 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         di.cls_off = cls_off;
         di.map_off = (uint32_t)map_off;
         di.lb = 0;
+        di.target = 0;
         p->inst[i] = di;
+        p->K0.push_back(K0);
+        // Eq. 1 at the root: the largest size any goal needs to consider
+        int rb = 0;
+        if (g.n > 0 && h.n > 0) {
+            if (!g.label) {
+                rb = std::min(g.n, h.n);
+            } else {
+                std::vector<int> seen;
+                for (int a = 0; a < g.n; a++) {
+                    int lab = g.label[a];
+                    if (std::find(seen.begin(), seen.end(), lab) != seen.end())
+                        continue;
+                    seen.push_back(lab);
+                    int cg = 0, ch = 0;
+                    for (int b = 0; b < g.n; b++)
+                        cg += g.label[b] == lab;
+                    for (int b = 0; b < h.n; b++)
+                        ch += h.label[b] == lab;
+                    rb += std::min(cg, ch);
+                }
+            }
+        }
+        p->root_bound.push_back(rb);
         cls_off += (uint32_t)K0;
         map_off += (size_t)mi * (mi + 1) / 2;
     }
@@ -662,7 +688,194 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     return MCS_OK;
 }
 
+mcs_status mcs_plan_set_goals(mcs_plan *p, const int32_t *goal, void *stream) {
+    g_err.clear();
+    if (!p || !goal)
+        return fail(MCS_E_INVALID, "NULL argument");
+    if (!p->uploaded)
+        return fail(MCS_E_WORKSPACE, "mcs_plan_upload has not been called");
+    for (int i = 0; i < p->count; i++) {
+        mcs::DevInst &di = p->inst[i];
+        if (goal[i] > p->m[i])
+            return fail(MCS_E_INVALID, "a goal exceeds min(nG, nH)");
+        di.K0 = (uint8_t)(goal[i] < 0 ? 0 : p->K0[i]);
+        di.lb = goal[i] > 0 ? goal[i] - 1 : 0;
+        di.target = goal[i] > 0 ? goal[i] : 0;
+    }
+    HIP_TRY(hipMemcpyAsync(p->ws + p->off_inst, p->inst.data(), sizeof(mcs::DevInst) * p->count,
+                           hipMemcpyHostToDevice, as_stream(stream)));
+    HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+    return MCS_OK;
+}
+
+mcs_status mcs_plan_root_bounds(const mcs_plan *p, int32_t *bounds) {
+    if (!p || !bounds)
+        return fail(MCS_E_INVALID, "NULL argument");
+    for (int i = 0; i < p->count; i++)
+        bounds[i] = p->root_bound[i];
+    return MCS_OK;
+}
+
 void mcs_plan_destroy(mcs_plan *p) { delete p; }
+
+// Goal-directed search over a batch (paper Sec. IV.A): each launch asks, per
+// open instance, "is there a common induced subgraph of at least `goal`
+// vertices?" (incumbent goal - 1, stop at the first mapping found).
+//   strategy 0 (top-down): goals root bound, root bound - 1, ... until one is
+//     reached; the first goal reached is the optimum.
+//   strategy 1 (bound correction): a plain run bounded by opts->node_limit
+//     gives a lower bound lo (and may already finish); then binary search on
+//     the goal in (lo, root bound], each refuted goal lowering the upper bound.
+// Every launch gets the full opts time limit; the node limit applies to the
+// first run of strategy 1 only.  Instances whose answer is settled are
+// skipped by later launches.
+mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                           const mcs_opts *opts, int32_t strategy, void *workspace,
+                           size_t bytes, void *stream, mcs_result *results,
+                           int32_t *launches) {
+    if (!results)
+        return fail(MCS_E_INVALID, "results is NULL");
+    for (int i = 0; i < count; i++)
+        results[i].size = -1;
+    if (strategy != 0 && strategy != 1)
+        return fail(MCS_E_INVALID, "strategy must be 0 (top-down) or 1 (bound correction)");
+    mcs_opts o1 = opts ? *opts : mcs_opts{};
+    mcs_opts og = o1;
+    og.node_limit = 0;
+    mcs_plan *p = nullptr;
+    mcs_status st = mcs_plan_create(count, G, H, strategy == 1 ? &o1 : &og, &p);
+    if (st != MCS_OK)
+        return st;
+    struct PlanGuard {
+        mcs_plan *p;
+        ~PlanGuard() { mcs_plan_destroy(p); }
+    } guard{p};
+    st = mcs_plan_upload(p, workspace, bytes, stream);
+    if (st != MCS_OK)
+        return st;
+    const int n = count;
+    std::vector<int> lo(n, 0), hi(p->root_bound), goal(n, 0), done(n, 0);
+    std::vector<std::vector<int32_t>> mg(n), mh(n);
+    std::vector<int64_t> nodes(n, 0);
+    std::vector<double> tbest(n, 0.0), tproof(n, 0.0);
+    std::vector<mcs_result> r(n);
+    std::vector<std::vector<int32_t>> bg(n), bh(n);
+    for (int i = 0; i < n; i++) {
+        bg[i].assign(std::max(1, p->m[i]), 0);
+        bh[i].assign(std::max(1, p->m[i]), 0);
+        r[i] = mcs_result{};
+        r[i].map_g = bg[i].data();
+        r[i].map_h = bh[i].data();
+    }
+    double elapsed = 0.0;
+    int runs = 0;
+    bool limited = false;
+    for (int i = 0; i < n; i++)
+        done[i] = lo[i] >= hi[i];  // e.g. an empty graph: root bound 0
+    auto keep_map = [&](int i) {
+        mg[i].assign(bg[i].begin(), bg[i].begin() + r[i].size);
+        mh[i].assign(bh[i].begin(), bh[i].begin() + r[i].size);
+    };
+    auto launch = [&](void) -> mcs_status {
+        mcs_status s1 = mcs_plan_set_goals(p, goal.data(), stream);
+        if (s1 == MCS_OK)
+            s1 = mcs_plan_run(p, stream);
+        if (s1 == MCS_OK)
+            s1 = mcs_plan_results(p, r.data(), stream);
+        if (s1 < 0)
+            return s1;
+        runs++;
+        elapsed += p->last_ms / 1000.0;
+        for (int i = 0; i < n; i++)
+            if (goal[i] >= 0) {
+                nodes[i] += r[i].nodes;
+                if (r[i].size > p->inst[i].lb)
+                    tbest[i] = elapsed - p->last_ms / 1000.0 + r[i].t_best_s;
+            }
+        return MCS_OK;
+    };
+    if (strategy == 1) {
+        // first run: plain search under the node limit
+        for (int i = 0; i < n; i++)
+            goal[i] = 0;
+        st = launch();
+        if (st < 0)
+            return st;
+        for (int i = 0; i < n; i++) {
+            lo[i] = r[i].size;
+            keep_map(i);
+            if (r[i].optimal)
+                hi[i] = lo[i];  // the plain run finished: lo is the optimum
+            if (lo[i] >= hi[i]) {
+                done[i] = 1;
+                tproof[i] = elapsed;
+            }
+        }
+        p->sp.node_limit = 0;
+    }
+    for (;;) {
+        bool any = false;
+        for (int i = 0; i < n; i++) {
+            if (done[i]) {
+                goal[i] = -1;
+                continue;
+            }
+            any = true;
+            goal[i] = strategy == 0 ? hi[i] : (lo[i] + 1 + hi[i] + 1) / 2;
+            if (goal[i] <= lo[i])
+                goal[i] = lo[i] + 1;
+        }
+        if (!any)
+            break;
+        if (elapsed >= o1.time_limit_s && o1.time_limit_s > 0) {
+            limited = true;
+            break;
+        }
+        st = launch();
+        if (st < 0)
+            return st;
+        for (int i = 0; i < n; i++) {
+            if (goal[i] < 0)
+                continue;
+            if (r[i].size >= goal[i]) {  // reached: a mapping of at least goal
+                lo[i] = r[i].size;
+                keep_map(i);
+            } else if (r[i].optimal) {  // refuted: nothing of size >= goal
+                hi[i] = goal[i] - 1;
+            } else {
+                limited = true;  // this launch hit the time limit
+                done[i] = 1;
+                continue;
+            }
+            if (strategy == 0 && lo[i] == goal[i])
+                hi[i] = lo[i];
+            if (lo[i] >= hi[i]) {
+                done[i] = 1;
+                tproof[i] = elapsed;
+            }
+        }
+    }
+    for (int i = 0; i < n; i++) {
+        mcs_result &o = results[i];
+        o.size = lo[i];
+        o.optimal = (lo[i] >= hi[i]) ? 1 : 0;
+        o.nodes = nodes[i];
+        o.t_best_s = tbest[i];
+        o.t_proof_s = o.optimal ? tproof[i] : 0.0;
+        for (int j = 0; j < lo[i]; j++) {
+            if (o.map_g)
+                o.map_g[j] = mg[i][j];
+            if (o.map_h)
+                o.map_h[j] = mh[i][j];
+        }
+    }
+    if (launches)
+        *launches = runs;
+    bool all = true;
+    for (int i = 0; i < n; i++)
+        all = all && results[i].optimal;
+    return (all && !limited) ? MCS_OK : MCS_LIMIT;
+}
 
 size_t mcs_workspace_size(int32_t count, const mcs_graph *G, const mcs_graph *H,
                           const mcs_opts *opts) {

@@ -12,6 +12,8 @@ struct DevInst {
     uint32_t cls_off;  // first root class in the root-class array
     uint32_t map_off;  // first mapping pair of this instance's per-size slots
     int32_t lb;        // initial incumbent size (0: none)
+    int32_t target;    // > 0: stop this instance once a mapping of this size is found
+    int32_t pad2;
 };
 
 // The node queue is sharded into one ring per XCD (workgroup i runs on XCD

@@ -191,7 +191,7 @@ struct Searcher {
     Cls<W> *scls;   // [cap_classes]
 
     uint8_t *sord;  // [policy levels][64]: partner order of policy-ordered frames
-    int inst, map_off, nG, nH;
+    int inst, map_off, nG, nH, target;
     // top frame, wave-uniform
     int t, base, K, d, v, sel, bound, flags, lsel, rsel;
     W rrem;
@@ -223,6 +223,7 @@ struct Searcher {
         inst = -1;
         map_off = 0;
         nG = nH = 1;
+        target = 0;
         stop = false;
         roots_left = true;
         my_ring = (int)(blockIdx.x & (kRings - 1));
@@ -428,11 +429,12 @@ struct Searcher {
             map_off = (int)P.inst[i].map_off;
             nG = (int)P.inst[i].nG;
             nH = (int)P.inst[i].nH;
+            target = (int)P.inst[i].target;
         }
         int g = 0;
         if (lane == 0)
             g = ld_rlx(&P.inc[i]);
-        inc = rl(g, 0);
+        inc = cap_inc(rl(g, 0));
         wave_sync();
     }
 
@@ -481,7 +483,17 @@ struct Searcher {
                 a_max64(&P.t_best[inst], ((unsigned long long)size << 48) |
                                              (now_ticks() & 0xFFFFFFFFFFFFull));
         }
-        inc = old > size ? old : size;
+        set_inc(old > size ? old : size);
+    }
+
+    // The local incumbent used for pruning.  Once a goal size is reached
+    // (goal-directed search), it jumps above every possible bound so that
+    // the rest of the instance's work prunes away at once.
+    __device__ int cap_inc(int x) const { return (target > 0 && x >= target) ? 255 : x; }
+    __device__ void set_inc(int x) {
+        x = cap_inc(x);
+        if (x > inc)
+            inc = x;
     }
 
     // -- one batch of sibling children -----------------------------------------
@@ -972,7 +984,7 @@ struct Searcher {
         }
         gi = rl(gi, 0);
         if (gi > inc)
-            inc = gi;
+            set_inc(gi);
         if (rl((uint32_t)(rl_ull(state, 0) >> 32), 0)) {
             stop = true;
             return;

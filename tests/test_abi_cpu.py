@@ -142,3 +142,20 @@ def test_mixed_batch_accepted(mcs_lib):
     p = _create(pairs)
     assert p.workspace_bytes > 0
     p.close()
+
+
+def test_root_bounds_host(mcs_lib):
+    """Eq. 1 at the root: min(nG, nH) unlabelled; sum over shared labels of
+    min(counts) labelled."""
+    from paper_1908_06418_amd import _Marshal
+    G = mi.er_graph(10, 0.3, 1)
+    H = mi.er_graph(7, 0.3, 2)
+    Gl = dict(G, label=[0, 0, 0, 1, 1, 2, 2, 2, 2, 3])
+    Hl = dict(H, label=[0, 1, 1, 1, 2, 5, 5])
+    m = _Marshal([(G, H), (Gl, Hl), (mi.empty_graph(0), H)])
+    h = ctypes.c_void_p()
+    assert mcs_lib.mcs_plan_create(3, m.G, m.H, None, ctypes.byref(h)) == 0
+    out = (ctypes.c_int32 * 3)()
+    assert mcs_lib.mcs_plan_root_bounds(h, out) == 0
+    assert list(out) == [7, 1 + 2 + 1, 0]
+    mcs_lib.mcs_plan_destroy(h)
