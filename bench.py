@@ -149,7 +149,12 @@ def main():
     desc, factory, exp_file = workloads()[args.workload]
     pairs = factory()
     exp = expected_sizes(exp_file)
-    tuning = json.loads(args.tuning) if args.tuning else None
+    if args.tuning:
+        tuning, tuning_src = json.loads(args.tuning), "command line"
+    else:
+        from paper_1908_06418_amd import autotune
+        tuning = autotune.tuned(pairs)
+        tuning_src = "autotuner table" if tuning else "library defaults"
     plan = Plan(pairs, time_limit_s=args.time_limit, tuning=tuning).upload()
 
     def step():
@@ -203,7 +208,8 @@ def main():
         "dtype": "u64" if word == 8 else "u32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "pairs": len(pairs),
-                   "word_bits": 8 * word, "directed": directed},
+                   "word_bits": 8 * word, "directed": directed,
+                   "tuning": tuning, "tuning_source": tuning_src},
         "instances_per_s": len(pairs) * K / elapsed,
         "exact": exact,
         "proven_per_step": proven / K,

@@ -106,9 +106,17 @@ def tune(pairs, candidates=None, time_limit_s: float = 30.0, reps: int = 1, log=
     return best
 
 
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_table.json")
+
+
 def tuned(pairs, path: str | None = None) -> dict | None:
-    """Cached tuning for this workload class, or None (library defaults)."""
-    entry = load_cache(path).get(workload_key(pairs))
+    """Tuning for this workload class: the user's cache first, then the table
+    shipped with the package (measured with tune_and_store on an MI355X),
+    else None (library defaults)."""
+    key = workload_key(pairs)
+    entry = load_cache(path).get(key)
+    if entry is None and path is None:
+        entry = load_cache(SHIPPED).get(key)
     return dict(entry["tuning"]) if entry else None
 
 

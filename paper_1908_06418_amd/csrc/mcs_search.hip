@@ -530,11 +530,13 @@ struct Searcher {
                 }
             }
         }
-        int myw = 0;
+        // this lane's partner: segment seg takes wl[seg] (the scalar guard
+        // skips the selects a small batch does not need)
+        int myw = wl[0];
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (seg == c)
-                myw = wl[c];
+        for (int c = 1; c < 8; ++c)
+            if (c < C)
+                myw = seg == c ? wl[c] : myw;
         const bool act = seg < C;
         const W vb = (W)1 << v;
         const W Lx = cL & ~vb;
