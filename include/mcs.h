@@ -68,19 +68,20 @@ typedef struct {
  * defaults the library derives from the instance sizes. */
 typedef struct {
     int32_t waves_per_cu;      /* resident search wavefronts per CU (0: about
-                                  16 per instance, between 1 and 8 per CU;
+                                  64 per instance, between 1 and 16 per CU;
                                   capped by what LDS and registers allow) */
     int32_t children_per_wave; /* how many sibling children one wavefront may
                                   evaluate at once (1, 2, 4 or 8; 0: 8) */
     int32_t ring_slots;        /* total capacity of the device node queue, split
                                   over 8 per-XCD rings (0: auto) */
-    int32_t donate_low;        /* a busy wavefront donates its shallowest open
-                                  node when fewer nodes than this wait and some
-                                  wavefront is idle (0: auto; < 0: never) */
+    int32_t donate_low;        /* records each XCD's queue ring is kept stocked
+                                  with: a busy wavefront whose periodic check
+                                  finds fewer waiting donates its shallowest
+                                  open node (0: 2; < 0: never donate) */
     int32_t donate_depth;      /* only nodes with |M| <= this are donated, as the
                                   paper delegates only above PART_LEVEL
                                   (0: a third of the largest min(nG, nH)) */
-    int32_t check_interval;    /* search steps between queue/limit checks (0: 64) */
+    int32_t check_interval;    /* search steps between queue/limit checks (0: 128) */
     int32_t no_reprune;        /* 1: do not re-test a frame's bound against the
                                   incumbent when the search returns to it */
     int32_t single_wave;       /* 1: whole search on one wavefront, in the
@@ -133,6 +134,9 @@ typedef struct {
     int32_t lds_per_wave;      /* bytes of LDS per wavefront */
     int32_t stopped;           /* 1 if a limit stopped the search */
     double kernel_ms;          /* search kernel time of the last run */
+    double busy_wave_s;        /* wavefront-seconds spent searching; the rest
+                                  of waves x kernel time went to looking for
+                                  work (load imbalance and queue latency) */
 } mcs_stats;
 
 typedef struct mcs_plan mcs_plan;

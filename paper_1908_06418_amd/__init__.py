@@ -127,7 +127,14 @@ class Stats:
     lds_per_wave: int = 0
     stopped: int = 0
     kernel_ms: float = 0.0
+    busy_wave_s: float = 0.0
     extra: dict = field(default_factory=dict)
+
+    @property
+    def busy_frac(self) -> float:
+        """Share of the launch's wavefront-time spent searching."""
+        span = self.waves * self.kernel_ms * 1e-3
+        return self.busy_wave_s / span if span > 0 else 0.0
 
 
 class Plan:
@@ -206,7 +213,8 @@ class Plan:
             raise McsError(st, _last_error())
         return Stats(int(s.nodes), int(s.batches), int(s.children), int(s.lane_slots),
                      int(s.donations), int(s.pops), int(s.waves), int(s.blocks),
-                     int(s.lds_per_wave), int(s.stopped), float(s.kernel_ms))
+                     int(s.lds_per_wave), int(s.stopped), float(s.kernel_ms),
+                     float(s.busy_wave_s))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -52,7 +52,7 @@ class mcs_stats(ctypes.Structure):
                 ("donations", ctypes.c_int64), ("pops", ctypes.c_int64),
                 ("waves", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("lds_per_wave", ctypes.c_int32), ("stopped", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("busy_wave_s", ctypes.c_double)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/mcs.h

@@ -3,7 +3,8 @@
 The knobs (mcs_tuning in include/mcs.h) change only speed, never answers:
 resident wavefronts per CU, how many sibling children a wavefront evaluates at
 once, which nodes may be donated to the shared queue (the paper's PART_LEVEL
-idea), how often a busy wavefront looks at the queue, and the queue capacity.
+idea), how often a busy wavefront looks at the queue, how many records each
+XCD's queue ring is kept stocked with, and the queue capacity.
 The tuner times candidate settings on a sample of the workload through the C
 ABI, rejects any setting whose sizes differ from the others (they must agree:
 the search is exact), and caches the fastest per workload class in a JSON
@@ -17,11 +18,10 @@ import os
 import time
 
 DEFAULT_CANDIDATES = [
-    {"waves_per_cu": w, "children_per_wave": c, "donate_depth": dd, "check_interval": ci}
-    for w in (4, 8, 16)
-    for c in (4, 8)
-    for dd in (0, 6)
-    for ci in (16, 64)
+    {"waves_per_cu": w, "children_per_wave": 8, "check_interval": ci, "donate_low": lo}
+    for w in (8, 12, 16, 24)
+    for ci in (128, 256)
+    for lo in (1, 2)
 ]
 
 

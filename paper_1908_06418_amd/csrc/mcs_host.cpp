@@ -404,18 +404,18 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         (void)hipGetLastError();
         per_cu = 1;
     }
-    // Default: about 16 wavefronts per instance, between one per CU and two
-    // per SIMD.  One wavefront's search is a long dependent chain, so a
-    // second one per SIMD adds throughput when there is work for it; but
-    // wavefronts beyond what the instances can keep busy only split the work
-    // into ever smaller donations.
+    // Default: about 64 wavefronts per instance, between one and sixteen
+    // per CU.  One wavefront's search is a long dependent chain of scalar
+    // and vector steps, so several per SIMD fill the issue slots while
+    // there is work for them; past what the instances can keep busy, more
+    // wavefronts only split the work into ever smaller donations.
     p->blocks = per_cu * cus;
     if (p->tun.single_wave) {
         p->blocks = 1;
     } else {
         int want = p->tun.waves_per_cu > 0
                        ? p->tun.waves_per_cu * cus
-                       : std::max(cus, std::min(8 * cus, 16 * count));
+                       : std::max(cus, std::min(16 * cus, 64 * count));
         p->blocks = std::max(1, std::min(p->blocks, (want + wpb - 1) / wpb));
     }
     p->waves = p->blocks * wpb;
@@ -497,10 +497,10 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     int cm = p->tun.children_per_wave;
     sp.cmax = (cm == 1 || cm == 2 || cm == 4 || cm == 8) ? cm : 8;
     sp.donate_low = p->tun.donate_low > 0 ? p->tun.donate_low
-                                          : (p->tun.donate_low < 0 ? -1 : p->waves);
+                                          : (p->tun.donate_low < 0 ? -1 : 2);
     sp.donate_depth = p->tun.donate_depth > 0 ? p->tun.donate_depth
                                               : std::max(1, p->mmax / 3);
-    sp.check_interval = p->tun.check_interval > 0 ? p->tun.check_interval : 64;
+    sp.check_interval = p->tun.check_interval > 0 ? p->tun.check_interval : 128;
     sp.reprune = p->tun.no_reprune ? 0 : 1;
     sp.single_wave = p->tun.single_wave ? 1 : 0;
     sp.policy = p->policy;
@@ -684,6 +684,7 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     z.lds_per_wave = p->lds_per_wave;
     z.stopped = p->h_glob.stop ? 1 : 0;
     z.kernel_ms = p->last_ms;
+    z.busy_wave_s = (double)p->h_glob.busy_ticks / p->tick_hz;
     *st = z;
     return MCS_OK;
 }

@@ -28,20 +28,28 @@ struct RingCtl {
     uint8_t pad_tail[120];
 };
 
-// Counters shared by every wavefront of a launch.  The ones every wavefront
-// polls or updates each sit on a cache line of their own.
+// Flags a wavefront polls, one copy per XCD on a line of its own: they are
+// written once per launch (by the wavefront that stops or ends the search,
+// into every copy), so polling them never contends with counter updates.
+constexpr unsigned kFlagStop = 1;  // a limit was hit or a capacity check fired
+constexpr unsigned kFlagDone = 2;  // no work unit is left
+
+struct XcdCtl {
+    unsigned flag;
+    uint8_t pad[124];
+};
+
+// Counters shared by every wavefront of a launch.  The ones wavefronts
+// update each sit on a cache line of their own.
 struct DevGlobals {
     RingCtl ring[kRings];
-    // open_total and stop share one 8-byte word, so an idle wavefront reads
-    // both with one load
+    XcdCtl xcd[kRings];
     int open_total;                 // work units alive: instances not yet claimed,
                                     // queued nodes and busy wavefronts
-    unsigned stop;                  // 1: a limit was hit, every wavefront leaves
+    unsigned stop;                  // 1: a limit was hit (reported to the host)
     uint8_t pad_state[120];
     unsigned next_inst;             // next instance whose root is not yet taken
     uint8_t pad_next[124];
-    int idle;                       // wavefronts currently looking for work
-    uint8_t pad_idle[124];
     unsigned long long t0;          // earliest wavefront start (realtime ticks)
     unsigned long long node_total;  // nodes flushed so far (for the node limit)
     unsigned error;                 // nonzero: a capacity check fired
@@ -51,6 +59,7 @@ struct DevGlobals {
     unsigned long long lane_slots;
     unsigned long long donations;
     unsigned long long pops;
+    unsigned long long busy_ticks;  // realtime ticks wavefronts spent searching
 };
 
 struct SearchParams {
@@ -72,7 +81,7 @@ struct SearchParams {
     int cap_classes;      // LDS class capacity of one wavefront's stack
     int lds_per_wave;     // bytes
     int cmax;             // children per batch (1, 2, 4, 8)
-    int donate_low;       // < 0: never donate
+    int donate_low;       // records a busy wavefront keeps queued in its XCD's ring (< 0: never donate)
     int donate_depth;     // only frames with |M| <= this are donated
     int check_interval;
     int reprune;

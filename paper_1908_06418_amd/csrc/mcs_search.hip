@@ -21,18 +21,21 @@
 //     the current path; the "v unmatched" child rewrites its parent frame in
 //     place, so the stack never needs more than m(m+1)/2 classes
 //     (m = min(|V_G|, |V_H|)).
-//   * Work sharing: a bounded lock-free ring of node records in HBM (Vyukov
-//     sequence numbers).  A busy wave donates the shallowest frame that still
-//     has unexplored children (as the paper's thread pool hands out shallow
-//     tasks first) when few records wait; idle waves take records or new
+//   * Work sharing: bounded lock-free rings of node records in HBM (Vyukov
+//     sequence numbers), one per XCD.  A busy wave keeps its XCD's ring
+//     stocked: when its periodic check finds fewer than a few records
+//     waiting, it donates the shallowest frame that still has unexplored
+//     children (as the paper's thread pool hands out shallow tasks first).
+//     Idle waves take records (their own ring first, then steal) or new
 //     instance roots.  The paper's shared loop index becomes the donated
 //     frame's remaining-children mask.
 //   * Incumbents: one int per instance, atomicMax at agent scope; the mapping
 //     of size s is written to a per-size slot by the unique wave that raised
 //     the incumbent to s.
 //   * Termination: a count of live work units (queued records plus busy
-//     waves), per instance and in total; every wave also leaves at the time
-//     limit, so the grid always drains.
+//     waves), per instance and in total; the wave that ends the last unit
+//     raises a done flag (one copy per XCD, so polling it is cheap); every
+//     wave also leaves at the time limit, so the grid always drains.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -124,6 +127,39 @@ DEV int wave_sum(int x) {
     return rl(s, 0) + rl(s, 16) + rl(s, 32) + rl(s, 48);
 }
 DEV uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// Segmented reductions over segments of 2^logS lanes.  The result is valid
+// in the last lane of each segment (lane (c << logS) + 2^logS - 1); for
+// logS <= 4 every lane of a segment holds it.  row_bcast:15 (0x142) adds
+// lane 15 of each row into the next row (rows 1 and 3 enabled), and
+// row_bcast:31 (0x143) adds lane 31 into rows 2 and 3.
+DEV int seg_sum(int x, int logS) {
+    x = sum8(x);
+    if (logS >= 4)
+        x += dpp<0x140>(x);
+    if (logS >= 5)
+        x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);
+    if (logS >= 6)
+        x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);
+    return x;
+}
+template <int CTRL, int ROWS>
+DEV uint32_t dpp_min_id(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, CTRL, ROWS, 0xF, false);
+}
+// Minimum over the first segment (lanes 0 .. 2^logS - 1), as a scalar.
+DEV uint32_t seg0_min(uint32_t x, int logS) {
+    x = umin(x, (uint32_t)dpp<0xB1>((int)x));
+    x = umin(x, (uint32_t)dpp<0x4E>((int)x));
+    x = umin(x, (uint32_t)dpp<0x141>((int)x));
+    if (logS >= 4)
+        x = umin(x, (uint32_t)dpp<0x140>((int)x));
+    if (logS >= 5)
+        x = umin(x, dpp_min_id<0x142, 0xA>(x));
+    if (logS >= 6)
+        x = umin(x, dpp_min_id<0x143, 0xC>(x));
+    return rl(x, (1 << logS) - 1);
+}
 DEV uint32_t wave_min(uint32_t x) {
     x = umin(x, (uint32_t)dpp<0xB1>((int)x));
     x = umin(x, (uint32_t)dpp<0x4E>((int)x));
@@ -166,8 +202,14 @@ template <typename T>
 DEV T ld_rlx(T *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 template <typename T>
 DEV void st_rel(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+DEV void st_rlx(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+// Ticket claims are relaxed: the data a ticket guards is ordered by the
+// slot's sequence number alone (see take_record and reserve).  At agent
+// scope an acquire or release costs a write-back or invalidation of the
+// XCD's whole L2, so the queue uses exactly one of each per record.
 DEV bool cas64(unsigned long long *p, unsigned long long expect, unsigned long long want) {
-    return __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_ACQ_REL,
+    return __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_RELAXED,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -205,7 +247,7 @@ struct Searcher {
     int steal_from;   // the other ring tried next when idle
     int d0;           // depth of the unit's first frame (the shallowest)
     int since_check;
-    unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops;
+    unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops, n_busy;
 
     __device__ Searcher(const SearchParams &p, uint8_t *lds) : P(p) {
         lane = lane_id();
@@ -230,16 +272,27 @@ struct Searcher {
         steal_from = my_ring;
         d0 = 0;
         since_check = 0;
-        pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = 0;
+        pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = n_busy = 0;
         inc = 0;
         t = -1;
     }
 
-    __device__ void fail() {
+    // Sets flag bits in every XCD's copy; a stop is also recorded in the
+    // word the host reads back.  Safe to call from lane 0 alone.
+    __device__ void raise_flag(unsigned bits) {
         if (lane == 0) {
-            __hip_atomic_store(&P.g->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (bits & kFlagStop)
+                __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 0; k < kRings; ++k)
+                __hip_atomic_fetch_or(&P.g->xcd[k].flag, bits, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
         }
+    }
+
+    __device__ void fail() {
+        if (lane == 0)
+            __hip_atomic_store(&P.g->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        raise_flag(kFlagStop);
         stop = true;
     }
 
@@ -265,7 +318,7 @@ struct Searcher {
             int nl = popc(cL), nr = popc(cR);
             key = ((uint32_t)(nl > nr ? nl : nr) << 8) | (uint32_t)ctz(cL);
         }
-        uint32_t mk = wave_min(key);
+        uint32_t mk = seg0_min(key, logS);
         int who = ctz((uint64_t)ballot(key == mk));
         sel = who;
         v = (int)(mk & 0xFF);
@@ -506,38 +559,43 @@ struct Searcher {
         if (C > (64 >> logS))
             C = 64 >> logS;
         const int seg = lane >> logS;
+        const bool act = seg < C;
+        // partners in the policy's order (policy kernels only)
+        const bool ordered = POL && (flags & kFlagOrdered);
 
-        // the next C partners w: lowest indices first, or the policy's order
+        // this lane's partner w: segment seg takes the seg-th of the next C
+        // partners (lowest indices first, or the policy's order)
+        int myw = 0;
         int wl[8];
-        {
+        if (ordered) {
             W rr = rrem;
             int pos = 0;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 wl[c] = 0;
                 if (c < C) {
-                    int wc;
-                    if (POL && (flags & kFlagOrdered)) {
-                        while (pos < 63 && !((rr >> sord[t * 64 + pos]) & 1))
-                            ++pos;
-                        wc = sc((int)sord[t * 64 + pos]);
+                    while (pos < 63 && !((rr >> sord[t * 64 + pos]) & 1))
                         ++pos;
-                    } else {
-                        wc = ctz(rr);
-                    }
+                    int wc = sc((int)sord[t * 64 + pos]);
+                    ++pos;
                     rr &= ~((W)1 << wc);
                     wl[c] = wc;
                 }
             }
-        }
-        // this lane's partner: segment seg takes wl[seg] (the scalar guard
-        // skips the selects a small batch does not need)
-        int myw = wl[0];
+            myw = wl[0];
 #pragma unroll
-        for (int c = 1; c < 8; ++c)
-            if (c < C)
-                myw = seg == c ? wl[c] : myw;
-        const bool act = seg < C;
+            for (int c = 1; c < 8; ++c)
+                if (c < C)
+                    myw = seg == c ? wl[c] : myw;
+        } else {
+            // drop the seg lowest vertices of rrem, then take the lowest
+            W x = rrem;
+            for (int i = 1; i < C; ++i) {
+                W y = x & (x - 1);
+                x = seg >= i ? y : x;
+            }
+            myw = act ? ctz(x) : 0;
+        }
         const W vb = (W)1 << v;
         const W Lx = cL & ~vb;
         const W Rx = cR & ~((W)1 << myw);
@@ -570,47 +628,42 @@ struct Searcher {
         if (!act)
             contrib = 0;
 
-        // Eq. 1 per segment
-        uint32_t surv = 0;
-        int first = -1, fb = 0;
-        if (logS == 6) {
-            int b = d + 1 + wave_sum(contrib);
-            if (b > inc) {
-                surv = 1;
-                first = 0;
-                fb = b;
-            }
-        } else {
-            int s = logS == 3 ? sum8(contrib) : sum16(contrib);
-            for (int c = 0; c < C; ++c) {
-                int sum = logS == 5 ? rl(s, c << 5) + rl(s, (c << 5) + 16) : rl(s, c << logS);
-                int b = d + 1 + sum;
-                if (b > inc) {
-                    surv |= 1u << c;
-                    if (first < 0) {
-                        first = c;
-                        fb = b;
-                    }
-                }
-            }
-        }
-        int nsurv = __builtin_popcount(surv);
+        // Eq. 1 per segment, decided in each segment's last lane
+        const int b = d + 1 + seg_sum(contrib, logS);
+        const bool rep = (lane & (S - 1)) == S - 1;
+        const uint64_t sb = ballot(act && rep && b > inc);
+        const int nsurv = __builtin_popcountll(sb);
+        const int first = sb ? (ctz(sb) >> logS) : -1;
+        const int fb = sb ? rl(b, ctz(sb)) : 0;
         pend_nodes += (unsigned long long)(C - nsurv + (nsurv ? 1 : 0));
         n_batches += 1;
         n_children += (unsigned long long)C;
         n_lanes += (unsigned long long)(C * K);
 
-        // drop pruned children and the one we descend into
+        // drop the pruned children and the one we descend into; the other
+        // survivors stay in rrem and are evaluated again after the descent
         int wF = 0;
+        if (ordered) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (c < C) {
-                bool keep = ((surv >> c) & 1u) && c != first;
-                if (!keep)
-                    rrem &= ~((W)1 << wl[c]);
-                if (c == first)
-                    wF = wl[c];
+            for (int c = 0; c < 8; ++c) {
+                if (c < C) {
+                    bool keep = ((sb >> (((c << logS) + S - 1) & 63)) & 1) && c != first;
+                    if (!keep)
+                        rrem &= ~((W)1 << wl[c]);
+                    if (c == first)
+                        wF = wl[c];
+                }
             }
+        } else {
+            // lane j stands for vertex j; the child of rank r took the r-th
+            // lowest vertex of rrem
+            const bool inR = lane < NB && ((rrem >> (lane & (NB - 1))) & 1);
+            const int r = mbcnt((uint64_t)rrem);
+            const bool taken = inR && r < C;
+            const bool surv = taken && ((sb >> (((r << logS) + S - 1) & 63)) & 1);
+            rrem &= ~(W)ballot(taken && (!surv || r == first));
+            if (first >= 0)
+                wF = ctz((uint64_t)ballot(taken && r == first));
         }
         if (first < 0)
             return;
@@ -740,8 +793,9 @@ struct Searcher {
                 }
             }
         }
-        // the slot's last reader has released it; order our writes after that
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // No acquire here: the slot's last reader had all its loads of the
+        // slot returned (s_waitcnt) before it stored the sequence number we
+        // read, so none of our writes below can reach them.
         ok = rl(ok, 0);
         ring = rl(rr, 0);
         ticket = rl_ull(tk, 0);
@@ -906,10 +960,14 @@ struct Searcher {
             mp = rmap[lane];
         if (lane < K)
             cc = rcls[lane];
-        // every lane's loads are done (waited on) before the slot is released
+        // every lane's loads of the slot have returned before the slot is
+        // handed back, so a relaxed store suffices: the producer's later
+        // writes cannot reach values already in registers (the signal fence
+        // keeps the compiler from moving the store above the loads)
         __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (lane == 0)
-            st_rel(&P.seq[idx], hd + (unsigned long long)P.ring_slots);
+            st_rlx(&P.seq[idx], hd + (unsigned long long)P.ring_slots);
         set_instance(ri);
         if (lane < d)
             smap[lane] = mp;
@@ -962,50 +1020,50 @@ struct Searcher {
             if (P.node_limit > 0) {
                 unsigned long long tot = a_add64(&P.g->node_total, pend_nodes) + pend_nodes;
                 if ((long long)tot > P.node_limit)
-                    __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    raise_flag(kFlagStop);
             }
         }
         pend_nodes = 0;
     }
 
-    // Periodic: refresh the incumbent, honour limits, feed the queue.
+    // Periodic: refresh the incumbent, honour limits, keep the queue
+    // stocked.  Every line read here is per instance or per XCD: a check
+    // never touches a line that all wavefronts of the chip update.
     __device__ void check() {
         since_check = 0;
         // the queue is read only when some frame of this unit may be donated
         const bool may_donate = !P.single_wave && P.donate_low >= 0 && d0 <= P.donate_depth;
-        unsigned long long hd = 0, tl = 0, state = 0;
-        int gi = 0, hungry = 0;
+        unsigned long long hd = 0, tl = 0;
+        int gi = 0;
+        unsigned fl = 0;
         if (lane == 0) {
             gi = ld_rlx(&P.inc[inst]);
-            state = ld_rlx((unsigned long long *)&P.g->open_total);
+            fl = ld_rlx(&P.g->xcd[my_ring].flag);
             if (may_donate) {
                 tl = ld_rlx(&P.g->ring[my_ring].tail);
                 hd = ld_rlx(&P.g->ring[my_ring].head);
-                hungry = ld_rlx(&P.g->idle);
             }
         }
         gi = rl(gi, 0);
         if (gi > inc)
             set_inc(gi);
-        if (rl((uint32_t)(rl_ull(state, 0) >> 32), 0)) {
+        // (the done flag cannot be up while this unit is alive: a set flag
+        // is a stop)
+        if (rl(fl, 0)) {
             stop = true;
             return;
         }
         if (now_ticks() - t_start > P.limit_ticks) {
-            if (lane == 0)
-                __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            raise_flag(kFlagStop);
             stop = true;
             return;
         }
         if (P.node_limit > 0)
             flush_nodes();
         if (may_donate) {
-            // donate while fewer nodes wait than wavefronts are hungry
+            // keep at least donate_low records waiting in this XCD's ring
             long long waiting = (long long)(rl_ull(tl, 0) - rl_ull(hd, 0));
-            long long want = rl(hungry, 0);
-            if (want > P.donate_low)
-                want = P.donate_low;
-            if (waiting < want)
+            if (waiting < P.donate_low)
                 donate();
         }
     }
@@ -1054,7 +1112,10 @@ struct Searcher {
             if (r == 1)
                 __hip_atomic_store(&P.t_proof[inst], now_ticks(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            a_add_rlx(&P.g->open_total, -1);
+            // a unit is only made by a live unit, so the count reaches zero
+            // once, when the last one ends: that wavefront says so to all
+            if (a_add_rlx(&P.g->open_total, -1) == 1)
+                raise_flag(kFlagDone);
         }
     }
 
@@ -1062,7 +1123,6 @@ struct Searcher {
         t_start = now_ticks();
         if (lane == 0)
             a_min64(&P.g->t0, t_start);
-        bool idle = false;
         int backoff = 0;
         for (;;) {
             bool got = false;
@@ -1071,30 +1131,22 @@ struct Searcher {
             if (!got)
                 got = claim_instance();
             if (got) {
-                if (idle && lane == 0)
-                    a_add_rlx(&P.g->idle, -1);
-                idle = false;
                 backoff = 0;
+                const unsigned long long t_unit = now_ticks();
                 run();
                 finish_unit();
+                n_busy += now_ticks() - t_unit;
                 if (stop)
                     break;
                 continue;
             }
-            if (!idle && lane == 0)
-                a_add_rlx(&P.g->idle, 1);
-            idle = true;
-            unsigned long long state = 0;
+            unsigned fl = 0;
             if (lane == 0)
-                state = ld_rlx((unsigned long long *)&P.g->open_total);
-            state = rl_ull(state, 0);
-            const int ot = (int)(uint32_t)state;
-            const unsigned st = (unsigned)(state >> 32);
-            if (st || ot == 0)
-                break;
+                fl = ld_rlx(&P.g->xcd[my_ring].flag);
+            if (rl(fl, 0))
+                break;  // stopped, or no work is left anywhere
             if (now_ticks() - t_start > P.limit_ticks) {
-                if (lane == 0)
-                    __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                raise_flag(kFlagStop);
                 break;
             }
             // back off: 1, 2, 4, ... 32 sleeps of about 8k cycles (3.4 us)
@@ -1102,14 +1154,13 @@ struct Searcher {
             for (int i = 0; i < backoff; ++i)
                 __builtin_amdgcn_s_sleep(127);
         }
-        if (idle && lane == 0)
-            a_add_rlx(&P.g->idle, -1);
         if (lane == 0) {
             a_add64(&P.g->batches, n_batches);
             a_add64(&P.g->children, n_children);
             a_add64(&P.g->lane_slots, n_lanes);
             a_add64(&P.g->donations, n_don);
             a_add64(&P.g->pops, n_pops);
+            a_add64(&P.g->busy_ticks, n_busy);
         }
     }
 };
@@ -1149,6 +1200,9 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
         DevGlobals z = {};
         z.t0 = ~0ull;
         z.open_total = R.count;
+        if (R.count == 0)
+            for (int k = 0; k < kRings; ++k)
+                z.xcd[k].flag = kFlagDone;
         *R.g = z;
     }
 }
