@@ -107,6 +107,9 @@ struct ResetParams {
     int ring_slots;
 };
 
+// Words of one frame header in LDS (one 32-bit word per field, padded).
+constexpr int kHdrWords = 12;
+
 // Record of a donated node in the queue: a 32-byte header, the mapping
 // (NB pairs of bytes) and the classes.
 constexpr int kRecHeader = 32;
@@ -124,7 +127,7 @@ constexpr int rec_cls_off() { return kRecHeader + 2 * bits_of<W>(); }
 //   classes   [cap_classes] (L, R) word pairs
 //   adjacency [R][NB] words
 //   mapping   [NB] byte pairs
-//   headers   [NB + 1] frame headers (24 bytes for 64-bit words, 16 for 32-bit)
+//   headers   [NB + 1][kHdrWords] frame headers, one 32-bit word per field
 //   orders    [policy levels][64] partner order of policy-ordered frames
 struct LdsLayout {
     int cls, adj, map, hdr, ord, total;
@@ -136,7 +139,7 @@ inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_clas
                                       int policy_levels = 0) {
     int nb = 8 * word_bytes;
     int rows = directed ? 4 : 2;
-    int hdr_bytes = word_bytes == 8 ? 24 : 16;
+    int hdr_bytes = 4 * kHdrWords;
     LdsLayout L{0, 0, 0, 0, 0, 0};
     L.cls = 0;
     L.adj = align16(cap_classes * 2 * word_bytes);

@@ -53,11 +53,21 @@ struct Cls {
     W L, R;
 };
 
-template <typename W>
-struct Hdr {
-    W rrem;         // children (w of the selected class) not yet taken
-    uint16_t base;  // first class of the frame in the LDS class stack
-    uint8_t K, d, v, sel, bound, flags, lsel, rsel;
+// A frame header in LDS: one 32-bit word per field, written from lane f of
+// one register (v_writelane, then a single masked LDS store) and read back
+// with one LDS load and v_readlane -- no byte packing on the scalar unit.
+enum HdrField {
+    kHRremLo = 0,  // children (w of the selected class) not yet taken
+    kHRremHi,
+    kHBase,        // first class of the frame in the LDS class stack
+    kHK,
+    kHD,
+    kHV,
+    kHSel,
+    kHBound,
+    kHFlags,
+    kHLsel,
+    kHRsel,
 };
 
 template <typename W>
@@ -68,7 +78,7 @@ struct RecHdr {
     W rrem;
 };
 
-static_assert(sizeof(Hdr<uint64_t>) == 24 && sizeof(Hdr<uint32_t>) == 16, "header layout");
+static_assert(kHRsel < kHdrWords, "header layout");
 static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>) <= kRecHeader,
               "record header layout");
 
@@ -229,7 +239,7 @@ struct Searcher {
     int lane;
     W *sadj;        // [NR][NB]: G rows, H rows (out), then G, H in-rows
     uint16_t *smap; // [NB] current path: g | h << 8
-    Hdr<W> *shdr;   // [NB + 1]
+    int *shdr;      // [NB + 1][kHdrWords]
     Cls<W> *scls;   // [cap_classes]
 
     uint8_t *sord;  // [policy levels][64]: partner order of policy-ordered frames
@@ -248,6 +258,9 @@ struct Searcher {
     int d0;           // depth of the unit's first frame (the shallowest)
     int since_check;
     unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops, n_busy;
+    // per-step counts since the last fold into the 64-bit totals (at most
+    // check_interval steps, so 32 bits cannot overflow)
+    uint32_t c_nodes, c_batches, c_children, c_lanes;
 
     __device__ Searcher(const SearchParams &p, uint8_t *lds) : P(p) {
         lane = lane_id();
@@ -260,7 +273,7 @@ struct Searcher {
         scls = (Cls<W> *)(lds + L.cls);
         sadj = (W *)(lds + L.adj);
         smap = (uint16_t *)(lds + L.map);
-        shdr = (Hdr<W> *)(lds + L.hdr);
+        shdr = (int *)(lds + L.hdr);
         sord = lds + L.ord;
         inst = -1;
         map_off = 0;
@@ -273,6 +286,7 @@ struct Searcher {
         d0 = 0;
         since_check = 0;
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = n_busy = 0;
+        c_nodes = c_batches = c_children = c_lanes = 0;
         inc = 0;
         t = -1;
     }
@@ -441,34 +455,58 @@ struct Searcher {
     }
 
     __device__ void save_top() {
-        if (lane == 0) {
-            Hdr<W> h;
-            h.rrem = rrem;
-            h.base = (uint16_t)base;
-            h.K = (uint8_t)K;
-            h.d = (uint8_t)d;
-            h.v = (uint8_t)v;
-            h.sel = (uint8_t)sel;
-            h.bound = (uint8_t)bound;
-            h.flags = (uint8_t)flags;
-            h.lsel = (uint8_t)lsel;
-            h.rsel = (uint8_t)rsel;
-            shdr[t] = h;
-        }
+        // lane f of x takes field f (one asm block: no hazard padding
+        // between the writes, which depend on nothing but their operands)
+        int x = 0;
+        const int lo = (int)(uint32_t)rrem;
+        const int hi = sizeof(W) == 8 ? (int)(uint32_t)((uint64_t)rrem >> 32) : 0;
+        static_assert(kHRremLo == 0 && kHRremHi == 1 && kHBase == 2 && kHK == 3 && kHD == 4 &&
+                          kHV == 5 && kHSel == 6 && kHBound == 7 && kHFlags == 8 &&
+                          kHLsel == 9 && kHRsel == 10,
+                      "header field order");
+        asm volatile(
+            "v_writelane_b32 %0, %1, 0\n\t"
+            "v_writelane_b32 %0, %2, 1\n\t"
+            "v_writelane_b32 %0, %3, 2\n\t"
+            "v_writelane_b32 %0, %4, 3\n\t"
+            "v_writelane_b32 %0, %5, 4\n\t"
+            "v_writelane_b32 %0, %6, 5\n\t"
+            "v_writelane_b32 %0, %7, 6\n\t"
+            "v_writelane_b32 %0, %8, 7\n\t"
+            "v_writelane_b32 %0, %9, 8\n\t"
+            "v_writelane_b32 %0, %10, 9\n\t"
+            "v_writelane_b32 %0, %11, 10"
+            : "+v"(x)
+            : "s"(lo), "s"(hi), "s"(base), "s"(K), "s"(d), "s"(v), "s"(sel), "s"(bound),
+              "s"(flags), "s"(lsel), "s"(rsel));
+        if (lane <= kHRsel)
+            shdr[t * kHdrWords + lane] = x;
+    }
+
+    // One field of frame i's header, as a scalar.
+    __device__ int hdr(int i, int f) const { return sc(shdr[i * kHdrWords + f]); }
+    __device__ W hdr_rrem(int i) const {
+        W r = (W)(uint32_t)hdr(i, kHRremLo);
+        if constexpr (sizeof(W) == 8)
+            r |= (W)(uint32_t)hdr(i, kHRremHi) << 32;
+        return r;
     }
 
     __device__ void read_hdr(int i) {
-        Hdr<W> h = shdr[i];
-        rrem = sc((W)h.rrem);
-        base = sc((int)h.base);
-        K = sc((int)h.K);
-        d = sc((int)h.d);
-        v = sc((int)h.v);
-        sel = sc((int)h.sel);
-        bound = sc((int)h.bound);
-        flags = sc((int)h.flags);
-        lsel = sc((int)h.lsel);
-        rsel = sc((int)h.rsel);
+        const int x = shdr[i * kHdrWords + (lane < kHdrWords ? lane : 0)];
+        W r = (W)(uint32_t)rl(x, kHRremLo);
+        if constexpr (sizeof(W) == 8)
+            r |= (W)(uint32_t)rl(x, kHRremHi) << 32;
+        rrem = r;
+        base = rl(x, kHBase);
+        K = rl(x, kHK);
+        d = rl(x, kHD);
+        v = rl(x, kHV);
+        sel = rl(x, kHSel);
+        bound = rl(x, kHBound);
+        flags = rl(x, kHFlags);
+        lsel = rl(x, kHLsel);
+        rsel = rl(x, kHRsel);
     }
 
     // -- instances -------------------------------------------------------------
@@ -511,7 +549,7 @@ struct Searcher {
             contrib = nl < nr ? nl : nr;
         }
         bound = wave_sum(contrib);
-        pend_nodes += 1;  // the root
+        c_nodes += 1;  // the root
         if (K == 0 || bound <= inc) {
             rrem = 0;
             flags = 0;
@@ -603,7 +641,7 @@ struct Searcher {
         // filterDomain: parts by adjacency letter
         W pl[NR], pr[NR];
         const W go = sadj[v], ho = sadj[NB + myw];
-        if (!DIR) {
+        if constexpr (!DIR) {
             pl[0] = Lx & ~go;
             pr[0] = Rx & ~ho;
             pl[1] = Lx & go;
@@ -635,10 +673,10 @@ struct Searcher {
         const int nsurv = __builtin_popcountll(sb);
         const int first = sb ? (ctz(sb) >> logS) : -1;
         const int fb = sb ? rl(b, ctz(sb)) : 0;
-        pend_nodes += (unsigned long long)(C - nsurv + (nsurv ? 1 : 0));
-        n_batches += 1;
-        n_children += (unsigned long long)C;
-        n_lanes += (unsigned long long)(C * K);
+        c_nodes += (uint32_t)(C - nsurv + (nsurv ? 1 : 0));
+        c_batches += 1;
+        c_children += (uint32_t)C;
+        c_lanes += (uint32_t)(C * K);
 
         // drop the pruned children and the one we descend into; the other
         // survivors stay in rrem and are evaluated again after the descent
@@ -717,7 +755,7 @@ struct Searcher {
     __device__ bool unmatched() {
         flags = 0;
         int ub = bound - (lsel <= rsel ? 1 : 0);
-        pend_nodes += 1;
+        c_nodes += 1;
         if (ub <= inc)
             return false;
         const W vb = (W)1 << v;
@@ -808,9 +846,9 @@ struct Searcher {
         W grr = 0;
         int gfl = 0;
         for (int i = 0; i < t; ++i) {
-            W r = sc((W)shdr[i].rrem);
-            int f = sc((int)shdr[i].flags);
-            if (sc((int)shdr[i].d) > P.donate_depth)
+            W r = hdr_rrem(i);
+            int f = hdr(i, kHFlags);
+            if (hdr(i, kHD) > P.donate_depth)
                 return;  // deeper frames hold too little work to hand out
             if (r != 0 || (f & kFlagUnmatched)) {
                 b = i;
@@ -861,15 +899,14 @@ struct Searcher {
             rh.lsel = (uint8_t)lsel;
             rh.rsel = (uint8_t)rsel;
         } else {
-            Hdr<W> h = shdr[b];
-            fK = sc((int)h.K);
-            fd = sc((int)h.d);
-            fbase = sc((int)h.base);
-            rh.v = h.v;
-            rh.sel = h.sel;
-            rh.bound = h.bound;
-            rh.lsel = h.lsel;
-            rh.rsel = h.rsel;
+            fK = hdr(b, kHK);
+            fd = hdr(b, kHD);
+            fbase = hdr(b, kHBase);
+            rh.v = (uint8_t)hdr(b, kHV);
+            rh.sel = (uint8_t)hdr(b, kHSel);
+            rh.bound = (uint8_t)hdr(b, kHBound);
+            rh.lsel = (uint8_t)hdr(b, kHLsel);
+            rh.rsel = (uint8_t)hdr(b, kHRsel);
         }
         rh.inst = (uint32_t)inst;
         rh.K = (uint8_t)fK;
@@ -894,8 +931,9 @@ struct Searcher {
             rrem = keep_r;
             flags &= kFlagOrdered;
         } else if (lane == 0) {
-            shdr[b].rrem = 0;
-            shdr[b].flags = 0;
+            shdr[b * kHdrWords + kHRremLo] = 0;
+            shdr[b * kHdrWords + kHRremHi] = 0;
+            shdr[b * kHdrWords + kHFlags] = 0;
         }
         wave_sync();
         n_don += 1;
@@ -1014,7 +1052,16 @@ struct Searcher {
         return true;
     }
 
+    __device__ void fold() {
+        pend_nodes += c_nodes;
+        n_batches += c_batches;
+        n_children += c_children;
+        n_lanes += c_lanes;
+        c_nodes = c_batches = c_children = c_lanes = 0;
+    }
+
     __device__ void flush_nodes() {
+        fold();
         if (pend_nodes && inst >= 0 && lane == 0) {
             a_add64(&P.nodes[inst], pend_nodes);
             if (P.node_limit > 0) {
@@ -1031,6 +1078,7 @@ struct Searcher {
     // never touches a line that all wavefronts of the chip update.
     __device__ void check() {
         since_check = 0;
+        fold();
         // the queue is read only when some frame of this unit may be donated
         const bool may_donate = !P.single_wave && P.donate_low >= 0 && d0 <= P.donate_depth;
         unsigned long long hd = 0, tl = 0;
@@ -1154,6 +1202,7 @@ struct Searcher {
             for (int i = 0; i < backoff; ++i)
                 __builtin_amdgcn_s_sleep(127);
         }
+        fold();
         if (lane == 0) {
             a_add64(&P.g->batches, n_batches);
             a_add64(&P.g->children, n_children);
