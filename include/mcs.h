@@ -68,7 +68,7 @@ typedef struct {
  * defaults the library derives from the instance sizes. */
 typedef struct {
     int32_t waves_per_cu;      /* resident search wavefronts per CU (0: about
-                                  64 per instance, between 1 and 16 per CU;
+                                  96 per instance, between 1 and 24 per CU;
                                   capped by what LDS and registers allow) */
     int32_t children_per_wave; /* how many sibling children one wavefront may
                                   evaluate at once (1, 2, 4 or 8; 0: 8) */
@@ -88,6 +88,12 @@ typedef struct {
                                   sequential order (debugging and node-count
                                   comparisons) */
     int32_t use_graph;         /* 1: mcs_plan_run replays a HIP graph */
+    int32_t stack_classes;     /* capacity of one wavefront's LDS class stack
+                                  (0: the worst case m(m+1)/2, m the largest
+                                  min(nG, nH), or less if that keeps
+                                  waves_per_cu from fitting in LDS; never
+                                  below 2m + 1).  A child that does not fit
+                                  goes to the node queue as a record. */
 } mcs_tuning;
 
 typedef struct {
@@ -137,6 +143,9 @@ typedef struct {
     double busy_wave_s;        /* wavefront-seconds spent searching; the rest
                                   of waves x kernel time went to looking for
                                   work (load imbalance and queue latency) */
+    int64_t spills;            /* children queued because the class stack was full */
+    int32_t stack_classes;     /* class-stack capacity per wavefront */
+    int32_t max_stack_used;    /* most classes any wavefront's stack held */
 } mcs_stats;
 
 typedef struct mcs_plan mcs_plan;

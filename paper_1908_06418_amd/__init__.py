@@ -46,11 +46,13 @@ class Tuning:
     no_reprune: int = 0
     single_wave: int = 0
     use_graph: int = 0
+    stack_classes: int = 0
 
     def to_c(self) -> _abi.mcs_tuning:
         return _abi.mcs_tuning(self.waves_per_cu, self.children_per_wave, self.ring_slots,
                                self.donate_low, self.donate_depth, self.check_interval,
-                               self.no_reprune, self.single_wave, self.use_graph)
+                               self.no_reprune, self.single_wave, self.use_graph,
+                               self.stack_classes)
 
 
 class _Marshal:
@@ -128,6 +130,9 @@ class Stats:
     stopped: int = 0
     kernel_ms: float = 0.0
     busy_wave_s: float = 0.0
+    spills: int = 0
+    stack_classes: int = 0
+    max_stack_used: int = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -214,7 +219,8 @@ class Plan:
         return Stats(int(s.nodes), int(s.batches), int(s.children), int(s.lane_slots),
                      int(s.donations), int(s.pops), int(s.waves), int(s.blocks),
                      int(s.lds_per_wave), int(s.stopped), float(s.kernel_ms),
-                     float(s.busy_wave_s))
+                     float(s.busy_wave_s), int(s.spills), int(s.stack_classes),
+                     int(s.max_stack_used))
 
     def close(self):
         if getattr(self, "handle", None):

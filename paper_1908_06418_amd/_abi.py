@@ -28,7 +28,8 @@ class mcs_tuning(ctypes.Structure):
                 ("ring_slots", ctypes.c_int32), ("donate_low", ctypes.c_int32),
                 ("donate_depth", ctypes.c_int32),
                 ("check_interval", ctypes.c_int32), ("no_reprune", ctypes.c_int32),
-                ("single_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("single_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("stack_classes", ctypes.c_int32)]
 
 
 class mcs_opts(ctypes.Structure):
@@ -52,7 +53,9 @@ class mcs_stats(ctypes.Structure):
                 ("donations", ctypes.c_int64), ("pops", ctypes.c_int64),
                 ("waves", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("lds_per_wave", ctypes.c_int32), ("stopped", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double), ("busy_wave_s", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("busy_wave_s", ctypes.c_double),
+                ("spills", ctypes.c_int64), ("stack_classes", ctypes.c_int32),
+                ("max_stack_used", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/mcs.h

@@ -146,7 +146,7 @@ struct mcs_plan {
     size_t off_inst = 0, off_adj = 0, off_cls = 0, off_inc = 0, off_open = 0, off_nodes = 0,
            off_tbest = 0, off_tproof = 0, off_maps = 0, off_glob = 0, off_seq = 0, off_slots = 0,
            ws_bytes = 0;
-    int ring_slots = 0, slot_bytes = 0, cap_classes = 0, lds_per_wave = 0;
+    int ring_slots = 0, slot_bytes = 0, cap_classes = 0, frames = 0, lds_per_wave = 0;
     int waves_per_block = 4, blocks = 0, waves = 0, lds_per_block = 0;
     double tick_hz = 1e8;
 
@@ -367,22 +367,54 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     if (p->rootcls.empty())
         pack_word(p->rootcls, p->word_bytes, 0), pack_word(p->rootcls, p->word_bytes, 0);
     p->map_pairs = std::max<size_t>(map_off, 1);
-    p->cap_classes = std::max(1, p->mmax * (p->mmax + 1) / 2);
+    // The worst case of the depth-first class stack: frame t holds at most
+    // m - t classes.  Smaller stacks queue the children that do not fit.
+    const int full_cap = std::max(1, p->mmax * (p->mmax + 1) / 2);
+    const int min_cap = std::min(full_cap, 2 * p->mmax + 1);
+    p->frames = p->mmax + 1;
 
     // launch shape
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         dev = 0;
-    int cus = 256, max_lds_block = 65536, clock_khz = 100000;
+    int cus = 256, max_lds_block = 65536, lds_cu = 163840, clock_khz = 100000;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipDeviceGetAttribute(&max_lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (lds_cu < max_lds_block)
+        lds_cu = max_lds_block;
     if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
         clock_khz <= 0)
         clock_khz = 100000;
     (void)hipGetLastError();
     p->tick_hz = (double)clock_khz * 1000.0;
-    p->lds_per_wave =
-        mcs::lds_layout(p->word_bytes, directed, p->cap_classes, p->policy_levels).total;
+    // Default: about 96 wavefronts per instance, between one and 24 per
+    // CU.  One wavefront's search is a long dependent chain of scalar
+    // and vector steps, so several per SIMD fill the issue slots while
+    // there is work for them; past what the instances can keep busy, more
+    // wavefronts only split the work into ever smaller donations.
+    const int want_waves = p->tun.waves_per_cu > 0
+                               ? p->tun.waves_per_cu * cus
+                               : std::max(cus, std::min(24 * cus, 96 * count));
+    const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
+    auto per_wave = [&](int cap) {
+        return mcs::lds_layout(p->word_bytes, directed, cap, p->frames, p->policy_levels).total;
+    };
+    if (p->tun.single_wave) {
+        p->cap_classes = full_cap;  // one wavefront never takes queued work back
+    } else if (p->tun.stack_classes > 0) {
+        p->cap_classes = std::max(min_cap, std::min(full_cap, p->tun.stack_classes));
+    } else {
+        // the whole worst case if target_wpc wavefronts still fit in a CU's
+        // LDS, else the largest stack that lets them
+        p->cap_classes = full_cap;
+        const int share = lds_cu / target_wpc - 64;  // 64: a wave's part of the static LDS
+        if (per_wave(full_cap) > share) {
+            const int room = share - per_wave(0) - 16;
+            p->cap_classes = std::max(min_cap, std::min(full_cap, room / (2 * p->word_bytes)));
+        }
+    }
+    p->lds_per_wave = per_wave(p->cap_classes);
     int wpb = 4;
     max_lds_block -= 256;  // the kernel's static LDS (its parameter copy)
     while (wpb > 1 && wpb * p->lds_per_wave > max_lds_block)
@@ -404,20 +436,11 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         (void)hipGetLastError();
         per_cu = 1;
     }
-    // Default: about 64 wavefronts per instance, between one and sixteen
-    // per CU.  One wavefront's search is a long dependent chain of scalar
-    // and vector steps, so several per SIMD fill the issue slots while
-    // there is work for them; past what the instances can keep busy, more
-    // wavefronts only split the work into ever smaller donations.
     p->blocks = per_cu * cus;
-    if (p->tun.single_wave) {
+    if (p->tun.single_wave)
         p->blocks = 1;
-    } else {
-        int want = p->tun.waves_per_cu > 0
-                       ? p->tun.waves_per_cu * cus
-                       : std::max(cus, std::min(16 * cus, 64 * count));
-        p->blocks = std::max(1, std::min(p->blocks, (want + wpb - 1) / wpb));
-    }
+    else
+        p->blocks = std::max(1, std::min(p->blocks, (want_waves + wpb - 1) / wpb));
     p->waves = p->blocks * wpb;
 
     {
@@ -493,6 +516,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.ring_slots = p->ring_slots;
     sp.slot_bytes = p->slot_bytes;
     sp.cap_classes = p->cap_classes;
+    sp.frames = p->frames;
     sp.lds_per_wave = p->lds_per_wave;
     int cm = p->tun.children_per_wave;
     sp.cmax = (cm == 1 || cm == 2 || cm == 4 || cm == 8) ? cm : 8;
@@ -686,6 +710,9 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     z.stopped = p->h_glob.stop ? 1 : 0;
     z.kernel_ms = p->last_ms;
     z.busy_wave_s = (double)p->h_glob.busy_ticks / p->tick_hz;
+    z.spills = (int64_t)p->h_glob.spills;
+    z.stack_classes = p->cap_classes;
+    z.max_stack_used = p->h_glob.max_stack;
     *st = z;
     return MCS_OK;
 }

@@ -60,6 +60,9 @@ struct DevGlobals {
     unsigned long long donations;
     unsigned long long pops;
     unsigned long long busy_ticks;  // realtime ticks wavefronts spent searching
+    unsigned long long spills;      // children queued for want of stack room
+    int max_stack;                  // most classes any wavefront's stack held
+    int pad1;
 };
 
 struct SearchParams {
@@ -79,6 +82,7 @@ struct SearchParams {
     int ring_slots;               // slots per ring (a power of two)
     int slot_bytes;
     int cap_classes;      // LDS class capacity of one wavefront's stack
+    int frames;           // frame headers per wavefront (largest min(nG, nH) + 1)
     int lds_per_wave;     // bytes
     int cmax;             // children per batch (1, 2, 4, 8)
     int donate_low;       // records a busy wavefront keeps queued in its XCD's ring (< 0: never donate)
@@ -127,7 +131,7 @@ constexpr int rec_cls_off() { return kRecHeader + 2 * bits_of<W>(); }
 //   classes   [cap_classes] (L, R) word pairs
 //   adjacency [R][NB] words
 //   mapping   [NB] byte pairs
-//   headers   [NB + 1][kHdrWords] frame headers, one 32-bit word per field
+//   headers   [frames][kHdrWords] frame headers, one 32-bit word per field
 //   orders    [policy levels][64] partner order of policy-ordered frames
 struct LdsLayout {
     int cls, adj, map, hdr, ord, total;
@@ -136,7 +140,7 @@ struct LdsLayout {
 inline constexpr int align16(int x) { return (x + 15) & ~15; }
 
 inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_classes,
-                                      int policy_levels = 0) {
+                                      int frames, int policy_levels = 0) {
     int nb = 8 * word_bytes;
     int rows = directed ? 4 : 2;
     int hdr_bytes = 4 * kHdrWords;
@@ -145,7 +149,7 @@ inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_clas
     L.adj = align16(cap_classes * 2 * word_bytes);
     L.map = align16(L.adj + rows * nb * word_bytes);
     L.hdr = align16(L.map + 2 * nb);
-    L.ord = align16(L.hdr + (nb + 1) * hdr_bytes);
+    L.ord = align16(L.hdr + frames * hdr_bytes);
     L.total = align16(L.ord + policy_levels * 64);
     return L;
 }

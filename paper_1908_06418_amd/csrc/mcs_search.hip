@@ -84,6 +84,7 @@ static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>)
 
 constexpr int kFlagUnmatched = 1;  // the "v unmatched" child is still to do
 constexpr int kFlagOrdered = 2;    // partners are tried in the policy's order
+constexpr int kFlagFresh = 4;      // (records only) a child whose class and v are not chosen yet
 
 // ---- bit helpers -----------------------------------------------------------
 
@@ -258,6 +259,8 @@ struct Searcher {
     int d0;           // depth of the unit's first frame (the shallowest)
     int since_check;
     unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops, n_busy;
+    unsigned long long n_spill;
+    int max_used;  // most classes this wavefront's stack has held
     // per-step counts since the last fold into the 64-bit totals (at most
     // check_interval steps, so 32 bits cannot overflow)
     uint32_t c_nodes, c_batches, c_children, c_lanes;
@@ -268,7 +271,7 @@ struct Searcher {
         cap_classes = sc(p.cap_classes);
         check_interval = sc(p.check_interval);
         reprune = sc(p.reprune);
-        const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes,
+        const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes, p.frames,
                                        p.policy_levels);
         scls = (Cls<W> *)(lds + L.cls);
         sadj = (W *)(lds + L.adj);
@@ -287,6 +290,8 @@ struct Searcher {
         since_check = 0;
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = n_busy = 0;
         c_nodes = c_batches = c_children = c_lanes = 0;
+        n_spill = 0;
+        max_used = 0;
         inc = 0;
         t = -1;
     }
@@ -720,9 +725,19 @@ struct Searcher {
         }
         const int nb = base + K;
         if (nb + K2 > cap_classes) {
-            fail();
+            // no room on this wavefront's stack: the child goes to the queue
+            // as a record (its mapping may still raise the incumbent)
+            if (lane == 0)
+                smap[d] = (uint16_t)(v | (wF << 8));
+            wave_sync();
+            if (d + 1 > inc)
+                improve(d + 1);
+            if (P.single_wave || !spill_child(fb, K2, ne, pos, pl, pr))
+                fail();
             return;
         }
+        if (nb + K2 > max_used)
+            max_used = nb + K2;
 #pragma unroll
         for (int a = 0; a < NR; ++a)
             if (ne[a]) {
@@ -939,6 +954,53 @@ struct Searcher {
         n_don += 1;
     }
 
+    // Queue the child whose classes segment `first` holds (compacted at
+    // pos[a] for the parts ne[a]) as a fresh record: the taker chooses its
+    // class and v.  Its mapping is the current path plus smap[d].
+    __device__ bool spill_child(int fb, int K2, const bool *ne, const int *pos, const W *pl,
+                                const W *pr) {
+        unsigned long long ticket;
+        int ring;
+        if (!reserve(ring, ticket))
+            return false;
+        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+        const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
+        uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
+        RecHdr<W> rh;
+        rh.inst = (uint32_t)inst;
+        rh.K = (uint8_t)K2;
+        rh.d = (uint8_t)(d + 1);
+        rh.v = 0;
+        rh.sel = 0;
+        rh.bound = (uint8_t)fb;
+        rh.flags = (uint8_t)kFlagFresh;
+        rh.lsel = 0;
+        rh.rsel = 0;
+        rh.pad[0] = rh.pad[1] = rh.pad[2] = rh.pad[3] = 0;
+        rh.rrem = 0;
+        if (lane == 0)
+            *(RecHdr<W> *)slot = rh;
+        uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
+        if (lane <= d)
+            rmap[lane] = smap[lane];
+        Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
+#pragma unroll
+        for (int a = 0; a < NR; ++a)
+            if (ne[a]) {
+                Cls<W> c;
+                c.L = pl[a];
+                c.R = pr[a];
+                rcls[pos[a]] = c;
+            }
+        if (lane == 0) {
+            a_add_rlx(&P.open[inst], 1);
+            a_add_rlx(&P.g->open_total, 1);
+            st_rel(&P.seq[idx], ticket + 1);
+        }
+        n_spill += 1;
+        return true;
+    }
+
     // Take a queued node: from this XCD's ring, else (steal) from one other
     // ring, a different one on each call.
     __device__ bool take_record() {
@@ -1019,6 +1081,9 @@ struct Searcher {
         if (bound <= inc) {
             rrem = 0;
             flags = 0;
+        } else if (flags & kFlagFresh) {
+            flags = kFlagUnmatched;
+            select();
         } else if (POL && (flags & kFlagOrdered)) {
             if constexpr (POL)
                 order_partners(rrem);
@@ -1210,6 +1275,9 @@ struct Searcher {
             a_add64(&P.g->donations, n_don);
             a_add64(&P.g->pops, n_pops);
             a_add64(&P.g->busy_ticks, n_busy);
+            a_add64(&P.g->spills, n_spill);
+            __hip_atomic_fetch_max(&P.g->max_stack, max_used, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 };

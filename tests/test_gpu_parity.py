@@ -185,6 +185,35 @@ def test_tunings_do_not_change_sizes(gpu, tun):
     _check(pairs, res, sizes)
 
 
+@pytest.mark.parametrize("tun", [
+    {"stack_classes": 1},
+    {"stack_classes": 1, "children_per_wave": 1, "check_interval": 1, "waves_per_cu": 1},
+    {"stack_classes": 1, "donate_low": -1},
+])
+def test_small_class_stack_spills_children_exactly(gpu, tun):
+    """A class stack far below the worst case (1 asks for the smallest
+    allowed, 2m + 1 classes): children that do not fit on a wavefront's stack
+    go to the node queue as fresh records, and every size still equals the
+    oracle's."""
+    from paper_1908_06418_amd import Plan
+    pairs, sizes = _tuning_case()
+    c3 = mi.pairs_c3(ns=(40, 60), seeds=range(3))
+    c3_sizes = [oracle.mcs(G, H)["size"] for G, H in c3]
+    for batch, want in ((pairs, sizes), (c3, c3_sizes)):
+        _say(f"small stack {tun}: {len(batch)} pairs")
+        plan = Plan(batch, time_limit_s=60, tuning=tun).upload()
+        plan.run()
+        res = plan.results()
+        st = plan.stats()
+        plan.close()
+        mmax = max(min(G["n"], H["n"]) for G, H in batch)
+        assert st.stack_classes == min(2 * mmax + 1, mmax * (mmax + 1) // 2)
+        assert st.max_stack_used <= st.stack_classes
+        assert st.spills > 0
+        assert all(r.optimal for r in res)
+        _check(batch, res, want)
+
+
 def test_graph_replays_match_eager(gpu):
     """The HIP graph (reset kernel + search kernel) replayed several times,
     with eager work between replays, gives the eager result every time."""
