@@ -4,10 +4,12 @@ A step is one pass of the whole search over one batch of synthetic pairs: the
 search kernel (class split, Eq. 1 bound, prune/spawn, work queue, incumbent,
 termination) plus the result copy-back and un-permuting.  Inputs are uploaded
 to HBM once, before the timed region.  Every step's sizes are checked against
-the oracle's stored sizes for the workload; a mismatch marks the line
-"exact": false.
+the oracle's stored results for the workload: equal where the oracle finished
+(oracle_checked counts those pairs), at least its lower bound where its node
+budget ran out, and every pair proven optimal by the search itself; anything
+else marks the line "exact": false.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2_n30]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 
 Prints one JSON line.
 """
@@ -42,12 +44,16 @@ OPS_PER_CLASS = {(4, False): 14, (8, False): 24, (4, True): 34, (8, True): 60}
 def workloads():
     import mcs_instances as mi
     return {
+        "c2": ("180 undirected unlabelled pairs G(n,p), n in {30,35,40}, p in {0.1,0.3,0.5}, "
+               "20 seeds each, one batched launch", lambda: mi.pairs_c2(), "expected_c2.json"),
         "c2_n30": ("60 undirected unlabelled pairs G(30,p), p in {0.1,0.3,0.5}, 20 seeds each, "
                    "one batched launch", lambda: mi.pairs_c2(ns=(30,)), "expected_c2_n30.json"),
         "c3": ("60 directed vertex-labelled pairs n in {40,50,60}, p=0.1, ceil(0.33n) labels, "
                "one batched launch", lambda: mi.pairs_c3(), "expected_c3.json"),
         "c4_1024": ("first 1024 pairs of the batched workload, n ~ U{10..35}, p ~ U[0.05,0.5)",
                     lambda: mi.pairs_c4(1024), "expected_c4_1024.json"),
+        "c4": ("the batched workload: 4096 undirected pairs, n ~ U{10..35}, p ~ U[0.05,0.5), "
+               "one persistent launch", lambda: mi.pairs_c4(4096), "expected_c4.json"),
         "c1": ("one undirected unlabelled pair G(16,0.3)", lambda: mi.pair_c1(), None),
     }
 
@@ -107,6 +113,14 @@ def cpu_baseline(pairs, exp, budget_s=20.0):
                       f"{cores} host cores, {dt:.1f} s wall"}
 
 
+def _spread(xs):
+    """Median and maximum over instances (and steps), in seconds of kernel time."""
+    if not xs:
+        return None
+    xs = sorted(xs)
+    return {"median": xs[len(xs) // 2], "max": xs[-1]}
+
+
 def _oracle_one(G, H):
     import oracle
     r = oracle.mcs(G, H)
@@ -116,9 +130,9 @@ def _oracle_one(G, H):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2_n30")
+    ap.add_argument("--workload", default="c2")
     ap.add_argument("--time-limit", type=float, default=120.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", default="", help="JSON dict of mcs_tuning fields")
@@ -169,6 +183,8 @@ def main():
     kernel_ms = 0.0
     lane_slots = batches = children = 0
     proven = 0
+    busy = []
+    t_best, t_proof = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = step()
@@ -179,6 +195,9 @@ def main():
         batches += st.batches
         children += st.children
         proven += sum(r.optimal for r in res)
+        busy.append(st.busy_frac)
+        t_best += [r.t_best_s for r in res]
+        t_proof += [r.t_proof_s for r in res if r.optimal]
         if exp is not None:
             for r, e in zip(res, exp["pairs"]):
                 if (e["complete"] and r.size != e["size"]) or r.size < e["size"]:
@@ -212,9 +231,13 @@ def main():
                    "tuning": tuning, "tuning_source": tuning_src},
         "instances_per_s": len(pairs) * K / elapsed,
         "exact": exact,
+        "oracle_checked": sum(e["complete"] for e in exp["pairs"]) if exp else 0,
         "proven_per_step": proven / K,
         "kernel_ms_per_step": kernel_ms / K,
         "nodes_per_step": nodes / K,
+        "time_to_best_s": _spread(t_best),
+        "time_to_proof_s": _spread(t_proof),
+        "busy_frac": sum(busy) / len(busy) if busy else 0.0,
         "active_lane_frac": lane_slots / (64.0 * batches) if batches else 0.0,
         "children_per_batch": children / batches if batches else 0.0,
         "waves": st.waves,

@@ -21,8 +21,14 @@ sys.path.insert(0, ROOT)
 import mcs_instances as mi  # noqa: E402
 import oracle  # noqa: E402
 
+def _c2_limit(G, H):
+    # G(30,p) pairs all finish (at most about 1.2e8 nodes); larger ones get a budget
+    return 0 if G["n"] <= 30 else 100_000_000
+
+
 SETS = {
-    # name: (pairs factory, oracle node limit, description)
+    # name: (pairs factory, oracle node limit (an int, or a function of the
+    # pair), description)
     "c2_n30": (lambda: mi.pairs_c2(ns=(30,)), 0,
                "undirected unlabelled G(30,p), p in {0.1,0.3,0.5}, seeds 0..19"),
     "c2_n35_p01": (lambda: mi.pairs_c2(ns=(35,), ps=(0.1,)), 200_000_000,
@@ -33,7 +39,14 @@ SETS = {
                 "batched workload, first 1024 pairs (n ~ U{10..35}, p ~ U[0.05,0.5))"),
     "c4": (lambda: mi.pairs_c4(4096), 20_000_000,
            "batched workload, all 4096 pairs (n ~ U{10..35}, p ~ U[0.05,0.5))"),
+    "c2": (lambda: mi.pairs_c2(), _c2_limit,
+           "undirected unlabelled G(n,p), n in {30,35,40}, p in {0.1,0.3,0.5}, seeds 0..19 "
+           "(node limit: none for n = 30, 1e8 otherwise)"),
 }
+
+
+def _limit(lim, G, H):
+    return lim(G, H) if callable(lim) else lim
 
 
 def _one(args):
@@ -43,20 +56,33 @@ def _one(args):
     return i, r["size"], r["complete"], r["nodes"], time.time() - t
 
 
-def _prefix_rows(pairs, lim):
-    """Rows of another stored set whose pairs are a prefix of these, made
-    with the same node limit (the same oracle runs: reused, not redone)."""
-    best = []
+def _known_rows(pairs, lim):
+    """Rows other stored sets already hold for identical pairs, where the
+    oracle run under this set's limit would give the same row: a finished
+    run within the limit, or an unfinished one under the same limit (the
+    oracle is deterministic, so these are reused, not redone)."""
+    want = {}
+    for i, (G, H) in enumerate(pairs):
+        want.setdefault(mi.workload_hash([(G, H)]), []).append(i)
+    rows = [None] * len(pairs)
     for other, (factory, olim, _) in SETS.items():
         path = os.path.join(HERE, f"expected_{other}.json")
-        if olim != lim or not os.path.exists(path):
+        if not os.path.exists(path):
             continue
         with open(path) as f:
             data = json.load(f)
-        k = len(data["pairs"])
-        if k > len(best) and k <= len(pairs) and data["digest"] == mi.workload_hash(pairs[:k]):
-            best = data["pairs"]
-    return best
+        opairs = factory()
+        if data["digest"] != mi.workload_hash(opairs):
+            continue
+        for (G, H), row in zip(opairs, data["pairs"]):
+            for i in want.get(mi.workload_hash([(G, H)]), []):
+                mine = _limit(lim, *pairs[i])
+                theirs = _limit(olim, G, H)
+                same = (row["complete"] and (mine == 0 or row["nodes"] <= mine)) or \
+                       (not row["complete"] and theirs == mine)
+                if same and rows[i] is None:
+                    rows[i] = row
+    return rows
 
 
 def make(name: str, workers: int = 8) -> str:
@@ -64,14 +90,15 @@ def make(name: str, workers: int = 8) -> str:
     pairs = factory()
     oracle._load()
     rows = [None] * len(pairs)
-    done = _prefix_rows(pairs, lim) if len(pairs) > 1 else []
-    rows[:len(done)] = done
+    rows = _known_rows(pairs, lim)
     with ProcessPoolExecutor(workers) as ex:
         for i, size, complete, nodes, dt in ex.map(
-                _one, [(i, G, H, lim) for i, (G, H) in enumerate(pairs) if rows[i] is None]):
+                _one, [(i, G, H, _limit(lim, G, H)) for i, (G, H) in enumerate(pairs)
+                       if rows[i] is None]):
             rows[i] = {"size": size, "complete": complete, "nodes": nodes,
                        "seconds": round(dt, 4)}
-    out = {"workload": name, "description": desc, "node_limit": lim,
+    out = {"workload": name, "description": desc,
+           "node_limit": lim if not callable(lim) else [_limit(lim, G, H) for G, H in pairs],
            "digest": mi.workload_hash(pairs),
            "made_by": "tests/golden/make_expected.py (oracle only)",
            "pairs": rows}
