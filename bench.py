@@ -73,9 +73,10 @@ def traffic_for(workload: str, launches: int):
 
 
 def expected_sizes(fname):
-    if fname is None:
+    path = os.path.join(ROOT, "tests", "golden", fname) if fname else None
+    if path is None or not os.path.exists(path):
         return None
-    with open(os.path.join(ROOT, "tests", "golden", fname)) as f:
+    with open(path) as f:
         return json.load(f)
 
 
