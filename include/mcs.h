@@ -80,7 +80,7 @@ typedef struct {
                                   open node (0: 2; < 0: never donate) */
     int32_t donate_depth;      /* only nodes with |M| <= this are donated, as the
                                   paper delegates only above PART_LEVEL
-                                  (0: a third of the largest min(nG, nH)) */
+                                  (0: half the largest min(nG, nH)) */
     int32_t check_interval;    /* search steps between queue/limit checks (0: 128) */
     int32_t no_reprune;        /* 1: do not re-test a frame's bound against the
                                   incumbent when the search returns to it */

@@ -523,7 +523,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.donate_low = p->tun.donate_low > 0 ? p->tun.donate_low
                                           : (p->tun.donate_low < 0 ? -1 : 2);
     sp.donate_depth = p->tun.donate_depth > 0 ? p->tun.donate_depth
-                                              : std::max(1, p->mmax / 3);
+                                              : std::max(1, p->mmax / 2);
     // (at most 2^16: the kernel's per-check step counters are 32-bit)
     sp.check_interval = p->tun.check_interval > 0 ? std::min(p->tun.check_interval, 65536) : 128;
     sp.reprune = p->tun.no_reprune ? 0 : 1;
