@@ -31,8 +31,9 @@ PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: int32 lane
 # FETCH_SIZE / WRITE_SIZE runs recorded in profiles/ (see the design doc); reported
 # only while the kernel source is the one those counters were taken on.
 TRAFFIC = {
-    "c2_n30": {"kernel_sha256_16": "848fae35b46e89e0", "bytes": int((1335737.75 * 2 + 1574133.03125) * 1024),
-               "profile": "profiles/mcs_search_kernel_c2_n30.md"},
+    "c2": {"kernel_sha256_16": "829f6ca0994dc79e",
+           "bytes": int((31261040.3125 * 2 + 46817527.0) * 1024),
+           "profile": "profiles/mcs_search_kernel_c2.md"},
 }
 
 # Algorithmic 32-bit lane operations per class per evaluated child: remove v
