@@ -100,9 +100,10 @@ typedef struct {
     int64_t node_limit;        /* stop after about this many nodes (0: none) */
     double time_limit_s;       /* stop after this much kernel time (<= 0: 600 s) */
     const mcs_tuning *tuning;  /* NULL: all defaults */
-    const uint16_t *policy;    /* device pointer to the learned branching policy's
-                                  half-precision parameters (mcs_policy_pack_half),
-                                  or NULL: branch on the smallest vertex index
+    const uint16_t *policy;    /* device pointer, 16-byte aligned, to the learned
+                                  branching policy's half-precision parameters
+                                  (mcs_policy_pack_half), or NULL: branch on the
+                                  smallest vertex index
                                   (descending degree) and try partners in index
                                   order */
     int32_t policy_depth;      /* the policy orders choices at nodes with

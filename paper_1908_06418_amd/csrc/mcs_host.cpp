@@ -260,6 +260,10 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
                 delete p;
                 return fail(MCS_E_INVALID, "policy_depth must be in 0..8");
             }
+            if ((uintptr_t)opts->policy % 16 != 0) {
+                delete p;
+                return fail(MCS_E_INVALID, "policy parameters must be 16-byte aligned");
+            }
             p->policy = opts->policy;
             p->policy_depth = opts->policy_depth;
             p->policy_mode = opts->policy_mode ? (opts->policy_mode & 3) : 2;

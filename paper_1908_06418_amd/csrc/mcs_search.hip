@@ -227,6 +227,18 @@ DEV bool cas64(unsigned long long *p, unsigned long long expect, unsigned long l
 DEV unsigned long long now_ticks() { return wall_clock64(); }
 
 DEV float hf(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+DEV float rlf(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+template <int CTRL>
+DEV float fdpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+DEV float fwave_sum(float x) {
+    x += fdpp<0xB1>(x);
+    x += fdpp<0x4E>(x);
+    x += fdpp<0x141>(x);
+    x += fdpp<0x140>(x);
+    return (rlf(x, 0) + rlf(x, 16)) + (rlf(x, 32) + rlf(x, 48));
+}
 
 // ---- one wavefront's search ------------------------------------------------
 
@@ -360,72 +372,97 @@ struct Searcher {
     }
 
     // -- learned branching policy ----------------------------------------------
-    // Lane u scores vertex u of one side (u in cand) from the 16 features the
-    // policy reference defines, with the half-precision network.
-
-    // Not inlined: it runs only at shallow frames, and keeping its registers
-    // out of the main loop keeps the loop's own allocation small.
-    __device__ __attribute__((noinline)) float policy_score(int side, W cand) {
-        const int u = lane;
-        const bool is_cand = u < NB && ((cand >> (u & (NB - 1))) & 1);
+    // Scores of the candidate vertices `cand` of one side, from the 16
+    // features the policy reference defines and the half-precision network:
+    // lane u returns the score of vertex u.  One lane per hidden unit (both
+    // hidden layers are 64 wide) and one candidate at a time: the features
+    // are wave-uniform, layer 1 is 16 multiply-adds per lane, layer 2 takes
+    // every lane's layer-1 output by readlane, and the output is a wave sum.
+    // This keeps the scorer's registers few, so a policy kernel runs as many
+    // wavefronts per CU as a plain one; the scorer itself runs only at
+    // shallow frames.
+    __device__ float policy_score(int side, W cand) {
         const int off = side ? NB : 0;
-        W row = sadj[off + (u & (NB - 1))];
-        if (DIR)
-            row |= sadj[2 * NB + off + (u & (NB - 1))];
         const int n = side ? nH : nG;
         const float inv = 1.f / (float)(n > 0 ? n : 1);
-        const int deg = popc(row);
-        float x[kPolicyF];
+        // class lanes: this side's set and the class-size bucket (8-bit field)
+        W mine = 0;
+        int bsh = 0;
+        if (lane < K) {
+            Cls<W> c = scls[base + lane];
+            const int nl = popc(c.L), nr = popc(c.R);
+            const int m = nl < nr ? nl : nr;
+            const int bq = m <= 1 ? 0 : m == 2 ? 1 : m <= 4 ? 2 : m <= 8 ? 3 : m <= 16 ? 4 : 5;
+            mine = side ? c.R : c.L;
+            bsh = 8 * bq;
+        }
+        // largest degree among the candidates
+        const int ul = lane & (NB - 1);
+        W rowl = sadj[off + ul];
+        if (DIR)
+            rowl |= sadj[2 * NB + off + ul];
+        const bool is_cand = lane < NB && ((cand >> ul) & 1);
+        const int dmax = (int)~wave_min(~(uint32_t)(is_cand ? popc(rowl) : 0));
+        // this lane's hidden unit
+        const uint16_t *w = P.policy;
+        float w1[kPolicyF];
 #pragma unroll
         for (int f = 0; f < kPolicyF; ++f)
-            x[f] = 0.f;
-        int tot = 0;
-        for (int k = 0; k < K; ++k) {
-            Cls<W> c = scls[base + k];
-            int m = popc(c.L) < popc(c.R) ? popc(c.L) : popc(c.R);
-            int b = m <= 1 ? 0 : m == 2 ? 1 : m <= 4 ? 2 : m <= 8 ? 3 : m <= 16 ? 4 : 5;
-            int cnt = popc(row & (side ? c.R : c.L));
-            tot += cnt;
+            w1[f] = hf(w[kOffW1 + lane * kPolicyF + f]);
+        const float b1 = hf(w[kOffB1 + lane]), b2 = hf(w[kOffB2 + lane]);
+        const float w3 = hf(w[kOffW3 + lane]), b3 = hf(w[kOffB3]);
+        const uint4 *w2 = (const uint4 *)(w + kOffW2 + lane * kPolicyH);  // 16-byte aligned
+        float out = 0.f;
+        for (W rest = cand; rest; rest &= rest - 1) {
+            const int u = sc((int)ctz(rest));
+            W row = sadj[off + u];
+            if (DIR)
+                row |= sadj[2 * NB + off + u];
+            row = sc(row);
+            const int deg = popc(row);
+            // neighbours of u per class, summed per size bucket (each sum is
+            // at most deg < 64, so 8-bit fields cannot carry)
+            const unsigned long long packed = (unsigned long long)popc(row & mine) << bsh;
+            const int lo = wave_sum((int)(uint32_t)packed);
+            const int hi = wave_sum((int)(uint32_t)(packed >> 32));
+            float x[kPolicyF];
+            x[0] = deg * inv;
+            x[1] = lsel * inv;
+            x[2] = rsel * inv;
+            x[3] = d * inv;
+            x[4] = K * inv;
+            int tot = 0;
 #pragma unroll
-            for (int q = 0; q < 6; ++q)
-                if (q == b)
-                    x[6 + q] += (float)cnt;
-        }
-        uint32_t dk = is_cand ? (uint32_t)deg : 0u;
-        uint32_t dmax = ~wave_min(~dk);
-        x[0] = deg * inv;
-        x[1] = lsel * inv;
-        x[2] = rsel * inv;
-        x[3] = d * inv;
-        x[4] = K * inv;
-        x[5] = tot * inv;
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-            x[6 + q] *= inv;
-        x[12] = (float)side;
-        x[13] = (uint32_t)deg == dmax ? 1.f : 0.f;
-        x[15] = 1.f;
-        const uint16_t *w = P.policy;
-        float h1[kPolicyH];
-#pragma unroll
-        for (int j = 0; j < kPolicyH; ++j) {
-            float acc = hf(w[kOffB1 + j]);
+            for (int q = 0; q < 6; ++q) {
+                const int cq = q < 4 ? (lo >> (8 * q)) & 0xFF : (hi >> (8 * (q - 4))) & 0xFF;
+                x[6 + q] = cq * inv;
+                tot += cq;
+            }
+            x[5] = tot * inv;
+            x[12] = (float)side;
+            x[13] = deg == dmax ? 1.f : 0.f;
+            x[14] = 0.f;
+            x[15] = 1.f;
+            float h1 = b1;
 #pragma unroll
             for (int f = 0; f < kPolicyF; ++f)
-                acc += hf(w[kOffW1 + j * kPolicyF + f]) * x[f];
-            h1[j] = acc > 0.f ? acc : 0.f;
-        }
-        float z = hf(w[kOffB3]);
+                h1 += w1[f] * x[f];
+            h1 = h1 > 0.f ? h1 : 0.f;
+            float a2 = b2;
 #pragma unroll 1
-        for (int j = 0; j < kPolicyH; ++j) {
-            float acc = hf(w[kOffB2 + j]);
-            const uint16_t *row = w + kOffW2 + j * kPolicyH;
+            for (int c = 0; c < kPolicyH / 8; ++c) {
+                const uint4 q = w2[c];
+                const uint32_t pk[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-            for (int i = 0; i < kPolicyH; ++i)
-                acc += hf(row[i]) * h1[i];
-            z += hf(w[kOffW3 + j]) * (acc > 0.f ? acc : 0.f);
+                for (int e = 0; e < 4; ++e) {
+                    a2 += hf((uint16_t)(pk[e] & 0xFFFFu)) * rlf(h1, 8 * c + 2 * e);
+                    a2 += hf((uint16_t)(pk[e] >> 16)) * rlf(h1, 8 * c + 2 * e + 1);
+                }
+            }
+            const float z = b3 + fwave_sum(w3 * (a2 > 0.f ? a2 : 0.f));
+            out = lane == u ? z : out;
         }
-        return z;
+        return out;
     }
 
     // Highest-scoring candidate lane (lowest index among equal scores).

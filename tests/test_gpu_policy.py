@@ -141,6 +141,49 @@ def test_policy_search_is_exact(gpu, trained):
     assert [r.size for r in res] == want[:20]
 
 
+def _feature_net(sign: float) -> np.ndarray:
+    """Parameters whose network output is sign * feature 0 (degree / n):
+    W1[0][0] = 1, W2[0][0] = 1, w3[0] = sign, everything else 0 (exact in
+    half precision)."""
+    p = ref.unflat(np.zeros(ref.N_PARAMS))
+    p = {k: a.copy() for k, a in p.items()}
+    p["W1"][0, 0] = 1.0
+    p["W2"][0, 0] = 1.0
+    p["w3"][0] = sign
+    return ref.flat(p)
+
+
+def test_in_search_scorer_plumbing(gpu):
+    """The in-search scorer, end to end: with a network whose score is the
+    candidate's degree / n, choosing v by the policy and ordering partners
+    by it reproduce the plain rule exactly (vertices are numbered by
+    descending degree, ties by index, and the policy breaks score ties by the
+    lowest index), so a single wavefront expands exactly the plain search's
+    nodes.  With the negated score the search changes (other node counts)
+    but every size stays the oracle's."""
+    from paper_1908_06418_amd import solve_batch
+    from paper_1908_06418_amd.policy import Policy
+    rng = np.random.default_rng(5)
+    pairs = [pq for pq in mi.pairs_c4(120, start=2000) if pq[0]["n"] <= 22][:24]
+    pairs += [(mi.random_small(rng, 14, 0.4, False, 3), mi.random_small(rng, 15, 0.4, False, 3))
+              for _ in range(6)]
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    tun = {"single_wave": 1}
+    plain = solve_batch(pairs, time_limit_s=60, tuning=tun)
+    deg = Policy(params=_feature_net(1.0))
+    neg = Policy(params=_feature_net(-1.0))
+    for mode in (1, 2, 3):
+        _say(f"scorer plumbing, mode {mode}")
+        same = solve_batch(pairs, time_limit_s=60, tuning=tun, policy=deg, policy_depth=8,
+                           policy_mode=mode)
+        assert [r.nodes for r in same] == [r.nodes for r in plain], mode
+        assert [r.size for r in same] == want
+    other = solve_batch(pairs, time_limit_s=60, tuning=tun, policy=neg, policy_depth=8,
+                        policy_mode=1)
+    assert [r.size for r in other] == want
+    assert [r.nodes for r in other] != [r.nodes for r in plain]
+
+
 def test_policy_gain_report(gpu):
     """What the trained policy gains over the plain rule (smallest vertex in
     descending-degree order, partners in index order) at |M| <= 1: node
