@@ -68,7 +68,7 @@ typedef struct {
  * defaults the library derives from the instance sizes. */
 typedef struct {
     int32_t waves_per_cu;      /* resident search wavefronts per CU (0: about
-                                  96 per instance, between 1 and 24 per CU;
+                                  96 per instance, between 8 and 24 per CU;
                                   capped by what LDS and registers allow) */
     int32_t children_per_wave; /* how many sibling children one wavefront may
                                   evaluate at once (1, 2, 4 or 8; 0: 8) */

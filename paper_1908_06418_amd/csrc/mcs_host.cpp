@@ -392,14 +392,14 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         clock_khz = 100000;
     (void)hipGetLastError();
     p->tick_hz = (double)clock_khz * 1000.0;
-    // Default: about 96 wavefronts per instance, between one and 24 per
-    // CU.  One wavefront's search is a long dependent chain of scalar
+    // Default: about 96 wavefronts per instance, between 8 and 24 per CU
+    // (one hard instance alone still splits across thousands of them).  One wavefront's search is a long dependent chain of scalar
     // and vector steps, so several per SIMD fill the issue slots while
     // there is work for them; past what the instances can keep busy, more
     // wavefronts only split the work into ever smaller donations.
     const int want_waves = p->tun.waves_per_cu > 0
                                ? p->tun.waves_per_cu * cus
-                               : std::max(cus, std::min(24 * cus, 96 * count));
+                               : std::max(8 * cus, std::min(24 * cus, 96 * count));
     const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
     auto per_wave = [&](int cap) {
         return mcs::lds_layout(p->word_bytes, directed, cap, p->frames, p->policy_levels).total;

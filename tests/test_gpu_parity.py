@@ -329,3 +329,34 @@ def test_side_stream_single_runtime(gpu):
         res = plan.results()
     _check(pairs, res, want)
     plan.close()
+
+
+def test_batched_vs_one_at_a_time_report(gpu):
+    """The batched launch against the plain search of one instance per
+    launch (the whole GPU on one pair, library defaults, then at 24
+    wavefronts per CU), on the 60 pairs G(30,p): equal sizes, and the
+    kernel time of each way, written to gpurun_out/batch_report.json."""
+    from paper_1908_06418_amd import Plan
+    pairs = mi.pairs_c2(ns=(30,))
+    plan = Plan(pairs, time_limit_s=60).upload()
+    plan.run()
+    batched = plan.results()
+    batched_ms = plan.stats().kernel_ms
+    plan.close()
+    report = {"pairs": len(pairs), "batched_ms": batched_ms}
+    for name, tun in (("one_at_a_time_default", None),
+                      ("one_at_a_time_24_per_cu", {"waves_per_cu": 24})):
+        total = 0.0
+        for i, pq in enumerate(pairs):
+            plan = Plan([pq], time_limit_s=60, tuning=tun).upload()
+            plan.run()
+            r = plan.results()[0]
+            total += plan.stats().kernel_ms
+            plan.close()
+            assert r.optimal and r.size == batched[i].size, (name, i)
+        report[name + "_ms"] = total
+        _say(f"{name}: {total:.1f} ms for {len(pairs)} launches")
+    _say("batch report: " + json.dumps(report))
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "batch_report.json"), "w") as f:
+        json.dump(report, f, indent=1)
