@@ -46,7 +46,10 @@ typedef enum {
     MCS_E_TOO_LARGE = -2, /* a graph has more than MCS_MAX_N vertices */
     MCS_E_DEVICE = -3,    /* a HIP call or the search kernel failed */
     MCS_E_WORKSPACE = -4, /* workspace missing, too small or misaligned */
-    MCS_E_INTERNAL = -5   /* an internal capacity check fired (a bug) */
+    MCS_E_INTERNAL = -5,  /* an internal capacity check fired (a bug) */
+    MCS_E_QUEUE_FULL = -6 /* a child with no room on a wavefront's class stack
+                             found every node-queue slot taken: raise
+                             mcs_tuning.ring_slots or stack_classes */
 } mcs_status;
 
 #define MCS_MAX_N 64

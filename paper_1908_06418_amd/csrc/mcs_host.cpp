@@ -215,6 +215,7 @@ const char *mcs_status_string(mcs_status s) {
     case MCS_E_DEVICE: return "device error";
     case MCS_E_WORKSPACE: return "workspace missing or too small";
     case MCS_E_INTERNAL: return "internal capacity check failed";
+    case MCS_E_QUEUE_FULL: return "node queue full while queueing a child";
     }
     return "unknown status";
 }
@@ -663,6 +664,9 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
         p->last_ms = 0.f;
     }
     p->have_results = true;
+    if (p->h_glob.error == 2)
+        return fail(MCS_E_QUEUE_FULL, "a child had no room on a wavefront's class stack and every "
+                                      "node-queue slot was taken; raise ring_slots or stack_classes");
     if (p->h_glob.error)
         return fail(MCS_E_INTERNAL, "a search wavefront hit an internal capacity check");
 

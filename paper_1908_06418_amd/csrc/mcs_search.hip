@@ -320,9 +320,11 @@ struct Searcher {
         }
     }
 
-    __device__ void fail() {
+    // code 1: a capacity check that cannot fire unless there is a bug;
+    // code 2: the node queue was full when a child had to be queued.
+    __device__ void fail(unsigned code) {
         if (lane == 0)
-            __hip_atomic_store(&P.g->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&P.g->error, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         raise_flag(kFlagStop);
         stop = true;
     }
@@ -769,8 +771,11 @@ struct Searcher {
             wave_sync();
             if (d + 1 > inc)
                 improve(d + 1);
-            if (P.single_wave || !spill_child(fb, K2, ne, pos, pl, pr))
-                fail();
+            // (one wavefront alone has the worst-case stack: no spill there)
+            if (P.single_wave)
+                fail(1);
+            else if (!spill_child(fb, K2, ne, pos, pl, pr))
+                fail(2);
             return;
         }
         if (nb + K2 > max_used)

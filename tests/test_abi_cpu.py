@@ -66,7 +66,7 @@ def _status(exc):
 
 
 def test_status_strings(mcs_lib):
-    for s in (0, 1, -1, -2, -3, -4, -5):
+    for s in (0, 1, -1, -2, -3, -4, -5, -6):
         assert mcs_lib.mcs_status_string(s)
     assert b"unknown" in mcs_lib.mcs_status_string(42)
 

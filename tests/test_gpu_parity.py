@@ -214,6 +214,28 @@ def test_small_class_stack_spills_children_exactly(gpu, tun):
         _check(batch, res, want)
 
 
+def test_queue_full_while_spilling_is_reported(gpu):
+    """The smallest class stack with a node queue of 16 slots: a child that
+    finds no stack room and no free slot stops the search with
+    MCS_E_QUEUE_FULL (every wavefront leaves through the stop flag); if the
+    queue never fills, the run is exact.  Either way it ends."""
+    from paper_1908_06418_amd import McsError, Plan, _abi
+    pairs, sizes = _tuning_case()
+    plan = Plan(pairs, time_limit_s=60,
+                tuning={"stack_classes": 1, "ring_slots": 2, "waves_per_cu": 8}).upload()
+    try:
+        plan.run()
+        res = plan.results()
+    except McsError as e:
+        assert e.status == _abi.MCS_E_QUEUE_FULL, e
+        _say(f"queue full reported: {e}")
+    else:
+        _say("queue never filled")
+        _check(pairs, res, sizes)
+    finally:
+        plan.close()
+
+
 def test_graph_replays_match_eager(gpu):
     """The HIP graph (reset kernel + search kernel) replayed several times,
     with eager work between replays, gives the eager result every time."""
