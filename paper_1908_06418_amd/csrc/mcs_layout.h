@@ -128,7 +128,9 @@ template <typename W>
 constexpr int rec_cls_off() { return kRecHeader + 2 * bits_of<W>(); }
 
 // LDS of one wavefront, in this order, each part 16-byte aligned:
-//   classes   [cap_classes] (L, R) word pairs
+//   classes   [cap_classes + 1] (L, R) word pairs; the last is a trash slot
+//             that lanes with nothing to store write to, so the stores need
+//             no exec-mask branches
 //   adjacency [R][NB] words
 //   mapping   [NB] byte pairs
 //   headers   [frames][kHdrWords] frame headers, one 32-bit word per field
@@ -146,7 +148,7 @@ inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_clas
     int hdr_bytes = 4 * kHdrWords;
     LdsLayout L{0, 0, 0, 0, 0, 0};
     L.cls = 0;
-    L.adj = align16(cap_classes * 2 * word_bytes);
+    L.adj = align16((cap_classes + 1) * 2 * word_bytes);
     L.map = align16(L.adj + rows * nb * word_bytes);
     L.hdr = align16(L.map + 2 * nb);
     L.ord = align16(L.hdr + frames * hdr_bytes);

@@ -333,14 +333,11 @@ struct Searcher {
 
     __device__ void load_regs() {
         logS = K <= 8 ? 3 : K <= 16 ? 4 : K <= 32 ? 5 : 6;
-        int k = lane & ((1 << logS) - 1);
-        cL = 0;
-        cR = 0;
-        if (k < K) {
-            Cls<W> c = scls[base + k];
-            cL = c.L;
-            cR = c.R;
-        }
+        const int k = lane & ((1 << logS) - 1);
+        const bool in = k < K;
+        const Cls<W> c = scls[base + (in ? k : 0)];  // (no exec-mask branch)
+        cL = in ? c.L : (W)0;
+        cR = in ? c.R : (W)0;
     }
 
     // selectLabelClass + selectVertex: the class with the smallest
@@ -523,8 +520,8 @@ struct Searcher {
             : "+v"(x)
             : "s"(lo), "s"(hi), "s"(base), "s"(K), "s"(d), "s"(v), "s"(sel), "s"(bound),
               "s"(flags), "s"(lsel), "s"(rsel));
-        if (lane <= kHRsel)
-            shdr[t * kHdrWords + lane] = x;
+        // lanes past the last field all store into the header's padding word
+        shdr[t * kHdrWords + (lane < kHdrWords ? lane : kHdrWords - 1)] = x;
     }
 
     // One field of frame i's header, as a scalar.
@@ -780,16 +777,15 @@ struct Searcher {
         }
         if (nb + K2 > max_used)
             max_used = nb + K2;
+        // every lane stores; lanes without a class of the child hit the trash slot
 #pragma unroll
-        for (int a = 0; a < NR; ++a)
-            if (ne[a]) {
-                Cls<W> c;
-                c.L = pl[a];
-                c.R = pr[a];
-                scls[nb + pos[a]] = c;
-            }
-        if (lane == 0)
-            smap[d] = (uint16_t)(v | (wF << 8));
+        for (int a = 0; a < NR; ++a) {
+            Cls<W> c;
+            c.L = pl[a];
+            c.R = pr[a];
+            scls[ne[a] ? nb + pos[a] : cap_classes] = c;
+        }
+        smap[d] = (uint16_t)(v | (wF << 8));  // the same value from every lane
         save_top();
         wave_sync();
         if (d + 1 > inc)
@@ -818,12 +814,10 @@ struct Searcher {
         const W vb = (W)1 << v;
         if (lsel == 1) {
             int last = K - 1;
-            if (sel != last && lane == last) {
-                Cls<W> c;
-                c.L = cL;
-                c.R = cR;
-                scls[base + sel] = c;
-            }
+            Cls<W> c;
+            c.L = cL;
+            c.R = cR;
+            scls[(sel != last && lane == last) ? base + sel : cap_classes] = c;
             K = last;
             wave_sync();
             bound = ub;
@@ -834,8 +828,7 @@ struct Searcher {
             int k = lane & ((1 << logS) - 1);
             if (k == sel)
                 cL &= ~vb;
-            if (lane == sel)
-                scls[base + sel].L = cL;
+            scls[lane == sel ? base + sel : cap_classes].L = cL;
             wave_sync();
             bound = ub;
         }
