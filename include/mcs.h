@@ -97,6 +97,9 @@ typedef struct {
                                   waves_per_cu from fitting in LDS; never
                                   below 2m + 1).  A child that does not fit
                                   goes to the node queue as a record. */
+    int32_t backoff_max;       /* an idle wavefront that finds no work sleeps
+                                  1, 2, 4, ... up to this many times about
+                                  3.4 us before polling again (0: 32) */
 } mcs_tuning;
 
 typedef struct {
@@ -150,6 +153,8 @@ typedef struct {
     int64_t spills;            /* children queued because the class stack was full */
     int32_t stack_classes;     /* class-stack capacity per wavefront */
     int32_t max_stack_used;    /* most classes any wavefront's stack held */
+    double sleep_wave_s;       /* wavefront-seconds idle wavefronts spent in
+                                  back-off sleeps (part of the time not busy) */
 } mcs_stats;
 
 typedef struct mcs_plan mcs_plan;

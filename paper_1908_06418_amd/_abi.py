@@ -30,7 +30,7 @@ class mcs_tuning(ctypes.Structure):
                 ("donate_depth", ctypes.c_int32),
                 ("check_interval", ctypes.c_int32), ("no_reprune", ctypes.c_int32),
                 ("single_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("stack_classes", ctypes.c_int32)]
+                ("stack_classes", ctypes.c_int32), ("backoff_max", ctypes.c_int32)]
 
 
 class mcs_opts(ctypes.Structure):
@@ -56,7 +56,7 @@ class mcs_stats(ctypes.Structure):
                 ("lds_per_wave", ctypes.c_int32), ("stopped", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("busy_wave_s", ctypes.c_double),
                 ("spills", ctypes.c_int64), ("stack_classes", ctypes.c_int32),
-                ("max_stack_used", ctypes.c_int32)]
+                ("max_stack_used", ctypes.c_int32), ("sleep_wave_s", ctypes.c_double)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/mcs.h

@@ -532,6 +532,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     // (at most 2^16: the kernel's per-check step counters are 32-bit)
     sp.check_interval = p->tun.check_interval > 0 ? std::min(p->tun.check_interval, 65536) : 128;
     sp.reprune = p->tun.no_reprune ? 0 : 1;
+    sp.backoff_max = p->tun.backoff_max > 0 ? std::min(p->tun.backoff_max, 1024) : 32;
     sp.single_wave = p->tun.single_wave ? 1 : 0;
     sp.policy = p->policy;
     sp.policy_depth = p->policy_depth;
@@ -719,6 +720,7 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     z.kernel_ms = p->last_ms;
     z.busy_wave_s = (double)p->h_glob.busy_ticks / p->tick_hz;
     z.spills = (int64_t)p->h_glob.spills;
+    z.sleep_wave_s = (double)p->h_glob.sleep_ticks / p->tick_hz;
     z.stack_classes = p->cap_classes;
     z.max_stack_used = p->h_glob.max_stack;
     *st = z;

@@ -61,6 +61,7 @@ struct DevGlobals {
     unsigned long long pops;
     unsigned long long busy_ticks;  // realtime ticks wavefronts spent searching
     unsigned long long spills;      // children queued for want of stack room
+    unsigned long long sleep_ticks; // realtime ticks idle wavefronts spent sleeping
     int max_stack;                  // most classes any wavefront's stack held
     int pad1;
 };
@@ -88,6 +89,7 @@ struct SearchParams {
     int donate_low;       // records a busy wavefront keeps queued in its XCD's ring (< 0: never donate)
     int donate_depth;     // only frames with |M| <= this are donated
     int check_interval;
+    int backoff_max;      // most sleeps (of about 3.4 us) between an idle wavefront's polls
     int reprune;
     int single_wave;
     const uint16_t *policy;  // half-precision policy parameters, or null

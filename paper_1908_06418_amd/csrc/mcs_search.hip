@@ -271,7 +271,7 @@ struct Searcher {
     int d0;           // depth of the unit's first frame (the shallowest)
     int since_check;
     unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops, n_busy;
-    unsigned long long n_spill;
+    unsigned long long n_spill, n_sleep;
     int max_used;  // most classes this wavefront's stack has held
     // per-step counts since the last fold into the 64-bit totals (at most
     // check_interval steps, so 32 bits cannot overflow)
@@ -302,7 +302,7 @@ struct Searcher {
         since_check = 0;
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = n_busy = 0;
         c_nodes = c_batches = c_children = c_lanes = 0;
-        n_spill = 0;
+        n_spill = n_sleep = 0;
         max_used = 0;
         inc = 0;
         t = -1;
@@ -1297,10 +1297,16 @@ struct Searcher {
                 raise_flag(kFlagStop);
                 break;
             }
-            // back off: 1, 2, 4, ... 32 sleeps of about 8k cycles (3.4 us)
-            backoff = backoff ? (backoff < 32 ? 2 * backoff : 32) : 1;
+            // back off: 1, 2, 4, ... backoff_max sleeps of about 8k cycles
+            // (3.4 us).  Polling more often slows the busy wavefronts more
+            // than it feeds the idle ones: the polls contend with their
+            // checks on the same ring lines.
+            const int bmax = P.backoff_max;
+            backoff = backoff ? (2 * backoff < bmax ? 2 * backoff : bmax) : 1;
+            const unsigned long long t_sleep = now_ticks();
             for (int i = 0; i < backoff; ++i)
                 __builtin_amdgcn_s_sleep(127);
+            n_sleep += now_ticks() - t_sleep;
         }
         fold();
         if (lane == 0) {
@@ -1311,6 +1317,7 @@ struct Searcher {
             a_add64(&P.g->pops, n_pops);
             a_add64(&P.g->busy_ticks, n_busy);
             a_add64(&P.g->spills, n_spill);
+            a_add64(&P.g->sleep_ticks, n_sleep);
             __hip_atomic_fetch_max(&P.g->max_stack, max_used, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }

@@ -177,6 +177,8 @@ def _tuning_case():
     {"waves_per_cu": 1},
     {"no_reprune": 1, "donate_low": 1},
     {"use_graph": 1},
+    {"waves_per_cu": 24, "donate_low": -1},
+    {"backoff_max": 1, "check_interval": 16},
 ])
 def test_tunings_do_not_change_sizes(gpu, tun):
     pairs, sizes = _tuning_case()
