@@ -117,6 +117,14 @@ typedef struct {
     int32_t policy_mode;       /* bit 0: the policy picks v within the selected
                                   class; bit 1: it orders the partners w
                                   (0: order the partners only) */
+    int32_t ordering;          /* static vertex order of both graphs (Sec. IV.A):
+                                  0: descending degree (total degree if
+                                  directed), ties by index; 1: connected
+                                  components, a component with more non-zero
+                                  rows per non-zero column first, each in a
+                                  bordered block-triangular order (the column
+                                  meeting the most shortest active rows next).
+                                  Sizes do not depend on it; node counts do. */
 } mcs_opts;
 
 /* Per-instance result.  map_g/map_h are caller-owned arrays of capacity

@@ -56,6 +56,15 @@ def build_planted(plant: int, out_path: str) -> str:
 
 
 def _bind(lib):
+    lib.oracle_mcs_ordered.restype = ctypes.c_int32
+    lib.oracle_mcs_ordered.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Graph),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
     lib.oracle_mcs.restype = ctypes.c_int32
     lib.oracle_mcs.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Graph),
                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
@@ -120,11 +129,14 @@ def _p32(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
 
 
-def mcs(G: dict, H: dict, node_limit: int = 0, lib=None) -> dict:
+def mcs(G: dict, H: dict, node_limit: int = 0, lib=None, order: str = "degree") -> dict:
     """Maximum common induced subgraph by the plain recursive McSplit.
 
     Returns {"size", "map" (list of (g, h) original ids), "nodes", "complete",
-    "root_bound"}.  ``complete`` is False when ``node_limit`` stopped it."""
+    "root_bound"}.  ``complete`` is False when ``node_limit`` stopped it.
+    ``order``: "degree" (descending degree, Sec. IV.A's default) or "btf"
+    (components and the bordered block-triangular order of Sec. IV.A,
+    oracle.ordering)."""
     if bool(G["directed"]) != bool(H["directed"]):
         raise ValueError("G and H must both be directed or both undirected")
     if (G.get("label") is None) != (H.get("label") is None):
@@ -138,9 +150,20 @@ def mcs(G: dict, H: dict, node_limit: int = 0, lib=None) -> dict:
     nodes = ctypes.c_int64(0)
     complete = ctypes.c_int32(0)
     rb = ctypes.c_int32(0)
-    size = lib.oracle_mcs(ctypes.byref(cg), ctypes.byref(ch), int(node_limit), _p32(mg),
-                          _p32(mh), ctypes.byref(nodes), ctypes.byref(complete),
-                          ctypes.byref(rb))
+    if order == "degree":
+        size = lib.oracle_mcs(ctypes.byref(cg), ctypes.byref(ch), int(node_limit), _p32(mg),
+                              _p32(mh), ctypes.byref(nodes), ctypes.byref(complete),
+                              ctypes.byref(rb))
+    elif order == "btf":
+        from .ordering import btf_order
+        og = np.array(btf_order(G) or [0], np.int32)
+        oh = np.array(btf_order(H) or [0], np.int32)
+        size = lib.oracle_mcs_ordered(ctypes.byref(cg), ctypes.byref(ch), _p32(og), _p32(oh),
+                                      int(node_limit), _p32(mg), _p32(mh),
+                                      ctypes.byref(nodes), ctypes.byref(complete),
+                                      ctypes.byref(rb))
+    else:
+        raise ValueError(f"unknown order {order!r}")
     return {"size": int(size), "map": [(int(mg[i]), int(mh[i])) for i in range(size)],
             "nodes": int(nodes.value), "complete": bool(complete.value),
             "root_bound": int(rb.value)}

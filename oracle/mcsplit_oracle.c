@@ -262,6 +262,9 @@ static void solve(search_ctx *s, int level, int m, const bidomain *C, int K)
 
 /* ---- set-up shared by the entry points -------------------------------- */
 
+static int ctx_init_orders(search_ctx *s, const oracle_graph *G, const oracle_graph *H,
+                           const int32_t *ordG, const int32_t *ordH);
+
 static int ctx_init(search_ctx *s, const oracle_graph *G, const oracle_graph *H, int ordered)
 {
     memset(s, 0, sizeof(*s));
@@ -293,6 +296,23 @@ static int ctx_init(search_ctx *s, const oracle_graph *G, const oracle_graph *H,
     s->mh = (int *)malloc(sizeof(int) * (size_t)nG1);
     s->bg = (int *)malloc(sizeof(int) * (size_t)nG1);
     s->bh = (int *)malloc(sizeof(int) * (size_t)nG1);
+    return 0;
+}
+
+/* As ctx_init, with the vertex orders given (ordG[k] = the vertex of G placed
+ * at position k); used for the alternative ordering of Sec. IV.A. */
+static int ctx_init_orders(search_ctx *s, const oracle_graph *G, const oracle_graph *H,
+                           const int32_t *ordG, const int32_t *ordH)
+{
+    ctx_init(s, G, H, 0);
+    for (int i = 0; i < G->n; i++)
+        s->ordG[i] = ordG[i];
+    for (int i = 0; i < H->n; i++)
+        s->ordH[i] = ordH[i];
+    free(s->aG);
+    free(s->aH);
+    s->aG = reorder(G, s->ordG);
+    s->aH = reorder(H, s->ordH);
     return 0;
 }
 
@@ -370,12 +390,36 @@ static int root_classes(search_ctx *s, const oracle_graph *G, const oracle_graph
  * lower bound) and the root bound.  G and H must agree on directed and on
  * label presence.
  */
+static int32_t run_mcs(search_ctx *sp, const oracle_graph *G, const oracle_graph *H,
+                       int64_t node_limit, int32_t *map_g, int32_t *map_h, int64_t *nodes,
+                       int32_t *complete, int32_t *root_bound);
+
 int32_t oracle_mcs(const oracle_graph *G, const oracle_graph *H, int64_t node_limit,
                    int32_t *map_g, int32_t *map_h, int64_t *nodes, int32_t *complete,
                    int32_t *root_bound)
 {
     search_ctx s;
     ctx_init(&s, G, H, 1);
+    return run_mcs(&s, G, H, node_limit, map_g, map_h, nodes, complete, root_bound);
+}
+
+/* As oracle_mcs, with the vertex orders given instead of descending degree
+ * (ordG[k] = the vertex of G placed at position k, likewise ordH). */
+int32_t oracle_mcs_ordered(const oracle_graph *G, const oracle_graph *H, const int32_t *ordG,
+                           const int32_t *ordH, int64_t node_limit, int32_t *map_g,
+                           int32_t *map_h, int64_t *nodes, int32_t *complete,
+                           int32_t *root_bound)
+{
+    search_ctx s;
+    ctx_init_orders(&s, G, H, ordG, ordH);
+    return run_mcs(&s, G, H, node_limit, map_g, map_h, nodes, complete, root_bound);
+}
+
+static int32_t run_mcs(search_ctx *sp, const oracle_graph *G, const oracle_graph *H,
+                       int64_t node_limit, int32_t *map_g, int32_t *map_h, int64_t *nodes,
+                       int32_t *complete, int32_t *root_bound)
+{
+    search_ctx s = *sp;
     s.node_limit = node_limit;
     int K = root_classes(&s, G, H);
     if (root_bound)

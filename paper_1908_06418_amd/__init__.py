@@ -83,9 +83,14 @@ class _Marshal:
                               rows.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), lab)
 
 
-def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0, policy_mode=0):
+ORDERINGS = {"degree": 0, "btf": 1}
+
+
+def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0, policy_mode=0,
+          ordering="degree"):
     """policy: a torch half tensor of packed parameters on the device (or an
-    object with .half_params, see policy.Policy)."""
+    object with .half_params, see policy.Policy).  ordering: "degree" or
+    "btf" (mcs_opts.ordering)."""
     t = None
     tc = None
     if tuning is not None:
@@ -96,7 +101,7 @@ def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0, policy_
         hp = getattr(policy, "half_params", policy)
         ptr = ctypes.c_void_p(hp.data_ptr())
     o = _abi.mcs_opts(int(node_limit or 0), float(time_limit_s or 0.0), t, ptr,
-                      int(policy_depth), int(policy_mode))
+                      int(policy_depth), int(policy_mode), ORDERINGS[ordering])
     return o, tc
 
 
@@ -150,13 +155,13 @@ class Plan:
     (mcs_plan_run) -- inputs stay resident in HBM between runs."""
 
     def __init__(self, pairs, node_limit=0, time_limit_s=0.0, tuning=None, policy=None,
-                 policy_depth=1, policy_mode=0):
+                 policy_depth=1, policy_mode=0, ordering="degree"):
         self.lib = _abi.load()
         self.pairs = list(pairs)
         self._m = _Marshal(self.pairs)
         self._policy = policy  # keeps the device parameters alive
         self._o, self._t = _opts(node_limit, time_limit_s, tuning, policy, policy_depth,
-                                 policy_mode)
+                                 policy_mode, ordering)
         h = ctypes.c_void_p()
         st = self.lib.mcs_plan_create(len(self.pairs), self._m.G, self._m.H,
                                       ctypes.byref(self._o), ctypes.byref(h))
@@ -237,9 +242,10 @@ class Plan:
 
 
 def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=False,
-                policy=None, policy_depth=1, policy_mode=0):
+                policy=None, policy_depth=1, policy_mode=0, ordering="degree"):
     """MCS of every pair in one launch.  Returns a list of Result (and Stats)."""
-    p = Plan(pairs, node_limit, time_limit_s, tuning, policy, policy_depth, policy_mode).upload()
+    p = Plan(pairs, node_limit, time_limit_s, tuning, policy, policy_depth, policy_mode,
+             ordering).upload()
     p.run()
     res = p.results()
     st = p.stats() if with_stats else None

@@ -98,6 +98,116 @@ std::vector<int> degree_order(const mcs_graph &g) {
     return ord;
 }
 
+// The alternative order of Sec. IV.A ("graph sorting"): weak connected
+// components, a component with more non-zero rows per non-zero column first
+// (ties: the larger, then the one with the smaller first vertex; components
+// without arcs last); within a component, Hellerman-Rarick style, the
+// column meeting the most shortest active rows is taken next (ties: the
+// smaller index) and leaves the active submatrix; rows whose active length
+// reaches zero leave it too; vertices never taken follow in index order.
+static bool arc(const mcs_graph &g, int i, int j) { return (g.adj[i] >> j) & 1; }
+
+std::vector<int> btf_order(const mcs_graph &g) {
+    const int n = g.n;
+    std::vector<int> comp_of(n, -1);
+    std::vector<std::vector<int>> comps;
+    for (int s = 0; s < n; s++) {
+        if (comp_of[s] >= 0)
+            continue;
+        std::vector<int> members, todo{s};
+        comp_of[s] = (int)comps.size();
+        while (!todo.empty()) {
+            int u = todo.back();
+            todo.pop_back();
+            members.push_back(u);
+            for (int x = 0; x < n; x++)
+                if (comp_of[x] < 0 && (arc(g, u, x) || arc(g, x, u))) {
+                    comp_of[x] = comp_of[s];
+                    todo.push_back(x);
+                }
+        }
+        std::sort(members.begin(), members.end());
+        comps.push_back(members);
+    }
+    struct Key {
+        int no_arcs;
+        double neg_ratio;
+        int neg_size, first, idx;
+    };
+    std::vector<Key> keys;
+    for (int c = 0; c < (int)comps.size(); c++) {
+        const std::vector<int> &m = comps[c];
+        int nzr = 0, nzc = 0;
+        for (int u : m) {
+            bool r = false, col = false;
+            for (int x : m) {
+                r = r || arc(g, u, x);
+                col = col || arc(g, x, u);
+            }
+            nzr += r;
+            nzc += col;
+        }
+        keys.push_back({nzr == 0 ? 1 : 0, nzr == 0 ? 0.0 : -(double)nzr / nzc,
+                        nzr == 0 ? 0 : -(int)m.size(), m[0], c});
+    }
+    std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) {
+        if (a.no_arcs != b.no_arcs)
+            return a.no_arcs < b.no_arcs;
+        if (a.neg_ratio != b.neg_ratio)
+            return a.neg_ratio < b.neg_ratio;
+        if (a.neg_size != b.neg_size)
+            return a.neg_size < b.neg_size;
+        return a.first < b.first;
+    });
+    std::vector<int> ord;
+    for (const Key &k : keys) {
+        const std::vector<int> &m = comps[k.idx];
+        std::vector<char> row_on(n, 0), col_on(n, 0), taken(n, 0);
+        for (int u : m)
+            for (int x : m) {
+                if (arc(g, u, x)) {
+                    row_on[u] = 1;
+                    col_on[x] = 1;
+                }
+            }
+        for (;;) {
+            int least = n + 1;
+            std::vector<int> len(n, 0);
+            for (int r : m) {
+                if (!row_on[r])
+                    continue;
+                for (int c : m)
+                    len[r] += col_on[c] && arc(g, r, c);
+                if (len[r] == 0)
+                    row_on[r] = 0;
+                else
+                    least = std::min(least, len[r]);
+            }
+            if (least > n)
+                break;  // no active row left
+            int best = -1, best_hits = -1;
+            for (int c : m) {  // ascending: ties go to the smaller index
+                if (!col_on[c])
+                    continue;
+                int hits = 0;
+                for (int r : m)
+                    hits += row_on[r] && len[r] == least && arc(g, r, c);
+                if (hits > best_hits) {
+                    best = c;
+                    best_hits = hits;
+                }
+            }
+            ord.push_back(best);
+            taken[best] = 1;
+            col_on[best] = 0;
+        }
+        for (int u : m)
+            if (!taken[u])
+                ord.push_back(u);
+    }
+    return ord;
+}
+
 // rows of the relabelled graph: vertex p is original ord[p]
 std::vector<uint64_t> permuted_rows(const mcs_graph &g, const std::vector<int> &ord) {
     std::vector<uint64_t> rows(g.n, 0);
@@ -132,6 +242,7 @@ struct mcs_plan {
     double time_limit_s = 600.0;
     const uint16_t *policy = nullptr;
     int policy_depth = 0, policy_levels = 0, policy_mode = 0;
+    int ordering = 0;  // 0: descending degree; 1: components, block-triangular (Sec. IV.A)
 
     std::vector<mcs::DevInst> inst;
     std::vector<uint8_t> adj;      // packed rows, word_bytes each
@@ -271,6 +382,11 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
             p->policy_levels = opts->policy_depth + 1;
         }
         p->node_limit = opts->node_limit > 0 ? opts->node_limit : 0;
+        if (opts->ordering < 0 || opts->ordering > 1) {
+            delete p;
+            return fail(MCS_E_INVALID, "ordering must be 0 (degree) or 1 (block-triangular)");
+        }
+        p->ordering = opts->ordering;
         if (opts->time_limit_s > 0)
             p->time_limit_s = opts->time_limit_s;
     }
@@ -289,8 +405,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     size_t map_off = 0;
     for (int i = 0; i < count; i++) {
         const mcs_graph &g = G[i], &h = H[i];
-        p->ordG[i] = degree_order(g);
-        p->ordH[i] = degree_order(h);
+        p->ordG[i] = p->ordering == 1 ? btf_order(g) : degree_order(g);
+        p->ordH[i] = p->ordering == 1 ? btf_order(h) : degree_order(h);
         std::vector<uint64_t> rg = permuted_rows(g, p->ordG[i]);
         std::vector<uint64_t> rh = permuted_rows(h, p->ordH[i]);
         std::vector<std::vector<uint64_t>> sets = {rg, rh};

@@ -159,3 +159,19 @@ def test_root_bounds_host(mcs_lib):
     assert mcs_lib.mcs_plan_root_bounds(h, out) == 0
     assert list(out) == [7, 1 + 2 + 1, 0]
     mcs_lib.mcs_plan_destroy(h)
+
+
+def test_ordering_option_validated(mcs_lib):
+    """mcs_opts.ordering takes 0 (degree) or 1 (block-triangular); anything
+    else is rejected before any device work."""
+    from paper_1908_06418_amd import _Marshal, _abi, _opts
+    m = _Marshal([(mi.er_graph(10, 0.3, 1), mi.er_graph(10, 0.3, 2))])
+    h = ctypes.c_void_p()
+    for ordering, status in ((0, _abi.MCS_OK), (1, _abi.MCS_OK), (2, _abi.MCS_E_INVALID),
+                             (-1, _abi.MCS_E_INVALID)):
+        o, _t = _opts(0, 0.0, None)
+        o.ordering = ordering
+        st = mcs_lib.mcs_plan_create(1, m.G, m.H, ctypes.byref(o), ctypes.byref(h))
+        assert st == status, (ordering, st)
+        if st == _abi.MCS_OK:
+            mcs_lib.mcs_plan_destroy(h)

@@ -73,6 +73,36 @@ def test_single_wave_reproduces_oracle_node_count(gpu, kind):
         assert oracle.check.is_valid(G, H, r.mapping)
 
 
+@pytest.mark.parametrize("kind", ["undirected", "directed", "labelled"])
+def test_block_triangular_order_matches_oracle(gpu, kind):
+    """The alternative order of Sec. IV.A (mcs_opts.ordering = 1): the host
+    library's implementation and the oracle's (oracle/ordering.py, written
+    separately from the paper) induce the same search -- one wavefront
+    expands exactly the oracle's node count under that order -- and sizes
+    equal the degree order's.  Sparse pairs, so that several components
+    occur."""
+    from paper_1908_06418_amd import solve_batch
+    rng = np.random.default_rng({"undirected": 21, "directed": 22, "labelled": 23}[kind])
+    directed = kind == "directed"
+    nlab = 3 if kind == "labelled" else 0
+    pairs = []
+    for i in range(16):
+        n1, n2 = int(rng.integers(4, 21)), int(rng.integers(4, 21))
+        p = float(rng.uniform(0.05, 0.5))
+        pairs.append((mi.random_small(rng, n1, p, directed, nlab),
+                      mi.random_small(rng, n2, p, directed, nlab)))
+    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1}
+    _say(f"block-triangular order, {kind}: {len(pairs)} pairs")
+    res = solve_batch(pairs, tuning=tun, time_limit_s=60, ordering="btf")
+    for (G, H), r in zip(pairs, res):
+        o = oracle.mcs(G, H, order="btf")
+        assert r.optimal and r.size == o["size"] == oracle.mcs(G, H)["size"]
+        assert r.nodes == o["nodes"], (r.nodes, o["nodes"])
+        assert oracle.check.is_valid(G, H, r.mapping)
+    batched = solve_batch(pairs, time_limit_s=60, ordering="btf")
+    assert [r.size for r in batched] == [r.size for r in res]
+
+
 @pytest.mark.parametrize("directed,nlab", [(False, 0), (True, 0), (False, 4), (True, 3)])
 def test_random_sweep_batched(gpu, directed, nlab):
     """Random pairs of every size from 0 to 24 vertices and densities 0..1,
@@ -387,4 +417,32 @@ def test_batched_vs_one_at_a_time_report(gpu):
     _say("batch report: " + json.dumps(report))
     os.makedirs("gpurun_out", exist_ok=True)
     with open(os.path.join("gpurun_out", "batch_report.json"), "w") as f:
+        json.dump(report, f, indent=1)
+
+
+def test_ordering_report(gpu):
+    """Nodes and kernel time under the two static orders of Sec. IV.A, on the
+    60 pairs G(30,p) and the 60 directed labelled pairs: equal sizes; the
+    comparison is written to gpurun_out/ordering_report.json."""
+    from paper_1908_06418_amd import Plan
+    report = {}
+    for name, pairs in (("c2_n30", mi.pairs_c2(ns=(30,))), ("c3", mi.pairs_c3())):
+        sizes = {}
+        for ordering in ("degree", "btf"):
+            plan = Plan(pairs, time_limit_s=120, ordering=ordering).upload()
+            best = None
+            for _ in range(2):
+                plan.run()
+                res = plan.results()
+                st = plan.stats()
+                best = st.kernel_ms if best is None else min(best, st.kernel_ms)
+            plan.close()
+            assert all(r.optimal for r in res)
+            sizes[ordering] = [r.size for r in res]
+            report[f"{name}_{ordering}"] = {"kernel_ms": best, "nodes": st.nodes}
+            _say(f"ordering {name} {ordering}: {best:.1f} ms, {st.nodes} nodes")
+        assert sizes["degree"] == sizes["btf"]
+    _say("ordering report: " + json.dumps(report))
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "ordering_report.json"), "w") as f:
         json.dump(report, f, indent=1)
