@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "search nodes/sec + MCS instances/sec (batched) at exact size match"
 PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: int32 lane-ops/s
+PEAK_LDS_BYTES = 256 * 128 * 2.4e9     # CUs x 128 bytes per clock x clock: LDS bytes/s
+PEAK_HBM_BYTES = 8e12
 
 # HBM bytes per launch of the search kernel, from the copy-calibrated
 # FETCH_SIZE / WRITE_SIZE runs recorded in profiles/ (see the design doc); reported
@@ -184,6 +186,7 @@ def main():
     nodes = 0
     kernel_ms = 0.0
     lane_slots = batches = children = 0
+    lds_bytes = 0
     proven = 0
     busy = []
     t_best, t_proof = [], []
@@ -194,6 +197,7 @@ def main():
         nodes += st.nodes
         kernel_ms += st.kernel_ms
         lane_slots += st.lane_slots
+        lds_bytes += st.lds_bytes
         batches += st.batches
         children += st.children
         proven += sum(r.optimal for r in res)
@@ -250,6 +254,19 @@ def main():
                      "kernel": "mcs_search_kernel",
                      "per_unit": f"{OPS_PER_CLASS[(word, directed)]} int32 lane-ops per class "
                                  "per evaluated child"},
+    }
+    traffic = line["roofline"]["traffic"]
+    line["bandwidth"] = {
+        "lds": {"achieved_GBps": lds_bytes / kern_s / 1e9 if kern_s else 0.0,
+                "peak_GBps": PEAK_LDS_BYTES / 1e9,
+                "frac": lds_bytes / kern_s / PEAK_LDS_BYTES if kern_s else 0.0,
+                "bytes": "algorithmic: adjacency rows per child batch, classes, header and "
+                         "mapping entry per pushed frame, classes and header per frame load "
+                         "(kernel counter)"},
+        "hbm": {"achieved_GBps": traffic * K / kern_s / 1e9 if traffic and kern_s else None,
+                "peak_GBps": PEAK_HBM_BYTES / 1e9,
+                "frac": traffic * K / kern_s / PEAK_HBM_BYTES if traffic and kern_s else None,
+                "bytes": "FETCH_SIZE + WRITE_SIZE per launch, copy-calibrated (profiles/)"},
     }
     plan.close()
     if not args.no_cpu_baseline:

@@ -163,6 +163,11 @@ typedef struct {
     int32_t max_stack_used;    /* most classes any wavefront's stack held */
     double sleep_wave_s;       /* wavefront-seconds idle wavefronts spent in
                                   back-off sleeps (part of the time not busy) */
+    int64_t lds_bytes;         /* algorithmic bytes through LDS: the adjacency
+                                  rows each child batch reads; the classes,
+                                  header and mapping entry of each pushed
+                                  frame; the classes (and header) read back
+                                  when a frame is loaded */
 } mcs_stats;
 
 typedef struct mcs_plan mcs_plan;

@@ -140,6 +140,7 @@ class Stats:
     stack_classes: int = 0
     max_stack_used: int = 0
     sleep_wave_s: float = 0.0
+    lds_bytes: int = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -227,7 +228,7 @@ class Plan:
                      int(s.donations), int(s.pops), int(s.waves), int(s.blocks),
                      int(s.lds_per_wave), int(s.stopped), float(s.kernel_ms),
                      float(s.busy_wave_s), int(s.spills), int(s.stack_classes),
-                     int(s.max_stack_used), float(s.sleep_wave_s))
+                     int(s.max_stack_used), float(s.sleep_wave_s), int(s.lds_bytes))
 
     def close(self):
         if getattr(self, "handle", None):

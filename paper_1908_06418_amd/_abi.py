@@ -56,7 +56,8 @@ class mcs_stats(ctypes.Structure):
                 ("lds_per_wave", ctypes.c_int32), ("stopped", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("busy_wave_s", ctypes.c_double),
                 ("spills", ctypes.c_int64), ("stack_classes", ctypes.c_int32),
-                ("max_stack_used", ctypes.c_int32), ("sleep_wave_s", ctypes.c_double)]
+                ("max_stack_used", ctypes.c_int32), ("sleep_wave_s", ctypes.c_double),
+                ("lds_bytes", ctypes.c_int64)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/mcs.h

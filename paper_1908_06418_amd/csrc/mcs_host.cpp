@@ -837,6 +837,7 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     z.busy_wave_s = (double)p->h_glob.busy_ticks / p->tick_hz;
     z.spills = (int64_t)p->h_glob.spills;
     z.sleep_wave_s = (double)p->h_glob.sleep_ticks / p->tick_hz;
+    z.lds_bytes = (int64_t)p->h_glob.lds_bytes;
     z.stack_classes = p->cap_classes;
     z.max_stack_used = p->h_glob.max_stack;
     *st = z;
