@@ -260,9 +260,9 @@ def main():
         "lds": {"achieved_GBps": lds_bytes / kern_s / 1e9 if kern_s else 0.0,
                 "peak_GBps": PEAK_LDS_BYTES / 1e9,
                 "frac": lds_bytes / kern_s / PEAK_LDS_BYTES if kern_s else 0.0,
-                "bytes": "algorithmic: adjacency rows per child batch, classes, header and "
-                         "mapping entry per pushed frame, classes and header per frame load "
-                         "(kernel counter)"},
+                "bytes": "algorithmic: adjacency rows of v and the partners per child batch, "
+                         "and each pushed frame's classes written once and read twice "
+                         "(mcs_stats.lds_bytes, from the kernel's counters)"},
         "hbm": {"achieved_GBps": traffic * K / kern_s / 1e9 if traffic and kern_s else None,
                 "peak_GBps": PEAK_HBM_BYTES / 1e9,
                 "frac": traffic * K / kern_s / PEAK_HBM_BYTES if traffic and kern_s else None,

@@ -164,10 +164,10 @@ typedef struct {
     double sleep_wave_s;       /* wavefront-seconds idle wavefronts spent in
                                   back-off sleeps (part of the time not busy) */
     int64_t lds_bytes;         /* algorithmic bytes through LDS: the adjacency
-                                  rows each child batch reads; the classes,
-                                  header and mapping entry of each pushed
-                                  frame; the classes (and header) read back
-                                  when a frame is loaded */
+                                  rows each child batch reads (v's and its
+                                  partners'), and the classes of each pushed
+                                  frame, written once and read twice (headers
+                                  and mapping entries are not counted) */
 } mcs_stats;
 
 typedef struct mcs_plan mcs_plan;

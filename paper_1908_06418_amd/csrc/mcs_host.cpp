@@ -837,7 +837,15 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     z.busy_wave_s = (double)p->h_glob.busy_ticks / p->tick_hz;
     z.spills = (int64_t)p->h_glob.spills;
     z.sleep_wave_s = (double)p->h_glob.sleep_ticks / p->tick_hz;
-    z.lds_bytes = (int64_t)p->h_glob.lds_bytes;
+    // Algorithmic LDS bytes: each child batch reads the rows of v and of
+    // its C partners (one word each, two when directed); each pushed frame's
+    // classes (L and R words) are written once and read twice (at the descent
+    // and when the search returns to the frame).
+    {
+        const int64_t rows = (int64_t)p->h_glob.batches + (int64_t)p->h_glob.children;
+        const int rw = (p->directed ? 2 : 1) * p->word_bytes;
+        z.lds_bytes = rows * rw + (int64_t)p->h_glob.pushed_classes * 3 * 2 * p->word_bytes;
+    }
     z.stack_classes = p->cap_classes;
     z.max_stack_used = p->h_glob.max_stack;
     *st = z;

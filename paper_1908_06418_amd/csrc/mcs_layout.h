@@ -62,7 +62,7 @@ struct DevGlobals {
     unsigned long long busy_ticks;  // realtime ticks wavefronts spent searching
     unsigned long long spills;      // children queued for want of stack room
     unsigned long long sleep_ticks; // realtime ticks idle wavefronts spent sleeping
-    unsigned long long lds_bytes;   // algorithmic bytes the search moved through LDS
+    unsigned long long pushed_classes;  // classes in the frames pushed onto LDS stacks
     int max_stack;                  // most classes any wavefront's stack held
     int pad1;
 };

@@ -276,11 +276,10 @@ struct Searcher {
     // per-step counts since the last fold into the 64-bit totals (at most
     // check_interval steps, so 32 bits cannot overflow)
     uint32_t c_nodes, c_batches, c_children, c_lanes;
-    // algorithmic bytes through LDS since the last fold: adjacency rows read
-    // by each batch, classes, header and mapping entry written at a push,
-    // classes (and a header at a pop) read back when a frame is loaded
-    uint32_t c_ldsb;
-    unsigned long long n_ldsb;
+    // classes in frames pushed since the last fold (the host turns this and
+    // the batch counts into the bytes the search moves through LDS)
+    uint32_t c_pushed;
+    unsigned long long n_pushed;
 
     __device__ Searcher(const SearchParams &p, uint8_t *lds) : P(p) {
         lane = lane_id();
@@ -306,8 +305,8 @@ struct Searcher {
         d0 = 0;
         since_check = 0;
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = n_busy = 0;
-        c_nodes = c_batches = c_children = c_lanes = c_ldsb = 0;
-        n_ldsb = 0;
+        c_nodes = c_batches = c_children = c_lanes = c_pushed = 0;
+        n_pushed = 0;
         n_spill = n_sleep = 0;
         max_used = 0;
         inc = 0;
@@ -722,7 +721,6 @@ struct Searcher {
         const int fb = sb ? rl(b, ctz(sb)) : 0;
         c_nodes += (uint32_t)(C - nsurv + (nsurv ? 1 : 0));
         c_batches += 1;
-        c_ldsb += (uint32_t)((1 + C) * (NR / 2) * (int)sizeof(W));  // rows of v and the w's
         c_children += (uint32_t)C;
         c_lanes += (uint32_t)(C * K);
 
@@ -799,8 +797,7 @@ struct Searcher {
             improve(d + 1);
         if (K2 == 0)
             return;  // a leaf: nothing left to split
-        // pushed: K2 classes, a header and a mapping entry; then loaded back
-        c_ldsb += (uint32_t)(2 * K2 * 2 * (int)sizeof(W) + 4 * kHdrWords + 2);
+        c_pushed += (uint32_t)K2;
         t += 1;
         base = nb;
         K = K2;
@@ -858,7 +855,6 @@ struct Searcher {
             if (rrem == 0 && !(flags & kFlagUnmatched))
                 continue;
             load_regs();
-            c_ldsb += (uint32_t)(K * 2 * (int)sizeof(W) + 4 * kHdrWords);
             return true;
         }
     }
@@ -1167,8 +1163,8 @@ struct Searcher {
         n_batches += c_batches;
         n_children += c_children;
         n_lanes += c_lanes;
-        n_ldsb += c_ldsb;
-        c_nodes = c_batches = c_children = c_lanes = c_ldsb = 0;
+        n_pushed += c_pushed;
+        c_nodes = c_batches = c_children = c_lanes = c_pushed = 0;
     }
 
     __device__ void flush_nodes() {
@@ -1328,7 +1324,7 @@ struct Searcher {
             a_add64(&P.g->pops, n_pops);
             a_add64(&P.g->busy_ticks, n_busy);
             a_add64(&P.g->spills, n_spill);
-            a_add64(&P.g->lds_bytes, n_ldsb);
+            a_add64(&P.g->pushed_classes, n_pushed);
             a_add64(&P.g->sleep_ticks, n_sleep);
             __hip_atomic_fetch_max(&P.g->max_stack, max_used, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
