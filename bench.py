@@ -30,10 +30,11 @@ PEAK_LDS_BYTES = 256 * 128 * 2.4e9     # CUs x 128 bytes per clock x clock: LDS 
 PEAK_HBM_BYTES = 8e12
 
 # HBM bytes per launch of the search kernel, from the copy-calibrated
-# FETCH_SIZE / WRITE_SIZE runs recorded in profiles/ (see the design doc); reported
-# only while the kernel source is the one those counters were taken on.
+# FETCH_SIZE / WRITE_SIZE runs recorded in profiles/; reported only while the
+# kernel code (comments aside, code_hash) is the one those counters were
+# taken on.
 TRAFFIC = {
-    "c2": {"kernel_sha256_16": "a1991e0ab4a6555a",
+    "c2": {"kernel_code_hash": "763d29686f73d405",
            "bytes": int((30959497.4375 * 2 + 47339730.28125) * 1024),
            "profile": "profiles/mcs_search_kernel_c2.md"},
 }
@@ -61,16 +62,29 @@ def workloads():
     }
 
 
-def kernel_hash() -> str:
+def code_hash(text: str) -> str:
+    """sha256 (first 16 hex) of source text with // comments, trailing
+    blanks and empty lines removed: edits to comments keep it, edits to
+    code do not."""
     import hashlib
+    import re
+    lines = []
+    for line in text.splitlines():
+        line = re.sub(r"//.*$", "", line).rstrip()
+        if line:
+            lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
+def kernel_hash() -> str:
     path = os.path.join(ROOT, "paper_1908_06418_amd", "csrc", "mcs_search.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(path) as f:
+        return code_hash(f.read())
 
 
 def traffic_for(workload: str, launches: int):
     t = TRAFFIC.get(workload)
-    if not t or t["kernel_sha256_16"] != kernel_hash():
+    if not t or t["kernel_code_hash"] != kernel_hash():
         return None
     return t["bytes"] * launches
 

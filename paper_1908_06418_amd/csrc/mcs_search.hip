@@ -19,8 +19,13 @@
 //   * A surviving child's classes are compacted (ballot + mbcnt) into the
 //     wave's LDS stack.  Stack frames hold the classes of each open node on
 //     the current path; the "v unmatched" child rewrites its parent frame in
-//     place, so the stack never needs more than m(m+1)/2 classes
-//     (m = min(|V_G|, |V_H|)).
+//     place, so m(m+1)/2 classes (m = min(|V_G|, |V_H|)) is the worst case.
+//     The host may size the stack below that to fit more wavefronts per CU;
+//     a child that does not fit goes to the node queue as a fresh record.
+//   * Frame headers are one 32-bit word per field, written from the lanes of
+//     one register (v_writelane) and read back by readlane; stores that only
+//     some lanes have data for send the others to a trash slot instead of
+//     branching on the exec mask (the scalar unit is the busiest one).
 //   * Work sharing: bounded lock-free rings of node records in HBM (Vyukov
 //     sequence numbers), one per XCD.  A busy wave keeps its XCD's ring
 //     stocked: when its periodic check finds fewer than a few records
