@@ -40,8 +40,9 @@ TRAFFIC = {
 }
 
 # Algorithmic 32-bit lane operations per class per evaluated child: remove v
-# and w, split L and R by the adjacency letters, popcount every part, min()
-# per letter and the sum of Eq. 1 ("Roofline").
+# and w (2), split L and R by the adjacency letters (4; directed 16), popcount
+# every part (4; 8), min() per letter (2; 4) and add into Eq. 1 (2; 4):
+# 14 undirected, 34 directed; 64-bit words double the and/popcount work.
 OPS_PER_CLASS = {(4, False): 14, (8, False): 24, (4, True): 34, (8, True): 60}
 
 
