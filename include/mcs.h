@@ -52,14 +52,18 @@ typedef enum {
                              mcs_tuning.ring_slots or stack_classes */
 } mcs_status;
 
-#define MCS_MAX_N 64
+#define MCS_MAX_N 128
 
-/* One graph.  adj holds n rows of 64-bit words: bit j of adj[i] is set iff
- * the arc i -> j exists.  Undirected graphs must be symmetric.  No self loops
- * (diagonal bits) and no bits at or above n.  label is NULL (unlabelled) or n
- * vertex labels; G and H of a pair must agree on directed and on labelled.
- * One batch may mix directed and undirected pairs, and labelled and
- * unlabelled ones. */
+/* One graph.  adj holds n rows of rw 64-bit words each, rw = 1 for n <= 64
+ * and 2 for 65 <= n <= 128 (rw = ceil(n / 64), at least 1): the arc i -> j
+ * exists iff bit j % 64 of adj[i * rw + j / 64] is set.  Undirected graphs
+ * must be symmetric.  No self loops (diagonal bits) and no bits at or above
+ * n.  label is NULL (unlabelled) or n vertex labels; G and H of a pair must
+ * agree on directed and on labelled.  One batch may mix directed and
+ * undirected pairs, and labelled and unlabelled ones.  The search keeps one
+ * class per lane up to 64 vertices and two per lane above (128-bit rows), so
+ * a batch whose largest graph has more than 64 vertices runs the slower
+ * wide kernel for all its pairs. */
 typedef struct {
     int32_t n;
     int32_t directed;
@@ -89,13 +93,17 @@ typedef struct {
                                   incumbent when the search returns to it */
     int32_t single_wave;       /* 1: whole search on one wavefront, in the
                                   sequential order (debugging and node-count
-                                  comparisons) */
+                                  comparisons).  Its class stack is the whole
+                                  worst case: in LDS up to 64 vertices, in
+                                  HBM with 128-bit rows */
     int32_t use_graph;         /* 1: mcs_plan_run replays a HIP graph */
-    int32_t stack_classes;     /* capacity of one wavefront's LDS class stack
+    int32_t stack_classes;     /* capacity of one wavefront's class stack
                                   (0: the worst case m(m+1)/2, m the largest
                                   min(nG, nH), or less if that keeps
                                   waves_per_cu from fitting in LDS; never
-                                  below 2m + 1).  A child that does not fit
+                                  below 2m + 1).  With 128-bit rows the
+                                  stack is in HBM and 0 means the whole
+                                  worst case.  A child that does not fit
                                   goes to the node queue as a record. */
     int32_t backoff_max;       /* an idle wavefront that finds no work sleeps
                                   1, 2, 4, ... up to this many times about
@@ -108,7 +116,8 @@ typedef struct {
     const mcs_tuning *tuning;  /* NULL: all defaults */
     const uint16_t *policy;    /* device pointer, 16-byte aligned, to the learned
                                   branching policy's half-precision parameters
-                                  (mcs_policy_pack_half), or NULL: branch on the
+                                  (mcs_policy_pack_half; graphs of at most 64
+                                  vertices, else MCS_E_INVALID), or NULL: branch on the
                                   smallest vertex index
                                   (descending degree) and try partners in index
                                   order */

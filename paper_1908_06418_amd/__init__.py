@@ -70,9 +70,12 @@ class _Marshal:
 
     def _graph(self, g) -> _abi.mcs_graph:
         n = int(g["n"])
-        rows = np.zeros(max(n, 1), dtype=np.uint64)
+        # rw 64-bit words per row: one up to 64 vertices, ceil(n / 64) above
+        rw = 1 if n <= 64 else (n + 63) // 64
+        rows = np.zeros(max(n, 1) * rw, dtype=np.uint64)
         for i, r in enumerate(g["rows"][:max(n, 0)]):
-            rows[i] = np.uint64(int(r) & 0xFFFFFFFFFFFFFFFF)
+            for k in range(rw):
+                rows[i * rw + k] = np.uint64((int(r) >> (64 * k)) & 0xFFFFFFFFFFFFFFFF)
         self.keep.append(rows)
         lab = None
         if g.get("label") is not None:

@@ -15,7 +15,7 @@ MCS_E_DEVICE = -3
 MCS_E_WORKSPACE = -4
 MCS_E_INTERNAL = -5
 MCS_E_QUEUE_FULL = -6
-MCS_MAX_N = 64
+MCS_MAX_N = 128
 
 
 class mcs_graph(ctypes.Structure):

@@ -37,9 +37,31 @@ mcs_status hip_fail(hipError_t e, const char *what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+uint64_t low_mask(int n) { return n >= 64 ? ~0ull : n <= 0 ? 0ull : ((1ull << n) - 1); }
 
-uint64_t low_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1); }
+// 64-bit words per adjacency row of the caller's graph: one up to 64
+// vertices, then one more per 64 vertices.
+int row_words(int n) { return n <= 64 ? 1 : (n + 63) / 64; }
+
+// Arc i -> j of the caller's graph (bit j % 64 of word j / 64 of row i).
+bool in_arc(const mcs_graph &g, int i, int j) {
+    return (g.adj[(size_t)i * row_words(g.n) + (j >> 6)] >> (j & 63)) & 1;
+}
+
+// A vertex set (a row or one side of a class) of up to 128 vertices.
+struct Bits {
+    uint64_t w[2] = {0, 0};
+    void set(int j) { w[j >> 6] |= 1ull << (j & 63); }
+    bool get(int j) const { return (w[j >> 6] >> (j & 63)) & 1; }
+    bool any() const { return (w[0] | w[1]) != 0; }
+};
+
+Bits first_n(int n) {
+    Bits b;
+    b.w[0] = low_mask(n);
+    b.w[1] = low_mask(n - 64);
+    return b;
+}
 
 // Checks one graph; returns MCS_OK or an error with a message.
 mcs_status validate(const mcs_graph &g, const char *which, int idx) {
@@ -61,20 +83,20 @@ mcs_status validate(const mcs_graph &g, const char *which, int idx) {
         snprintf(buf, sizeof buf, "%s[%d]: directed must be 0 or 1", which, idx);
         return fail(MCS_E_INVALID, buf);
     }
-    const uint64_t keep = low_mask(g.n);
+    const int rw = row_words(g.n);
     for (int i = 0; i < g.n; i++) {
-        uint64_t r = g.adj[i];
-        if (r & ~keep) {
-            snprintf(buf, sizeof buf, "%s[%d]: row %d has bits at or above n", which, idx, i);
-            return fail(MCS_E_INVALID, buf);
-        }
-        if ((r >> i) & 1) {
+        for (int k = 0; k < rw; k++)
+            if (g.adj[(size_t)i * rw + k] & ~low_mask(g.n - 64 * k)) {
+                snprintf(buf, sizeof buf, "%s[%d]: row %d has bits at or above n", which, idx, i);
+                return fail(MCS_E_INVALID, buf);
+            }
+        if (in_arc(g, i, i)) {
             snprintf(buf, sizeof buf, "%s[%d]: self loop at vertex %d", which, idx, i);
             return fail(MCS_E_INVALID, buf);
         }
         if (!g.directed)
             for (int j = 0; j < g.n; j++)
-                if (((r >> j) & 1) != ((g.adj[j] >> i) & 1)) {
+                if (in_arc(g, i, j) != in_arc(g, j, i)) {
                     snprintf(buf, sizeof buf, "%s[%d]: undirected graph is not symmetric at (%d,%d)",
                              which, idx, i, j);
                     return fail(MCS_E_INVALID, buf);
@@ -86,12 +108,9 @@ mcs_status validate(const mcs_graph &g, const char *which, int idx) {
 // Descending degree (out + in when directed), ties by index (Sec. IV.A).
 std::vector<int> degree_order(const mcs_graph &g) {
     std::vector<int> deg(g.n, 0), ord(g.n);
-    for (int i = 0; i < g.n; i++) {
-        deg[i] = popcount64(g.adj[i]);
-        if (g.directed)
-            for (int j = 0; j < g.n; j++)
-                deg[i] += (int)((g.adj[j] >> i) & 1);
-    }
+    for (int i = 0; i < g.n; i++)
+        for (int j = 0; j < g.n; j++)
+            deg[i] += (int)in_arc(g, i, j) + (g.directed ? (int)in_arc(g, j, i) : 0);
     for (int i = 0; i < g.n; i++)
         ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return deg[a] > deg[b]; });
@@ -105,7 +124,7 @@ std::vector<int> degree_order(const mcs_graph &g) {
 // column meeting the most shortest active rows is taken next (ties: the
 // smaller index) and leaves the active submatrix; rows whose active length
 // reaches zero leave it too; vertices never taken follow in index order.
-static bool arc(const mcs_graph &g, int i, int j) { return (g.adj[i] >> j) & 1; }
+static bool arc(const mcs_graph &g, int i, int j) { return in_arc(g, i, j); }
 
 std::vector<int> btf_order(const mcs_graph &g) {
     const int n = g.n;
@@ -209,22 +228,22 @@ std::vector<int> btf_order(const mcs_graph &g) {
 }
 
 // rows of the relabelled graph: vertex p is original ord[p]
-std::vector<uint64_t> permuted_rows(const mcs_graph &g, const std::vector<int> &ord) {
-    std::vector<uint64_t> rows(g.n, 0);
+std::vector<Bits> permuted_rows(const mcs_graph &g, const std::vector<int> &ord) {
+    std::vector<Bits> rows(g.n);
     for (int p = 0; p < g.n; p++)
         for (int q = 0; q < g.n; q++)
-            if ((g.adj[ord[p]] >> ord[q]) & 1)
-                rows[p] |= 1ull << q;
+            if (in_arc(g, ord[p], ord[q]))
+                rows[p].set(q);
     return rows;
 }
 
-std::vector<uint64_t> transpose_rows(const std::vector<uint64_t> &rows) {
+std::vector<Bits> transpose_rows(const std::vector<Bits> &rows) {
     int n = (int)rows.size();
-    std::vector<uint64_t> t(n, 0);
+    std::vector<Bits> t(n);
     for (int i = 0; i < n; i++)
         for (int j = 0; j < n; j++)
-            if ((rows[i] >> j) & 1)
-                t[j] |= 1ull << i;
+            if (rows[i].get(j))
+                t[j].set(i);
     return t;
 }
 
@@ -245,7 +264,7 @@ struct mcs_plan {
     int ordering = 0;  // 0: descending degree; 1: components, block-triangular (Sec. IV.A)
 
     std::vector<mcs::DevInst> inst;
-    std::vector<uint8_t> adj;      // packed rows, word_bytes each
+    std::vector<uint8_t> adj;      // packed rows, word_bytes each (4, 8 or 16)
     std::vector<uint8_t> rootcls;  // packed (L, R) pairs
     std::vector<std::vector<int>> ordG, ordH;
     std::vector<int> m;            // min(nG, nH) per instance
@@ -256,6 +275,7 @@ struct mcs_plan {
     // device layout
     size_t off_inst = 0, off_adj = 0, off_cls = 0, off_inc = 0, off_open = 0, off_nodes = 0,
            off_tbest = 0, off_tproof = 0, off_maps = 0, off_glob = 0, off_seq = 0, off_slots = 0,
+           off_hstack = 0, hstack_stride = 0,
            ws_bytes = 0;
     int ring_slots = 0, slot_bytes = 0, cap_classes = 0, frames = 0, lds_per_wave = 0;
     int waves_per_block = 4, blocks = 0, waves = 0, lds_per_block = 0;
@@ -299,11 +319,15 @@ void put_word(std::vector<uint8_t> &buf, uint64_t x) {
     buf.insert(buf.end(), p, p + sizeof(W));
 }
 
-void pack_word(std::vector<uint8_t> &buf, int word_bytes, uint64_t x) {
-    if (word_bytes == 4)
-        put_word<uint32_t>(buf, x);
-    else
-        put_word<uint64_t>(buf, x);
+// One row word as the kernels read it: 32, 64 or 128 bits (low half first).
+void pack_word(std::vector<uint8_t> &buf, int word_bytes, const Bits &x) {
+    if (word_bytes == 4) {
+        put_word<uint32_t>(buf, x.w[0]);
+    } else {
+        put_word<uint64_t>(buf, x.w[0]);
+        if (word_bytes == 16)
+            put_word<uint64_t>(buf, x.w[1]);
+    }
 }
 
 int next_pow2(int x) {
@@ -393,7 +417,11 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     int nmax = 0;
     for (int i = 0; i < count; i++)
         nmax = std::max(nmax, std::max(G[i].n, H[i].n));
-    p->word_bytes = nmax <= 32 ? 4 : 8;
+    p->word_bytes = nmax <= 32 ? 4 : nmax <= 64 ? 8 : 16;
+    if (p->policy && p->word_bytes > 8) {
+        delete p;
+        return fail(MCS_E_INVALID, "the learned policy takes graphs of at most 64 vertices");
+    }
     const int NB = 8 * p->word_bytes;
     const int R = directed ? 4 : 2;
 
@@ -407,23 +435,23 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         const mcs_graph &g = G[i], &h = H[i];
         p->ordG[i] = p->ordering == 1 ? btf_order(g) : degree_order(g);
         p->ordH[i] = p->ordering == 1 ? btf_order(h) : degree_order(h);
-        std::vector<uint64_t> rg = permuted_rows(g, p->ordG[i]);
-        std::vector<uint64_t> rh = permuted_rows(h, p->ordH[i]);
-        std::vector<std::vector<uint64_t>> sets = {rg, rh};
+        std::vector<Bits> rg = permuted_rows(g, p->ordG[i]);
+        std::vector<Bits> rh = permuted_rows(h, p->ordH[i]);
+        std::vector<std::vector<Bits>> sets = {rg, rh};
         if (directed) {
             sets.push_back(transpose_rows(rg));
             sets.push_back(transpose_rows(rh));
         }
         for (int s = 0; s < R; s++)
             for (int j = 0; j < NB; j++)
-                pack_word(p->adj, p->word_bytes, j < (int)sets[s].size() ? sets[s][j] : 0);
+                pack_word(p->adj, p->word_bytes, j < (int)sets[s].size() ? sets[s][j] : Bits{});
 
         // root classes
         int K0 = 0;
         if (g.n > 0 && h.n > 0) {
             if (!g.label) {
-                pack_word(p->rootcls, p->word_bytes, low_mask(g.n));
-                pack_word(p->rootcls, p->word_bytes, low_mask(h.n));
+                pack_word(p->rootcls, p->word_bytes, first_n(g.n));
+                pack_word(p->rootcls, p->word_bytes, first_n(h.n));
                 K0 = 1;
             } else {
                 std::vector<int> seen;
@@ -432,14 +460,14 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
                     if (std::find(seen.begin(), seen.end(), lab) != seen.end())
                         continue;
                     seen.push_back(lab);
-                    uint64_t L = 0, Rm = 0;
+                    Bits L, Rm;
                     for (int b = 0; b < g.n; b++)
                         if (g.label[p->ordG[i][b]] == lab)
-                            L |= 1ull << b;
+                            L.set(b);
                     for (int b = 0; b < h.n; b++)
                         if (h.label[p->ordH[i][b]] == lab)
-                            Rm |= 1ull << b;
-                    if (!Rm)
+                            Rm.set(b);
+                    if (!Rm.any())
                         continue;
                     pack_word(p->rootcls, p->word_bytes, L);
                     pack_word(p->rootcls, p->word_bytes, Rm);
@@ -486,7 +514,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         map_off += (size_t)mi * (mi + 1) / 2;
     }
     if (p->rootcls.empty())
-        pack_word(p->rootcls, p->word_bytes, 0), pack_word(p->rootcls, p->word_bytes, 0);
+        pack_word(p->rootcls, p->word_bytes, Bits{}), pack_word(p->rootcls, p->word_bytes, Bits{});
     p->map_pairs = std::max<size_t>(map_off, 1);
     // The worst case of the depth-first class stack: frame t holds at most
     // m - t classes.  Smaller stacks queue the children that do not fit.
@@ -514,14 +542,23 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     // and vector steps, so several per SIMD fill the issue slots while
     // there is work for them; past what the instances can keep busy, more
     // wavefronts only split the work into ever smaller donations.
-    const int want_waves = p->tun.waves_per_cu > 0
-                               ? p->tun.waves_per_cu * cus
-                               : std::max(8 * cus, std::min(24 * cus, 96 * count));
+    const bool wide = p->word_bytes == 16;
+    const int want_waves = p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
+                           : wide ? std::max(4 * cus, std::min(8 * cus, 96 * count))
+                                  : std::max(8 * cus, std::min(24 * cus, 96 * count));
     const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
     auto per_wave = [&](int cap) {
-        return mcs::lds_layout(p->word_bytes, directed, cap, p->frames, p->policy_levels).total;
+        return mcs::lds_layout(p->word_bytes, directed, wide ? -1 : cap, p->frames,
+                               p->policy_levels).total;
     };
-    if (p->tun.single_wave) {
+    if (wide) {
+        // 128-bit rows: each wavefront's class stack is a slice of HBM
+        // holding the whole worst case (so it never overflows) unless the
+        // caller asks for a smaller one
+        p->cap_classes = p->tun.stack_classes > 0 && !p->tun.single_wave
+                             ? std::max(min_cap, std::min(full_cap, p->tun.stack_classes))
+                             : full_cap;
+    } else if (p->tun.single_wave) {
         p->cap_classes = full_cap;  // one wavefront never takes queued work back
     } else if (p->tun.stack_classes > 0) {
         p->cap_classes = std::max(min_cap, std::min(full_cap, p->tun.stack_classes));
@@ -541,7 +578,12 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     while (wpb > 1 && wpb * p->lds_per_wave > max_lds_block)
         wpb >>= 1;
     if (p->lds_per_wave > max_lds_block) {
+        const bool single = p->tun.single_wave != 0;
         delete p;
+        // only the single-wavefront mode asks for the whole worst-case stack
+        if (single)
+            return fail(MCS_E_INVALID, "single_wave needs the worst-case class stack in one "
+                                       "workgroup's LDS: min(nG, nH) is too large for it");
         return fail(MCS_E_INTERNAL, "LDS stack of one wavefront exceeds the workgroup limit");
     }
     p->waves_per_block = wpb;
@@ -569,6 +611,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         p->ring_slots = next_pow2(std::max(2, (total + mcs::kRings - 1) / mcs::kRings));
     }
     p->slot_bytes = mcs::slot_bytes_for(p->word_bytes, p->mmax);
+    if (wide)
+        p->hstack_stride = (long long)align256((size_t)(p->cap_classes + 1) * 2 * p->word_bytes);
 
     // workspace layout
     size_t o = 0;
@@ -589,6 +633,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     p->off_glob = take(sizeof(mcs::DevGlobals));
     p->off_seq = take(sizeof(unsigned long long) * mcs::kRings * p->ring_slots);
     p->off_slots = take((size_t)p->slot_bytes * mcs::kRings * p->ring_slots);
+    p->off_hstack = take((size_t)p->hstack_stride * (size_t)p->waves);
     p->ws_bytes = o;
     *out = p;
     return MCS_OK;
@@ -657,6 +702,8 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     double ticks = p->time_limit_s * p->tick_hz;
     sp.limit_ticks = ticks > 9e18 ? (unsigned long long)9e18 : (unsigned long long)ticks;
     sp.node_limit = p->node_limit;
+    sp.hstack = p->hstack_stride ? p->ws + p->off_hstack : nullptr;
+    sp.hstack_stride = p->hstack_stride;
 
     mcs::ResetParams &rp = p->rp;
     rp.inst = sp.inst;

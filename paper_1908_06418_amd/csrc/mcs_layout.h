@@ -99,6 +99,8 @@ struct SearchParams {
     int policy_levels;       // LDS partner-order lists per wavefront (0 without policy)
     unsigned long long limit_ticks;  // time limit in realtime ticks
     long long node_limit;            // 0: none
+    uint8_t *hstack;                 // (128-bit rows) [waves][hstack_stride] class stacks
+    long long hstack_stride;         // bytes per wavefront: (cap_classes + 1) (L, R) pairs
 };
 
 struct ResetParams {
@@ -115,7 +117,10 @@ struct ResetParams {
 };
 
 // Words of one frame header in LDS (one 32-bit word per field, padded).
+// Rows of 128 bits need two more words for the remaining-partner mask.
 constexpr int kHdrWords = 12;
+constexpr int kHdrWordsWide = 14;
+inline constexpr int hdr_words(int word_bytes) { return word_bytes > 8 ? kHdrWordsWide : kHdrWords; }
 
 // Record of a donated node in the queue: a 32-byte header, the mapping
 // (NB pairs of bytes) and the classes.
@@ -133,10 +138,11 @@ constexpr int rec_cls_off() { return kRecHeader + 2 * bits_of<W>(); }
 // LDS of one wavefront, in this order, each part 16-byte aligned:
 //   classes   [cap_classes + 1] (L, R) word pairs; the last is a trash slot
 //             that lanes with nothing to store write to, so the stores need
-//             no exec-mask branches
+//             no exec-mask branches (cap_classes = -1: the classes live
+//             elsewhere, as they do in HBM for 128-bit rows)
 //   adjacency [R][NB] words
 //   mapping   [NB] byte pairs
-//   headers   [frames][kHdrWords] frame headers, one 32-bit word per field
+//   headers   [frames][hdr_words] frame headers, one 32-bit word per field
 //   orders    [policy levels][64] partner order of policy-ordered frames
 struct LdsLayout {
     int cls, adj, map, hdr, ord, total;
@@ -148,7 +154,7 @@ inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_clas
                                       int frames, int policy_levels = 0) {
     int nb = 8 * word_bytes;
     int rows = directed ? 4 : 2;
-    int hdr_bytes = 4 * kHdrWords;
+    int hdr_bytes = 4 * hdr_words(word_bytes);
     LdsLayout L{0, 0, 0, 0, 0, 0};
     L.cls = 0;
     L.adj = align16((cap_classes + 1) * 2 * word_bytes);

@@ -8,9 +8,11 @@
 //
 // GPU mapping (ours, not the paper's CUDA design):
 //   * One wavefront runs one depth-first search at a time.  Classes are
-//     bitsets (L, R) of one machine word each (32-bit rows for graphs of at
-//     most 32 vertices, 64-bit otherwise); lane k holds class k.  A node has
-//     at most min(|V_G|, |V_H|) <= 64 classes, so one wave64 always holds it.
+//     bitsets (L, R) of one word each (32-bit rows for graphs of at most 32
+//     vertices, 64-bit up to 64, 128-bit up to 128); lane k holds class k.
+//     A node has at most min(|V_G|, |V_H|) classes, so one wave64 holds all
+//     of them up to 64 vertices; with 128-bit rows each lane holds two
+//     (classes k and k + S of its segment of S lanes).
 //   * A batch evaluates up to 8 sibling children at once: lanes are split in
 //     segments of S = 8/16/32/64 lanes, each segment a copy of the classes and
 //     its own w.  Split, popcounts and the min() of Eq. 1 are per lane; the
@@ -53,6 +55,9 @@ namespace mcs {
 
 #define DEV static __device__ __forceinline__
 
+// Rows of graphs with 65..128 vertices.
+using u128 = unsigned __int128;
+
 template <typename W>
 struct Cls {
     W L, R;
@@ -73,6 +78,8 @@ enum HdrField {
     kHFlags,
     kHLsel,
     kHRsel,
+    kHRrem2,  // (128-bit rows) bits 64..95 and 96..127 of the partner mask
+    kHRrem3,
 };
 
 template <typename W>
@@ -83,8 +90,9 @@ struct RecHdr {
     W rrem;
 };
 
-static_assert(kHRsel < kHdrWords, "header layout");
-static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>) <= kRecHeader,
+static_assert(kHRsel < kHdrWords && kHRrem3 < kHdrWordsWide, "header layout");
+static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>) <= kRecHeader &&
+                  sizeof(RecHdr<u128>) <= kRecHeader,
               "record header layout");
 
 constexpr int kFlagUnmatched = 1;  // the "v unmatched" child is still to do
@@ -97,6 +105,12 @@ DEV int popc(uint32_t x) { return __builtin_popcount(x); }
 DEV int popc(uint64_t x) { return __builtin_popcountll(x); }
 DEV int ctz(uint32_t x) { return __builtin_ctz(x); }
 DEV int ctz(uint64_t x) { return __builtin_ctzll(x); }
+
+DEV int popc(u128 x) { return popc((uint64_t)x) + popc((uint64_t)(x >> 64)); }
+DEV int ctz(u128 x) {
+    const uint64_t lo = (uint64_t)x;
+    return lo ? ctz(lo) : 64 + ctz((uint64_t)(x >> 64));
+}
 
 // ---- wave helpers ----------------------------------------------------------
 
@@ -115,6 +129,8 @@ DEV uint64_t rl(uint64_t x, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 DEV unsigned long long rl_ull(unsigned long long x, int l) { return (unsigned long long)rl((uint64_t)x, l); }
+DEV u128 sc(u128 x) { return ((u128)sc((uint64_t)(x >> 64)) << 64) | sc((uint64_t)x); }
+DEV u128 rl(u128 x, int l) { return ((u128)rl((uint64_t)(x >> 64), l) << 64) | rl((uint64_t)x, l); }
 
 DEV uint64_t ballot(bool p) { return __ballot(p); }
 DEV int mbcnt(uint64_t m) {
@@ -191,6 +207,14 @@ DEV void wave_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// The same for a wave's stores to global memory read back by other lanes of
+// the wave: the stores complete (reach the CU's L1 and L2) before any later
+// load issues.
+DEV void wave_sync_global() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // ---- device-scope atomics ----------------------------------------------------
 
@@ -251,14 +275,17 @@ template <typename W, bool DIR, bool POL>
 struct Searcher {
     static constexpr int NB = bits_of<W>();  // vertices per row word
     static constexpr int NR = DIR ? 4 : 2;   // adjacency row sets per instance
+    static constexpr int Q = NB > 64 ? 2 : 1;  // classes per lane
+    static constexpr int HW = hdr_words((int)sizeof(W));  // header words per frame
+    static_assert(!(POL && Q > 1), "the policy scorer takes one vertex per lane");
 
     const SearchParams &P;  // a copy in LDS: cold fields are read when needed
     int cmax, cap_classes, check_interval, reprune;  // hot knobs, kept in registers
     int lane;
     W *sadj;        // [NR][NB]: G rows, H rows (out), then G, H in-rows
     uint16_t *smap; // [NB] current path: g | h << 8
-    int *shdr;      // [NB + 1][kHdrWords]
-    Cls<W> *scls;   // [cap_classes]
+    int *shdr;      // [NB + 1][HW]
+    Cls<W> *scls;   // [cap_classes + 1] (LDS; HBM with 128-bit rows)
 
     uint8_t *sord;  // [policy levels][64]: partner order of policy-ordered frames
     int inst, map_off, nG, nH, target;
@@ -266,8 +293,10 @@ struct Searcher {
     int t, base, K, d, v, sel, bound, flags, lsel, rsel;
     W rrem;
     int logS;
-    // this lane's copy of class (lane mod S) of the top frame
+    // this lane's copy of class (lane mod S) of the top frame, and with
+    // two classes per lane, of class (lane mod S) + S in cL1, cR1
     W cL, cR;
+    W cL1, cR1;
     int inc;
     bool stop;
     bool roots_left;  // false once every instance root has been claimed
@@ -286,15 +315,20 @@ struct Searcher {
     uint32_t c_pushed;
     unsigned long long n_pushed;
 
-    __device__ Searcher(const SearchParams &p, uint8_t *lds) : P(p) {
+    __device__ Searcher(const SearchParams &p, uint8_t *lds, int wave) : P(p) {
         lane = lane_id();
         cmax = sc(p.cmax);
         cap_classes = sc(p.cap_classes);
         check_interval = sc(p.check_interval);
         reprune = sc(p.reprune);
-        const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes, p.frames,
-                                       p.policy_levels);
-        scls = (Cls<W> *)(lds + L.cls);
+        // with 128-bit rows the class stack is this wavefront's slice of HBM
+        // (the worst case, up to 264 KB, does not fit in LDS)
+        const LdsLayout L = lds_layout((int)sizeof(W), DIR ? 1 : 0, Q == 1 ? p.cap_classes : -1,
+                                       p.frames, p.policy_levels);
+        if constexpr (Q == 1)
+            scls = (Cls<W> *)(lds + L.cls);
+        else
+            scls = (Cls<W> *)(p.hstack + (size_t)wave * (size_t)p.hstack_stride);
         sadj = (W *)(lds + L.adj);
         smap = (uint16_t *)(lds + L.map);
         shdr = (int *)(lds + L.hdr);
@@ -339,20 +373,46 @@ struct Searcher {
         stop = true;
     }
 
+    // Orders a wavefront's own stack traffic between its lanes.
+    __device__ void sync() {
+        if constexpr (Q == 1)
+            wave_sync();
+        else
+            wave_sync_global();
+    }
+
     // -- frame registers -----------------------------------------------------
 
     __device__ void load_regs() {
-        logS = K <= 8 ? 3 : K <= 16 ? 4 : K <= 32 ? 5 : 6;
-        const int k = lane & ((1 << logS) - 1);
-        const bool in = k < K;
-        const Cls<W> c = scls[base + (in ? k : 0)];  // (no exec-mask branch)
-        cL = in ? c.L : (W)0;
-        cR = in ? c.R : (W)0;
+        if constexpr (Q == 1) {
+            logS = K <= 8 ? 3 : K <= 16 ? 4 : K <= 32 ? 5 : 6;
+            const int k = lane & ((1 << logS) - 1);
+            const bool in = k < K;
+            const Cls<W> c = scls[base + (in ? k : 0)];  // (no exec-mask branch)
+            cL = in ? c.L : (W)0;
+            cR = in ? c.R : (W)0;
+        } else {
+            // a segment of S lanes holds 2S classes
+            logS = K <= 16 ? 3 : K <= 32 ? 4 : K <= 64 ? 5 : 6;
+            const int S = 1 << logS;
+            const int k = lane & (S - 1);
+            const bool in0 = k < K, in1 = k + S < K;
+            const Cls<W> c0 = scls[base + (in0 ? k : 0)];
+            const Cls<W> c1 = scls[base + (in1 ? k + S : 0)];
+            cL = in0 ? c0.L : (W)0;
+            cR = in0 ? c0.R : (W)0;
+            cL1 = in1 ? c1.L : (W)0;
+            cR1 = in1 ? c1.R : (W)0;
+        }
     }
 
     // selectLabelClass + selectVertex: the class with the smallest
     // max(|L|, |R|), ties to the smallest vertex of L; v = that vertex.
     __device__ void select() {
+        if constexpr (Q == 2) {
+            select2();
+            return;
+        }
         uint32_t key = 0xFFFFFFFFu;
         if (lane < K) {
             int nl = popc(cL), nr = popc(cR);
@@ -378,6 +438,32 @@ struct Searcher {
                     order_partners(rrem);
             }
         }
+    }
+
+    // select() with two classes per lane: the first segment's lanes hold
+    // classes lane and lane + S.  L sets are disjoint, so keys are distinct.
+    __device__ void select2() {
+        const int S = 1 << logS;
+        uint32_t key0 = 0xFFFFFFFFu, key1 = 0xFFFFFFFFu;
+        if (lane < S) {
+            if (lane < K) {
+                int nl = popc(cL), nr = popc(cR);
+                key0 = ((uint32_t)(nl > nr ? nl : nr) << 8) | (uint32_t)ctz(cL);
+            }
+            if (lane + S < K) {
+                int nl = popc(cL1), nr = popc(cR1);
+                key1 = ((uint32_t)(nl > nr ? nl : nr) << 8) | (uint32_t)ctz(cL1);
+            }
+        }
+        const uint32_t mk = seg0_min(umin(key0, key1), logS);
+        const int who = ctz((uint64_t)ballot(key0 == mk || key1 == mk));
+        const bool hi = rl(key1 == mk ? 1 : 0, who) != 0;
+        sel = who + (hi ? S : 0);
+        v = (int)(mk & 0xFF);
+        rrem = rl(hi ? cR1 : cR, who);
+        lsel = popc(rl(hi ? cL1 : cL, who));
+        rsel = popc(rrem);
+        flags &= ~kFlagOrdered;
     }
 
     // -- learned branching policy ----------------------------------------------
@@ -501,7 +587,7 @@ struct Searcher {
         }
         if (is_cand)
             sord[t * 64 + rank] = (uint8_t)lane;
-        wave_sync();
+        sync();
         flags |= kFlagOrdered;
     }
 
@@ -510,7 +596,7 @@ struct Searcher {
         // between the writes, which depend on nothing but their operands)
         int x = 0;
         const int lo = (int)(uint32_t)rrem;
-        const int hi = sizeof(W) == 8 ? (int)(uint32_t)((uint64_t)rrem >> 32) : 0;
+        const int hi = sizeof(W) >= 8 ? (int)(uint32_t)((uint64_t)rrem >> 32) : 0;
         static_assert(kHRremLo == 0 && kHRremHi == 1 && kHBase == 2 && kHK == 3 && kHD == 4 &&
                           kHV == 5 && kHSel == 6 && kHBound == 7 && kHFlags == 8 &&
                           kHLsel == 9 && kHRsel == 10,
@@ -530,24 +616,42 @@ struct Searcher {
             : "+v"(x)
             : "s"(lo), "s"(hi), "s"(base), "s"(K), "s"(d), "s"(v), "s"(sel), "s"(bound),
               "s"(flags), "s"(lsel), "s"(rsel));
+        if constexpr (sizeof(W) == 16) {
+            static_assert(kHRrem2 == 11 && kHRrem3 == 12, "header field order");
+            const int w2 = (int)(uint32_t)((u128)rrem >> 64);
+            const int w3 = (int)(uint32_t)((u128)rrem >> 96);
+            asm volatile(
+                "v_writelane_b32 %0, %1, 11\n\t"
+                "v_writelane_b32 %0, %2, 12"
+                : "+v"(x)
+                : "s"(w2), "s"(w3));
+        }
         // lanes past the last field all store into the header's padding word
-        shdr[t * kHdrWords + (lane < kHdrWords ? lane : kHdrWords - 1)] = x;
+        shdr[t * HW + (lane < HW ? lane : HW - 1)] = x;
     }
 
     // One field of frame i's header, as a scalar.
-    __device__ int hdr(int i, int f) const { return sc(shdr[i * kHdrWords + f]); }
+    __device__ int hdr(int i, int f) const { return sc(shdr[i * HW + f]); }
     __device__ W hdr_rrem(int i) const {
         W r = (W)(uint32_t)hdr(i, kHRremLo);
-        if constexpr (sizeof(W) == 8)
+        if constexpr (sizeof(W) >= 8)
             r |= (W)(uint32_t)hdr(i, kHRremHi) << 32;
+        if constexpr (sizeof(W) == 16) {
+            r |= (W)(uint32_t)hdr(i, kHRrem2) << 64;
+            r |= (W)(uint32_t)hdr(i, kHRrem3) << 96;
+        }
         return r;
     }
 
     __device__ void read_hdr(int i) {
-        const int x = shdr[i * kHdrWords + (lane < kHdrWords ? lane : 0)];
+        const int x = shdr[i * HW + (lane < HW ? lane : 0)];
         W r = (W)(uint32_t)rl(x, kHRremLo);
-        if constexpr (sizeof(W) == 8)
+        if constexpr (sizeof(W) >= 8)
             r |= (W)(uint32_t)rl(x, kHRremHi) << 32;
+        if constexpr (sizeof(W) == 16) {
+            r |= (W)(uint32_t)rl(x, kHRrem2) << 64;
+            r |= (W)(uint32_t)rl(x, kHRrem3) << 96;
+        }
         rrem = r;
         base = rl(x, kHBase);
         K = rl(x, kHK);
@@ -577,27 +681,44 @@ struct Searcher {
         if (lane == 0)
             g = ld_rlx(&P.inc[i]);
         inc = cap_inc(rl(g, 0));
-        wave_sync();
+        sync();
     }
 
     __device__ void start_root(int i) {
         set_instance(i);
         DevInst di = P.inst[i];
         K = sc((int)di.K0);
-        if (lane < K) {
+        if constexpr (Q == 1) {
+            if (lane < K) {
+                const Cls<W> *rc = (const Cls<W> *)P.rootcls + sc((int)di.cls_off);
+                scls[lane] = rc[lane];
+            }
+        } else {
             const Cls<W> *rc = (const Cls<W> *)P.rootcls + sc((int)di.cls_off);
-            scls[lane] = rc[lane];
+            for (int j = lane; j < K; j += 64)
+                scls[j] = rc[j];
         }
-        wave_sync();
+        sync();
         t = 0;
         base = 0;
         d = 0;
         d0 = 0;
         load_regs();
         int contrib = 0;
-        if (lane < K) {
-            int nl = popc(cL), nr = popc(cR);
-            contrib = nl < nr ? nl : nr;
+        if constexpr (Q == 1) {
+            if (lane < K) {
+                int nl = popc(cL), nr = popc(cR);
+                contrib = nl < nr ? nl : nr;
+            }
+        } else {
+            // (slots past K hold empty classes)
+            if (lane < (1 << logS)) {
+                int nl = popc(cL), nr = popc(cR);
+                contrib = nl < nr ? nl : nr;
+                nl = popc(cL1);
+                nr = popc(cR1);
+                contrib += nl < nr ? nl : nr;
+            }
         }
         bound = wave_sum(contrib);
         c_nodes += 1;  // the root
@@ -619,8 +740,13 @@ struct Searcher {
         old = rl(old, 0);
         if (old < size) {
             uint16_t *dst = P.maps + map_off + size * (size - 1) / 2;
-            if (lane < size)
-                dst[lane] = smap[lane];
+            if constexpr (Q == 1) {
+                if (lane < size)
+                    dst[lane] = smap[lane];
+            } else {
+                for (int j = lane; j < size; j += 64)
+                    dst[j] = smap[j];
+            }
             if (lane == 0)
                 a_max64(&P.t_best[inst], ((unsigned long long)size << 48) |
                                              (now_ticks() & 0xFFFFFFFFFFFFull));
@@ -641,6 +767,10 @@ struct Searcher {
     // -- one batch of sibling children -----------------------------------------
 
     __device__ void batch() {
+        if constexpr (Q == 2) {
+            batch2();
+            return;
+        }
         const int S = 1 << logS;
         int C = popc(rrem);
         if (C > cmax)
@@ -775,13 +905,13 @@ struct Searcher {
             // as a record (its mapping may still raise the incumbent)
             if (lane == 0)
                 smap[d] = (uint16_t)(v | (wF << 8));
-            wave_sync();
+            sync();
             if (d + 1 > inc)
                 improve(d + 1);
             // (one wavefront alone has the worst-case stack: no spill there)
             if (P.single_wave)
                 fail(1);
-            else if (!spill_child(fb, K2, ne, pos, pl, pr))
+            else if (!spill_child<NR>(fb, K2, ne, pos, pl, pr))
                 fail(2);
             return;
         }
@@ -797,7 +927,7 @@ struct Searcher {
         }
         smap[d] = (uint16_t)(v | (wF << 8));  // the same value from every lane
         save_top();
-        wave_sync();
+        sync();
         if (d + 1 > inc)
             improve(d + 1);
         if (K2 == 0)
@@ -814,6 +944,143 @@ struct Searcher {
         (void)S;
     }
 
+    // batch() with two classes per lane (128-bit rows): the same steps on
+    // slots 0 and 1 of every lane.  Lane j stands for vertices j and 64 + j
+    // when the children taken are struck from the partner mask.
+    __device__ void batch2() {
+        const int S = 1 << logS;
+        int C = popc(rrem);
+        if (C > cmax)
+            C = cmax;
+        if (C > (64 >> logS))
+            C = 64 >> logS;
+        const int seg = lane >> logS;
+        const bool act = seg < C;
+        W x = rrem;
+        for (int i = 1; i < C; ++i) {
+            W y = x & (x - 1);
+            x = seg >= i ? y : x;
+        }
+        const int myw = act ? ctz(x) : 0;
+        const W vb = (W)1 << v;
+        const W wb = (W)1 << myw;
+        const W go = sadj[v], ho = sadj[NB + myw];
+        W gi = 0, hi = 0;
+        if constexpr (DIR) {
+            gi = sadj[2 * NB + v];
+            hi = sadj[3 * NB + myw];
+        }
+        // parts of slot q at index q * NR + a
+        W pl[2 * NR], pr[2 * NR];
+        int contrib = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const W Lx = (q ? cL1 : cL) & ~vb;
+            const W Rx = (q ? cR1 : cR) & ~wb;
+            W *l = pl + q * NR, *r = pr + q * NR;
+            if constexpr (!DIR) {
+                l[0] = Lx & ~go;
+                r[0] = Rx & ~ho;
+                l[1] = Lx & go;
+                r[1] = Rx & ho;
+            } else {
+                l[0] = Lx & ~go & ~gi;
+                r[0] = Rx & ~ho & ~hi;
+                l[1] = Lx & go & ~gi;
+                r[1] = Rx & ho & ~hi;
+                l[2] = Lx & ~go & gi;
+                r[2] = Rx & ~ho & hi;
+                l[3] = Lx & go & gi;
+                r[3] = Rx & ho & hi;
+            }
+#pragma unroll
+            for (int a = 0; a < NR; ++a) {
+                int nl = popc(l[a]), nr = popc(r[a]);
+                contrib += nl < nr ? nl : nr;
+            }
+        }
+        if (!act)
+            contrib = 0;
+
+        const int b = d + 1 + seg_sum(contrib, logS);
+        const bool rep = (lane & (S - 1)) == S - 1;
+        const uint64_t sb = ballot(act && rep && b > inc);
+        const int nsurv = __builtin_popcountll(sb);
+        const int first = sb ? (ctz(sb) >> logS) : -1;
+        const int fb = sb ? rl(b, ctz(sb)) : 0;
+        c_nodes += (uint32_t)(C - nsurv + (nsurv ? 1 : 0));
+        c_batches += 1;
+        c_children += (uint32_t)C;
+        c_lanes += (uint32_t)(C * (K < S ? K : S));
+
+        // the child of rank r took the r-th lowest vertex of rrem
+        const uint64_t mlo = (uint64_t)rrem, mhi = (uint64_t)(rrem >> 64);
+        const int r0 = mbcnt(mlo), r1 = __builtin_popcountll(mlo) + mbcnt(mhi);
+        const bool t0 = ((mlo >> lane) & 1) && r0 < C;
+        const bool t1 = ((mhi >> lane) & 1) && r1 < C;
+        const bool s0 = t0 && ((sb >> (((r0 << logS) + S - 1) & 63)) & 1);
+        const bool s1 = t1 && ((sb >> (((r1 << logS) + S - 1) & 63)) & 1);
+        const uint64_t x0 = ballot(t0 && (!s0 || r0 == first));
+        const uint64_t x1 = ballot(t1 && (!s1 || r1 == first));
+        rrem &= ~((W)x0 | ((W)x1 << 64));
+        if (first < 0)
+            return;
+        const uint64_t f0 = ballot(t0 && r0 == first), f1 = ballot(t1 && r1 == first);
+        const int wF = f0 ? ctz(f0) : 64 + ctz(f1);
+
+        const bool inF = seg == first;
+        int pos[2 * NR];
+        bool ne[2 * NR];
+        int K2 = 0;
+#pragma unroll
+        for (int j = 0; j < 2 * NR; ++j) {
+            ne[j] = inF && pl[j] != 0 && pr[j] != 0;
+            uint64_t m = ballot(ne[j]);
+            pos[j] = K2 + mbcnt(m);
+            K2 += __builtin_popcountll(m);
+        }
+        // (the stack holds the worst case here: this cannot fire unless the
+        // caller asked for a smaller one)
+        const int nb = base + K;
+        if (nb + K2 > cap_classes) {
+            if (lane == 0)
+                smap[d] = (uint16_t)(v | (wF << 8));
+            sync();
+            if (d + 1 > inc)
+                improve(d + 1);
+            if (P.single_wave)
+                fail(1);
+            else if (!spill_child<2 * NR>(fb, K2, ne, pos, pl, pr))
+                fail(2);
+            return;
+        }
+        if (nb + K2 > max_used)
+            max_used = nb + K2;
+#pragma unroll
+        for (int j = 0; j < 2 * NR; ++j) {
+            Cls<W> c;
+            c.L = pl[j];
+            c.R = pr[j];
+            scls[ne[j] ? nb + pos[j] : cap_classes] = c;
+        }
+        smap[d] = (uint16_t)(v | (wF << 8));
+        save_top();
+        sync();
+        if (d + 1 > inc)
+            improve(d + 1);
+        if (K2 == 0)
+            return;
+        c_pushed += (uint32_t)K2;
+        t += 1;
+        base = nb;
+        K = K2;
+        d += 1;
+        bound = fb;
+        flags = kFlagUnmatched;
+        load_regs();
+        select();
+    }
+
     // -- the "v unmatched" child, done in place on the top frame -----------------
     // Its bound follows from the parent's: only the selected class loses v.
     __device__ bool unmatched() {
@@ -823,14 +1090,44 @@ struct Searcher {
         if (ub <= inc)
             return false;
         const W vb = (W)1 << v;
-        if (lsel == 1) {
+        if constexpr (Q == 2) {
+            // class j sits in lane j mod S, slot j / S
+            const int S = 1 << logS;
+            if (lsel == 1) {
+                // the last class moves into the selected one's place
+                const int last = K - 1;
+                const bool lhi = last >= S;
+                Cls<W> c;
+                c.L = lhi ? cL1 : cL;
+                c.R = lhi ? cR1 : cR;
+                scls[(sel != last && lane == (last & (S - 1))) ? base + sel : cap_classes] = c;
+                K = last;
+                sync();
+                bound = ub;
+                if (K == 0)
+                    return false;
+                load_regs();
+            } else {
+                const int sl = sel & (S - 1);
+                const bool shi = sel >= S;
+                if ((lane & (S - 1)) == sl) {
+                    if (shi)
+                        cL1 &= ~vb;
+                    else
+                        cL &= ~vb;
+                }
+                scls[lane == sl ? base + sel : cap_classes].L = shi ? cL1 : cL;
+                sync();
+                bound = ub;
+            }
+        } else if (lsel == 1) {
             int last = K - 1;
             Cls<W> c;
             c.L = cL;
             c.R = cR;
             scls[(sel != last && lane == last) ? base + sel : cap_classes] = c;
             K = last;
-            wave_sync();
+            sync();
             bound = ub;
             if (K == 0)
                 return false;
@@ -840,7 +1137,7 @@ struct Searcher {
             if (k == sel)
                 cL &= ~vb;
             scls[lane == sel ? base + sel : cap_classes].L = cL;
-            wave_sync();
+            sync();
             bound = ub;
         }
         flags = kFlagUnmatched;
@@ -867,8 +1164,11 @@ struct Searcher {
     // -- work sharing ------------------------------------------------------------
 
     // A free slot in this XCD's ring, else in the next rings; false if all
-    // are full (the donation is then skipped: the work stays local).
-    __device__ bool reserve(int &ring, unsigned long long &ticket) {
+    // are full (the donation is then skipped: the work stays local).  A
+    // claim lost to another producer is retried up to `tries` times per ring:
+    // a donation gives up early, a child that has nowhere else to go keeps
+    // trying until the rings are really full.
+    __device__ bool reserve(int &ring, unsigned long long &ticket, int tries_per_ring) {
         const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
         int ok = 0, rr = 0;
         unsigned long long tk = 0;
@@ -876,7 +1176,7 @@ struct Searcher {
             for (int k = 0; k < kRings && !ok; ++k) {
                 const int r = (my_ring + k) & (kRings - 1);
                 unsigned long long *sq = P.seq + (size_t)r * P.ring_slots;
-                for (int tries = 0; tries < 4; ++tries) {
+                for (int tries = 0; tries < tries_per_ring; ++tries) {
                     unsigned long long tl = ld_rlx(&P.g->ring[r].tail);
                     unsigned long long s = ld_rlx(&sq[tl & mask]);
                     if (s == tl) {
@@ -943,7 +1243,7 @@ struct Searcher {
         }
         unsigned long long ticket;
         int ring;
-        if (!reserve(ring, ticket))
+        if (!reserve(ring, ticket, 4))
             return;
         const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
         const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
@@ -978,11 +1278,18 @@ struct Searcher {
         if (lane == 0)
             *(RecHdr<W> *)slot = rh;
         uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
-        if (lane < fd)
-            rmap[lane] = smap[lane];
         Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
-        if (lane < fK)
-            rcls[lane] = scls[fbase + lane];
+        if constexpr (Q == 1) {
+            if (lane < fd)
+                rmap[lane] = smap[lane];
+            if (lane < fK)
+                rcls[lane] = scls[fbase + lane];
+        } else {
+            for (int j = lane; j < fd; j += 64)
+                rmap[j] = smap[j];
+            for (int j = lane; j < fK; j += 64)
+                rcls[j] = scls[fbase + j];
+        }
         if (lane == 0) {
             a_add_rlx(&P.open[inst], 1);
             a_add_rlx(&P.g->open_total, 1);
@@ -992,22 +1299,27 @@ struct Searcher {
             rrem = keep_r;
             flags &= kFlagOrdered;
         } else if (lane == 0) {
-            shdr[b * kHdrWords + kHRremLo] = 0;
-            shdr[b * kHdrWords + kHRremHi] = 0;
-            shdr[b * kHdrWords + kHFlags] = 0;
+            shdr[b * HW + kHRremLo] = 0;
+            shdr[b * HW + kHRremHi] = 0;
+            shdr[b * HW + kHFlags] = 0;
+            if constexpr (sizeof(W) == 16) {
+                shdr[b * HW + kHRrem2] = 0;
+                shdr[b * HW + kHRrem3] = 0;
+            }
         }
-        wave_sync();
+        sync();
         n_don += 1;
     }
 
     // Queue the child whose classes segment `first` holds (compacted at
-    // pos[a] for the parts ne[a]) as a fresh record: the taker chooses its
-    // class and v.  Its mapping is the current path plus smap[d].
+    // pos[j] for the NP parts with ne[j]) as a fresh record: the taker
+    // chooses its class and v.  Its mapping is the current path plus smap[d].
+    template <int NP>
     __device__ bool spill_child(int fb, int K2, const bool *ne, const int *pos, const W *pl,
                                 const W *pr) {
         unsigned long long ticket;
         int ring;
-        if (!reserve(ring, ticket))
+        if (!reserve(ring, ticket, 1024))
             return false;
         const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
         const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
@@ -1027,11 +1339,16 @@ struct Searcher {
         if (lane == 0)
             *(RecHdr<W> *)slot = rh;
         uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
-        if (lane <= d)
-            rmap[lane] = smap[lane];
+        if constexpr (Q == 1) {
+            if (lane <= d)
+                rmap[lane] = smap[lane];
+        } else {
+            for (int j = lane; j <= d; j += 64)
+                rmap[j] = smap[j];
+        }
         Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
 #pragma unroll
-        for (int a = 0; a < NR; ++a)
+        for (int a = 0; a < NP; ++a)
             if (ne[a]) {
                 Cls<W> c;
                 c.L = pl[a];
@@ -1098,14 +1415,22 @@ struct Searcher {
         rrem = sc((W)rh.rrem);
         const uint16_t *rmap = (const uint16_t *)(slot + rec_map_off<W>());
         const Cls<W> *rcls = (const Cls<W> *)(slot + rec_cls_off<W>());
-        uint16_t mp = 0;
-        Cls<W> cc;
+        uint16_t mp = 0, mp1 = 0;
+        Cls<W> cc, cc1;
         cc.L = 0;
         cc.R = 0;
+        cc1.L = 0;
+        cc1.R = 0;
         if (lane < d)
             mp = rmap[lane];
         if (lane < K)
             cc = rcls[lane];
+        if constexpr (Q == 2) {
+            if (lane + 64 < d)
+                mp1 = rmap[lane + 64];
+            if (lane + 64 < K)
+                cc1 = rcls[lane + 64];
+        }
         // every lane's loads of the slot have returned before the slot is
         // handed back, so a relaxed store suffices: the producer's later
         // writes cannot reach values already in registers (the signal fence
@@ -1119,7 +1444,13 @@ struct Searcher {
             smap[lane] = mp;
         if (lane < K)
             scls[lane] = cc;
-        wave_sync();
+        if constexpr (Q == 2) {
+            if (lane + 64 < d)
+                smap[lane + 64] = mp1;
+            if (lane + 64 < K)
+                scls[lane + 64] = cc1;
+        }
+        sync();
         t = 0;
         base = 0;
         d0 = d;
@@ -1350,7 +1681,8 @@ __global__ void __launch_bounds__(256) mcs_search_kernel(SearchParams Pk) {
     const int wv = threadIdx.x >> 6;
     if (Pk.single_wave && (blockIdx.x != 0 || wv != 0))
         return;
-    Searcher<W, DIR, POL> s(P, smem + (size_t)wv * (size_t)Pk.lds_per_wave);
+    Searcher<W, DIR, POL> s(P, smem + (size_t)wv * (size_t)Pk.lds_per_wave,
+                            (int)(blockIdx.x * (blockDim.x >> 6)) + wv);
     s.main_loop();
 }
 
@@ -1385,6 +1717,13 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
 
 extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed, int policy) {
     using namespace mcs;
+    if (word_bytes == 16) {
+        // (the learned policy takes graphs of at most 64 vertices)
+        if (policy)
+            return nullptr;
+        return directed ? (void *)mcs_search_kernel<u128, true, false>
+                        : (void *)mcs_search_kernel<u128, false, false>;
+    }
     if (word_bytes == 4) {
         if (policy)
             return directed ? (void *)mcs_search_kernel<uint32_t, true, true>

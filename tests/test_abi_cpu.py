@@ -72,7 +72,7 @@ def test_status_strings(mcs_lib):
 
 
 @pytest.mark.parametrize("mutate,status", [
-    (lambda G, H: (dict(G, n=65, rows=[0] * 65), H), -2),
+    (lambda G, H: (dict(G, n=129, rows=[0] * 129), H), -2),
     (lambda G, H: (dict(G, n=-1), H), -1),
     (lambda G, H: (dict(G, rows=[G["rows"][0] | 1] + G["rows"][1:]), H), -1),   # self loop
     (lambda G, H: (dict(G, rows=[G["rows"][0] | (1 << 20)] + G["rows"][1:]), H), -1),  # bit >= n
@@ -89,6 +89,71 @@ def test_validation_errors(mcs_lib, mutate, status):
         _create([(G, H)])
     assert _status(e) == status
     assert mcs_lib.mcs_last_error()
+
+
+def _flip(g, i, j):
+    rows = list(g["rows"])
+    rows[i] ^= 1 << j
+    return dict(g, rows=rows)
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda G: _flip(G, 0, 110),    # a bit at or above n, in the second word of a row
+    lambda G: _flip(G, 90, 90),    # a self loop in the second word
+    lambda G: _flip(G, 3, 80),     # asymmetric in the second word
+    lambda G: _flip(G, 80, 3),     # asymmetric in the first word of a wide row
+])
+def test_validation_errors_two_word_rows(mcs_lib, mutate):
+    """Graphs of 65..128 vertices have two 64-bit words per row."""
+    from paper_1908_06418_amd import McsError
+    G = mi.er_graph(100, 0.1, 1)
+    H = mi.er_graph(100, 0.1, 2)
+    _create([(G, H)]).close()
+    with pytest.raises(McsError) as e:
+        _create([(mutate(G), H)])
+    assert _status(e) == -1
+    assert mcs_lib.mcs_last_error()
+
+
+def test_two_word_rows_marshalled_low_word_first():
+    from paper_1908_06418_amd import _Marshal
+    g = mi.er_graph(100, 0.2, 3)
+    m = _Marshal([(g, g)])
+    words = m.keep[0]
+    assert words.size == 2 * 100
+    for i, r in enumerate(g["rows"]):
+        assert int(words[2 * i]) | (int(words[2 * i + 1]) << 64) == r
+    small = _Marshal([(mi.er_graph(64, 0.2, 3), mi.er_graph(64, 0.2, 4))])
+    assert small.keep[0].size == 64
+
+
+def test_wide_plan_sizes(mcs_lib):
+    """128-bit rows: the plan keeps a capped class stack and larger records."""
+    from paper_1908_06418_amd import Plan, workspace_size
+    pairs = [(mi.er_graph(128, 0.3, 5), mi.er_graph(120, 0.3, 6))]
+    narrow = [(mi.er_graph(64, 0.3, 5), mi.er_graph(60, 0.3, 6))]
+    assert workspace_size(pairs) > workspace_size(narrow) > 0
+    Plan(pairs).close()
+
+
+def test_policy_rejected_above_64_vertices(mcs_lib):
+    from paper_1908_06418_amd import _abi, _Marshal
+    m = _Marshal([(mi.er_graph(70, 0.3, 1), mi.er_graph(70, 0.3, 2))])
+    o = _abi.mcs_opts()
+    o.policy = 4096  # (never dereferenced: the plan is refused first)
+    o.policy_depth = 2
+    h = ctypes.c_void_p()
+    assert mcs_lib.mcs_plan_create(1, m.G, m.H, ctypes.byref(o), ctypes.byref(h)) == \
+        _abi.MCS_E_INVALID
+    assert b"64" in mcs_lib.mcs_last_error()
+
+
+def test_single_wave_plan_at_128_vertices(mcs_lib):
+    """With 128-bit rows every wavefront's class stack lives in HBM, so one
+    wavefront can hold the whole worst case (8256 classes at 128 vertices)."""
+    from paper_1908_06418_amd import Plan
+    pairs = [(mi.er_graph(128, 0.3, 5), mi.er_graph(128, 0.3, 6))]
+    Plan(pairs, tuning={"single_wave": 1}).close()
 
 
 def test_null_and_count_errors(mcs_lib):

@@ -1,0 +1,206 @@
+"""GPU parity for graphs of 65..128 vertices: 128-bit rows, two classes per
+lane (class k of a frame in lane k mod S, slot k / S, for segments of S
+lanes).  A batch whose largest graph has more than 64 vertices runs every
+pair on this kernel, so small pairs mixed into such a batch exercise the
+second slot as soon as a frame has more than 8 classes; labelled pairs with
+more than 64 shared labels start with more than 64 classes at the root.
+
+Sizes must equal the oracle's; mappings are checked for validity.  With one
+wavefront the search walks the oracle's tree, so node counts agree too.
+"""
+import numpy as np
+import pytest
+
+import mcs_instances as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _check(pairs, res, want):
+    for i, ((G, H), r) in enumerate(zip(pairs, res)):
+        errs = oracle.check.mapping_errors(G, H, r.mapping)
+        assert not errs, (i, errs[:3])
+        assert len(r.mapping) == r.size
+        assert r.size == want[i], (i, r.size, want[i])
+
+
+def _many_labels(rng, n, p, directed, nlab):
+    """G and H drawn independently; label i % nlab on G, the same multiset in
+    a random order on H, so every label is shared: nlab root classes."""
+    g = mi.random_small(rng, n, p, directed)
+    h = mi.random_small(rng, n, p, directed)
+    g["label"] = [i % nlab for i in range(n)]
+    h["label"] = [int(x) % nlab for x in rng.permutation(n)]
+    return g, h
+
+
+def _relabelled_copy(rng, g):
+    return g, mi.permute(g, list(rng.permutation(g["n"])))
+
+
+def _small(rng, count, directed, nlab):
+    out = []
+    for _ in range(count):
+        n1, n2 = int(rng.integers(4, 19)), int(rng.integers(4, 19))
+        p = float(rng.uniform(0.1, 0.7))
+        out.append((mi.random_small(rng, n1, p, directed, nlab),
+                    mi.random_small(rng, n2, p, directed, nlab)))
+    return out
+
+
+@pytest.mark.parametrize("kind", ["undirected", "directed", "labelled", "directed_labelled"])
+def test_wide_single_wave_reproduces_oracle_node_count(gpu, kind):
+    """One wavefront on the 128-bit kernel expands exactly the oracle's nodes:
+    class selection over both slots, the split of both slots, the unmatched
+    child and the partner bookkeeping over 128 vertices all follow the
+    sequential algorithm."""
+    rng = np.random.default_rng({"undirected": 31, "directed": 32, "labelled": 33,
+                                 "directed_labelled": 34}[kind])
+    directed = kind.startswith("directed")
+    labelled = "labelled" in kind
+    # small pairs, and one pair with a 66-vertex graph that puts the batch on
+    # the 128-bit kernel
+    pairs = _small(rng, 10, directed, 6 if labelled else 0)
+    pairs += [(mi.random_small(rng, 66, 0.5, directed, 6 if labelled else 0),
+               mi.random_small(rng, 12, 0.5, directed, 6 if labelled else 0))]
+    # larger pairs: with labels, 66 shared labels give 66 classes at the
+    # root, more than one per lane; without, a relabelled copy of a 70-vertex
+    # graph (size 70).  The single wavefront's worst-case stack (2485
+    # classes at min(nG, nH) = 70) sits in HBM.
+    if labelled:
+        pairs += [_many_labels(rng, 70, 0.3 if directed else 0.5, directed, 66)
+                  for _ in range(2)]
+    else:
+        # (a draw whose copy the degree order aligns at once: with many
+        # equal degrees a relabelled copy can take the oracle millions of
+        # nodes to prove)
+        rb = np.random.default_rng(101)
+        pairs += [_relabelled_copy(rb, mi.random_small(rb, 70, 0.3, directed))]
+    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1}
+    _say(f"wide single-wave {kind}: {len(pairs)} pairs")
+    res = _solve(pairs, tuning=tun)
+    for i, ((G, H), r) in enumerate(zip(pairs, res)):
+        o = oracle.mcs(G, H)
+        assert r.optimal and r.size == o["size"], (i, r.size, o["size"])
+        assert r.nodes == o["nodes"], (i, r.nodes, o["nodes"])
+        assert oracle.check.is_valid(G, H, r.mapping)
+
+
+def _solve(pairs, **kw):
+    from paper_1908_06418_amd import solve_batch
+    return solve_batch(pairs, time_limit_s=kw.pop("time_limit_s", 120), **kw)
+
+
+def _wide_batch():
+    rng = np.random.default_rng(40)
+    pairs = []
+    # the directed labelled workload's recipe (p = 0.1, ceil(0.33 n) labels)
+    # at 70 and 100 vertices
+    for s in range(3):
+        pairs.append((mi.er_graph(70, 0.1, mi.stream_seed(6, s, 0), True, True),
+                      mi.er_graph(70, 0.1, mi.stream_seed(6, s, 1), True, True)))
+    pairs += [_many_labels(rng, 128, 0.5, False, 100) for _ in range(2)]
+    pairs += [_many_labels(rng, 128, 0.3, True, 100) for _ in range(2)]
+    pairs += [_many_labels(rng, 100, 0.3, True, 50) for _ in range(2)]
+    pairs += [_relabelled_copy(rng, mi.random_small(rng, 128, 0.5))]
+    pairs += [_relabelled_copy(rng, mi.random_small(rng, 128, 0.3, True))]
+    pairs += _small(rng, 8, False, 0)
+    return pairs
+
+
+def test_wide_batched_matches_oracle(gpu):
+    pairs = _wide_batch()
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    _say(f"wide batch: {len(pairs)} pairs")
+    res = _solve(pairs)
+    assert all(r.optimal for r in res)
+    _check(pairs, res, want)
+    assert want[9] == 128 and want[10] == 128
+
+
+def test_wide_edge_cases(gpu):
+    rng = np.random.default_rng(41)
+    g100 = mi.random_small(rng, 100, 0.2)
+    cases = [
+        (mi.empty_graph(128), mi.empty_graph(128), 128),
+        (mi.complete_graph(128), mi.complete_graph(100), 100),
+        (mi.empty_graph(65), mi.complete_graph(70), 1),
+        (mi.empty_graph(0), mi.empty_graph(128), 0),
+        (mi.complete_graph(128), mi.empty_graph(1), 1),
+        (g100, mi.induced(g100, list(range(0, 100, 25))), 4),
+        (mi.empty_graph(65), mi.empty_graph(64), 64),
+    ]
+    pairs = [(G, H) for G, H, _ in cases]
+    _say("wide edge cases")
+    res = _solve(pairs)
+    assert all(r.optimal for r in res)
+    _check(pairs, res, [s for _, _, s in cases])
+
+
+def test_wide_and_narrow_kernels_agree(gpu):
+    """The same small pairs on the 64-bit kernel, and on the 128-bit kernel
+    (one 65-vertex pair in the batch): identical sizes."""
+    rng = np.random.default_rng(42)
+    small = _small(rng, 24, False, 3) + _small(rng, 24, True, 0)
+    narrow = _solve(small)
+    wide = _solve(small + [(mi.empty_graph(65), mi.empty_graph(65))])
+    assert [r.size for r in wide[:-1]] == [r.size for r in narrow]
+    assert wide[-1].size == 65
+    assert all(r.optimal for r in narrow + wide)
+
+
+@pytest.mark.parametrize("tun", [
+    {"stack_classes": 4000, "ring_slots": 8192},
+    {"stack_classes": 4000, "ring_slots": 8192, "children_per_wave": 1, "check_interval": 1,
+     "waves_per_cu": 1},
+])
+def test_wide_small_class_stack_spills_children_exactly(gpu, tun):
+    """A class stack of 4000 against the 8256-class worst case at 128
+    vertices, with frames of up to about 100 classes: children that do not
+    fit go to the node queue as records of up to 128 classes (two per lane
+    when taken back), and sizes stay exact.  (The rings are first in, first
+    out, so spilled work spreads breadth-first: with much smaller stacks the
+    queued records outgrow any ring, which the next test covers.  This stack
+    spills a few hundred children here.)"""
+    from paper_1908_06418_amd import Plan
+    pairs = _wide_batch()
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    _say(f"wide small stack {tun}: {len(pairs)} pairs")
+    plan = Plan(pairs, time_limit_s=120, tuning=tun).upload()
+    try:
+        plan.run()
+        res = plan.results()
+        st = plan.stats()
+    finally:
+        plan.close()
+    assert st.stack_classes == 4000
+    assert st.max_stack_used <= st.stack_classes
+    assert st.spills > 0
+    assert all(r.optimal for r in res)
+    _check(pairs, res, want)
+
+
+def test_wide_smallest_stack_reports_queue_full_or_is_exact(gpu):
+    """The smallest stack (2m + 1 = 257 classes): nearly every node past the
+    second level spills, the first-in first-out rings fill, and the search
+    stops with MCS_E_QUEUE_FULL; if they never fill, the run is exact.
+    Either way it ends."""
+    from paper_1908_06418_amd import McsError, Plan, _abi
+    pairs = _wide_batch()
+    plan = Plan(pairs, time_limit_s=60, tuning={"stack_classes": 1}).upload()
+    try:
+        plan.run()
+        res = plan.results()
+    except McsError as e:
+        assert e.status == _abi.MCS_E_QUEUE_FULL, e
+        _say(f"queue full reported: {e}")
+    else:
+        _say("queue never filled")
+        _check(pairs, res, [oracle.mcs(G, H)["size"] for G, H in pairs])
+    finally:
+        plan.close()
