@@ -538,13 +538,15 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     (void)hipGetLastError();
     p->tick_hz = (double)clock_khz * 1000.0;
     // Default: about 96 wavefronts per instance, between 8 and 24 per CU
-    // (one hard instance alone still splits across thousands of them).  One wavefront's search is a long dependent chain of scalar
-    // and vector steps, so several per SIMD fill the issue slots while
-    // there is work for them; past what the instances can keep busy, more
-    // wavefronts only split the work into ever smaller donations.
+    // (4 and 16 with 128-bit rows, whose larger state fits fewer), so one
+    // hard instance alone still splits across thousands of them.  One
+    // wavefront's search is a long dependent chain of scalar and vector
+    // steps, so several per SIMD fill the issue slots while there is work
+    // for them; past what the instances can keep busy, more wavefronts only
+    // split the work into ever smaller donations.
     const bool wide = p->word_bytes == 16;
     const int want_waves = p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
-                           : wide ? std::max(4 * cus, std::min(8 * cus, 96 * count))
+                           : wide ? std::max(4 * cus, std::min(16 * cus, 96 * count))
                                   : std::max(8 * cus, std::min(24 * cus, 96 * count));
     const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
     auto per_wave = [&](int cap) {

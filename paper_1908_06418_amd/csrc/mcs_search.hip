@@ -11,8 +11,8 @@
 //     bitsets (L, R) of one word each (32-bit rows for graphs of at most 32
 //     vertices, 64-bit up to 64, 128-bit up to 128); lane k holds class k.
 //     A node has at most min(|V_G|, |V_H|) classes, so one wave64 holds all
-//     of them up to 64 vertices; with 128-bit rows each lane holds two
-//     (classes k and k + S of its segment of S lanes).
+//     of them up to 64 vertices; with 128-bit rows a frame of more than 64
+//     classes puts class 64 + k in a second slot of lane k.
 //   * A batch evaluates up to 8 sibling children at once: lanes are split in
 //     segments of S = 8/16/32/64 lanes, each segment a copy of the classes and
 //     its own w.  Split, popcounts and the min() of Eq. 1 are per lane; the
@@ -293,8 +293,8 @@ struct Searcher {
     int t, base, K, d, v, sel, bound, flags, lsel, rsel;
     W rrem;
     int logS;
-    // this lane's copy of class (lane mod S) of the top frame, and with
-    // two classes per lane, of class (lane mod S) + S in cL1, cR1
+    // this lane's copy of class (lane mod S) of the top frame, and in a
+    // frame of more than 64 classes (S = 64), of class lane + 64 in cL1, cR1
     W cL, cR;
     W cL1, cR1;
     int inc;
@@ -392,17 +392,23 @@ struct Searcher {
             cL = in ? c.L : (W)0;
             cR = in ? c.R : (W)0;
         } else {
-            // a segment of S lanes holds 2S classes
-            logS = K <= 16 ? 3 : K <= 32 ? 4 : K <= 64 ? 5 : 6;
+            // segments as with one class per lane; only a frame of more
+            // than 64 classes (S = 64) puts classes 64.. in the second slot
+            logS = K <= 8 ? 3 : K <= 16 ? 4 : K <= 32 ? 5 : 6;
             const int S = 1 << logS;
             const int k = lane & (S - 1);
-            const bool in0 = k < K, in1 = k + S < K;
+            const bool in0 = k < K;
             const Cls<W> c0 = scls[base + (in0 ? k : 0)];
-            const Cls<W> c1 = scls[base + (in1 ? k + S : 0)];
             cL = in0 ? c0.L : (W)0;
             cR = in0 ? c0.R : (W)0;
-            cL1 = in1 ? c1.L : (W)0;
-            cR1 = in1 ? c1.R : (W)0;
+            cL1 = 0;
+            cR1 = 0;
+            if (K > 64) {
+                const bool in1 = k + S < K;
+                const Cls<W> c1 = scls[base + (in1 ? k + S : 0)];
+                cL1 = in1 ? c1.L : (W)0;
+                cR1 = in1 ? c1.R : (W)0;
+            }
         }
     }
 
@@ -440,8 +446,8 @@ struct Searcher {
         }
     }
 
-    // select() with two classes per lane: the first segment's lanes hold
-    // classes lane and lane + S.  L sets are disjoint, so keys are distinct.
+    // select() with a second class slot per lane (classes lane + S, used
+    // only when S = 64).  L sets are disjoint, so keys are distinct.
     __device__ void select2() {
         const int S = 1 << logS;
         uint32_t key0 = 0xFFFFFFFFu, key1 = 0xFFFFFFFFu;
@@ -944,9 +950,10 @@ struct Searcher {
         (void)S;
     }
 
-    // batch() with two classes per lane (128-bit rows): the same steps on
-    // slots 0 and 1 of every lane.  Lane j stands for vertices j and 64 + j
-    // when the children taken are struck from the partner mask.
+    // batch() for 128-bit rows: the same steps, on the second class slot
+    // too when the frame has more than 64 classes.  Lane j stands for
+    // vertices j and 64 + j when the children taken are struck from the
+    // partner mask.
     __device__ void batch2() {
         const int S = 1 << logS;
         int C = popc(rrem);
@@ -970,11 +977,19 @@ struct Searcher {
             gi = sadj[2 * NB + v];
             hi = sadj[3 * NB + myw];
         }
-        // parts of slot q at index q * NR + a
+        // parts of slot q at index q * NR + a; the second slot only holds
+        // classes in frames of more than 64
+        const bool two = K > 64;
         W pl[2 * NR], pr[2 * NR];
         int contrib = 0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
+            if (q == 1 && !two) {
+#pragma unroll
+                for (int a = 0; a < NR; ++a)
+                    pl[NR + a] = pr[NR + a] = 0;
+                break;
+            }
             const W Lx = (q ? cL1 : cL) & ~vb;
             const W Rx = (q ? cR1 : cR) & ~wb;
             W *l = pl + q * NR, *r = pr + q * NR;
@@ -1034,6 +1049,13 @@ struct Searcher {
         int K2 = 0;
 #pragma unroll
         for (int j = 0; j < 2 * NR; ++j) {
+            ne[j] = false;
+            pos[j] = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * NR; ++j) {
+            if (j == NR && !two)
+                break;
             ne[j] = inF && pl[j] != 0 && pr[j] != 0;
             uint64_t m = ballot(ne[j]);
             pos[j] = K2 + mbcnt(m);
@@ -1058,6 +1080,8 @@ struct Searcher {
             max_used = nb + K2;
 #pragma unroll
         for (int j = 0; j < 2 * NR; ++j) {
+            if (j == NR && !two)
+                break;
             Cls<W> c;
             c.L = pl[j];
             c.R = pr[j];

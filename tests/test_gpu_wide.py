@@ -1,9 +1,9 @@
-"""GPU parity for graphs of 65..128 vertices: 128-bit rows, two classes per
-lane (class k of a frame in lane k mod S, slot k / S, for segments of S
-lanes).  A batch whose largest graph has more than 64 vertices runs every
-pair on this kernel, so small pairs mixed into such a batch exercise the
-second slot as soon as a frame has more than 8 classes; labelled pairs with
-more than 64 shared labels start with more than 64 classes at the root.
+"""GPU parity for graphs of 65..128 vertices: 128-bit rows, and a second
+class slot per lane for frames of more than 64 classes (class 64 + k in lane
+k).  A batch whose largest graph has more than 64 vertices runs every pair on
+this kernel, so small pairs mixed into such a batch run the 128-bit words on
+the one-slot path; labelled pairs with more than 64 shared labels start with
+more than 64 classes at the root and use the second slot.
 
 Sizes must equal the oracle's; mappings are checked for validity.  With one
 wavefront the search walks the oracle's tree, so node counts agree too.
