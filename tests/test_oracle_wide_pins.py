@@ -1,0 +1,57 @@
+"""Pins of the oracle on graphs of 65..128 vertices, the range the 128-bit
+search kernel covers (the oracle works on dense byte matrices, so nothing in
+it changes at 64; these check it there against closed forms and invariants,
+as the small-graph pins do below 12 vertices)."""
+import numpy as np
+
+import mcs_instances as mi
+import oracle
+
+
+def test_closed_forms_beyond_64():
+    for a in (65, 100, 128):
+        for b in (1, 64, 65, 128):
+            assert oracle.mcs(mi.empty_graph(a), mi.empty_graph(b))["size"] == min(a, b)
+            assert oracle.mcs(mi.complete_graph(a), mi.complete_graph(b))["size"] == min(a, b)
+            assert oracle.mcs(mi.complete_graph(a), mi.empty_graph(b))["size"] == 1
+
+
+def test_relabelled_copy_and_induced_subgraph_beyond_64():
+    """MCS(G, pi G) = n and MCS(G, G[S]) = |S| on random graphs of 70..128
+    vertices, undirected and directed, and the mapping is valid."""
+    rng = np.random.default_rng(101)
+    g70 = mi.random_small(rng, 70, 0.3)
+    cases = [(g70, mi.permute(g70, list(rng.permutation(70))), 70)]
+    # the two relabelled 128-vertex copies of the 128-bit kernel's GPU batch
+    # (draws whose copies the degree order aligns quickly; a relabelled copy
+    # of a dense graph with many equal degrees can take millions of nodes)
+    from test_gpu_wide import _wide_batch
+    wide = _wide_batch()
+    cases += [(wide[9][0], wide[9][1], 128), (wide[10][0], wide[10][1], 128)]
+    g100 = mi.random_small(np.random.default_rng(41), 100, 0.2)
+    for S in (list(range(0, 100, 25)), [0, 1, 2, 97, 98, 99], [64, 65, 66]):
+        cases.append((g100, mi.induced(g100, S), len(S)))
+    for G, H, want in cases:
+        r = oracle.mcs(G, H, node_limit=5_000_000)
+        assert r["complete"] and r["size"] == want, (G["n"], H["n"], r["size"], want)
+        assert oracle.check.is_valid(G, H, r["map"])
+
+
+def test_invariants_beyond_64():
+    """Symmetry and relabelling leave the size unchanged, and refining the
+    labels can only shrink it, on directed labelled pairs of 66..80 vertices
+    (the directed labelled workload's recipe)."""
+    rng = np.random.default_rng(7)
+    for trial in range(3):
+        n1, n2 = int(rng.integers(66, 81)), int(rng.integers(66, 81))
+        G = mi.er_graph(n1, 0.1, 1000 + 2 * trial, True, True)
+        H = mi.er_graph(n2, 0.1, 1001 + 2 * trial, True, True)
+        r = oracle.mcs(G, H, node_limit=5_000_000)
+        assert r["complete"]
+        s = r["size"]
+        assert oracle.check.is_valid(G, H, r["map"])
+        assert oracle.mcs(H, G)["size"] == s
+        assert oracle.mcs(mi.permute(G, list(rng.permutation(n1))),
+                          mi.permute(H, list(rng.permutation(n2))))["size"] == s
+        fine = lambda g: dict(g, label=[2 * l + (v % 2) for v, l in enumerate(g["label"])])
+        assert oracle.mcs(fine(G), fine(H))["size"] <= s
