@@ -8,6 +8,8 @@ more than 64 classes at the root and use the second slot.
 Sizes must equal the oracle's; mappings are checked for validity.  With one
 wavefront the search walks the oracle's tree, so node counts agree too.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -204,3 +206,62 @@ def test_wide_smallest_stack_reports_queue_full_or_is_exact(gpu):
         _check(pairs, res, [oracle.mcs(G, H)["size"] for G, H in pairs])
     finally:
         plan.close()
+
+
+def _wide_mixed():
+    """Directed labelled pairs of 70 and 80 vertices (the directed labelled
+    workload's recipe) and small pairs, on the 128-bit kernel."""
+    pairs = [(mi.er_graph(n, 0.1, mi.stream_seed(8, s, 0), True, True),
+              mi.er_graph(n, 0.1, mi.stream_seed(8, s, 1), True, True))
+             for n in (70, 80) for s in range(2)]
+    return pairs + _small(np.random.default_rng(43), 6, True, 3)
+
+
+@functools.lru_cache(maxsize=1)
+def _wide_mixed_sizes():
+    return tuple(oracle.mcs(G, H)["size"] for G, H in _wide_mixed())
+
+
+def test_wide_alternative_order(gpu):
+    """The component / block-triangular order (mcs_opts.ordering = 1) on the
+    128-bit kernel: the oracle's sizes and valid mappings."""
+    pairs = _wide_mixed()
+    want = list(_wide_mixed_sizes())
+    _say(f"wide btf order: {len(pairs)} pairs")
+    from paper_1908_06418_amd import solve_batch
+    res = solve_batch(pairs, time_limit_s=60, ordering="btf")
+    assert all(r.optimal for r in res)
+    _check(pairs, res, want)
+
+
+def test_wide_graph_replays_match_oracle(gpu):
+    """The HIP graph (reset kernel + 128-bit search kernel) replayed three
+    times, with eager work between replays: the oracle's sizes every time."""
+    import torch
+    from paper_1908_06418_amd import Plan
+    pairs = _wide_mixed()
+    want = list(_wide_mixed_sizes())
+    plan = Plan(pairs, time_limit_s=60, tuning={"use_graph": 1}).upload()
+    try:
+        for rep in range(3):
+            _say(f"wide graph replay {rep}")
+            plan.run()
+            res = plan.results()
+            assert all(r.optimal for r in res)
+            _check(pairs, res, want)
+            x = torch.randn(1 << 20, device="cuda")
+            torch.cuda.synchronize()
+            assert torch.isfinite(x.sum()).item()
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("strategy", ["top-down", "bisect"])
+def test_wide_goal_search(gpu, strategy):
+    from paper_1908_06418_amd import solve_goals
+    pairs = _wide_mixed()
+    want = list(_wide_mixed_sizes())
+    _say(f"wide goal search {strategy}: {len(pairs)} pairs")
+    res = solve_goals(pairs, strategy=strategy, node_limit=20000, time_limit_s=60)
+    assert all(r.optimal for r in res)
+    _check(pairs, res, want)
