@@ -37,13 +37,18 @@ TRAFFIC = {
     "c2": {"kernel_code_hash": "19d6bb92e9c532f0",
            "bytes": int((31221114.3125 * 2 + 47464952.0) * 1024),
            "profile": "profiles/mcs_search_kernel_c2.md"},
+    "w": {"kernel_code_hash": "19d6bb92e9c532f0",
+          "bytes": int((129434.9375 * 2 + 14574363.03125) * 1024),
+          "profile": "profiles/mcs_search_kernel_w.md"},
 }
 
 # Algorithmic 32-bit lane operations per class per evaluated child: remove v
 # and w (2), split L and R by the adjacency letters (4; directed 16), popcount
 # every part (4; 8), min() per letter (2; 4) and add into Eq. 1 (2; 4):
-# 14 undirected, 34 directed; 64-bit words double the and/popcount work.
-OPS_PER_CLASS = {(4, False): 14, (8, False): 24, (4, True): 34, (8, True): 60}
+# 14 undirected, 34 directed; 64-bit words double the and/popcount work
+# (24, 60) and 128-bit words quadruple it (44, 112).
+OPS_PER_CLASS = {(4, False): 14, (8, False): 24, (16, False): 44,
+                 (4, True): 34, (8, True): 60, (16, True): 112}
 
 
 def workloads():
@@ -60,6 +65,8 @@ def workloads():
         "c4": ("the batched workload: 4096 undirected pairs, n ~ U{10..35}, p ~ U[0.05,0.5), "
                "one persistent launch", lambda: mi.pairs_c4(4096), "expected_c4.json"),
         "c1": ("one undirected unlabelled pair G(16,0.3)", lambda: mi.pair_c1(), None),
+        "w": ("40 directed vertex-labelled pairs n in {80,100}, p=0.1, ceil(0.33n) labels "
+              "(128-bit rows), one batched launch", lambda: mi.pairs_w(), "expected_w.json"),
     }
 
 
@@ -228,7 +235,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     K = args.steps
-    word = 4 if max(max(G["n"], H["n"]) for G, H in pairs) <= 32 else 8
+    nmax = max(max(G["n"], H["n"]) for G, H in pairs)
+    word = 4 if nmax <= 32 else 8 if nmax <= 64 else 16
     directed = bool(pairs[0][0]["directed"])
     ops = lane_slots * OPS_PER_CLASS[(word, directed)]
     kern_s = kernel_ms / 1e3
@@ -245,7 +253,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64" if word == 8 else "u32",
+        "dtype": {4: "u32", 8: "u64", 16: "u128"}[word],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "pairs": len(pairs),
                    "word_bits": 8 * word, "directed": directed,
@@ -277,7 +285,9 @@ def main():
                 "frac": lds_bytes / kern_s / PEAK_LDS_BYTES if kern_s else 0.0,
                 "bytes": "algorithmic: adjacency rows of v and the partners per child batch, "
                          "and each pushed frame's classes written once and read twice "
-                         "(mcs_stats.lds_bytes, from the kernel's counters)"},
+                         "(mcs_stats.lds_bytes, from the kernel's counters)"
+                         + ("; with 128-bit rows the classes live in the workspace (L1/L2), "
+                            "not LDS" if word == 16 else "")},
         "hbm": {"achieved_GBps": traffic * K / kern_s / 1e9 if traffic and kern_s else None,
                 "peak_GBps": PEAK_HBM_BYTES / 1e9,
                 "frac": traffic * K / kern_s / PEAK_HBM_BYTES if traffic and kern_s else None,

@@ -128,6 +128,24 @@ def pairs_c3(ns=C3_N, seeds=range(20)) -> list:
     return out
 
 
+W_N = (80, 100)
+
+
+def pairs_w(ns=W_N, seeds=range(20)) -> list:
+    """The directed vertex-labelled recipe at 80 and 100 vertices (p = 0.1,
+    labels over ceil(0.33 n) values, 20 seeds each): graphs beyond 64
+    vertices; pair index n_idx * 20 + seed of workload 7."""
+    out = []
+    for ni, n in enumerate(W_N):
+        if n not in ns:
+            continue
+        for s in seeds:
+            i = ni * 20 + s
+            out.append((er_graph(n, 0.1, stream_seed(7, i, 0), True, True),
+                        er_graph(n, 0.1, stream_seed(7, i, 1), True, True)))
+    return out
+
+
 def c4_shape(i: int) -> tuple:
     u = uniforms(stream_seed(4, i, 2), 2)
     return 10 + int(u[0] * 26), 0.05 + float(u[1]) * 0.45

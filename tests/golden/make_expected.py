@@ -39,6 +39,8 @@ SETS = {
                 "batched workload, first 1024 pairs (n ~ U{10..35}, p ~ U[0.05,0.5))"),
     "c4": (lambda: mi.pairs_c4(4096), 20_000_000,
            "batched workload, all 4096 pairs (n ~ U{10..35}, p ~ U[0.05,0.5))"),
+    "w": (lambda: mi.pairs_w(), 0,
+          "directed vertex-labelled n in {80,100}, p=0.1, ceil(0.33n) labels, seeds 0..19"),
     "c2": (lambda: mi.pairs_c2(), _c2_limit,
            "undirected unlabelled G(n,p), n in {30,35,40}, p in {0.1,0.3,0.5}, seeds 0..19 "
            "(node limit: none for n = 30, 1e8 otherwise)"),
