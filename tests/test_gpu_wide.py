@@ -265,3 +265,20 @@ def test_wide_goal_search(gpu, strategy):
     res = solve_goals(pairs, strategy=strategy, node_limit=20000, time_limit_s=60)
     assert all(r.optimal for r in res)
     _check(pairs, res, want)
+
+
+def test_w_workload_matches_stored_oracle_sizes(gpu):
+    """The benchmark's workload beyond 64 vertices (40 directed labelled
+    pairs, n 80 and 100) in one launch: every size equals the oracle's stored
+    size (the oracle finished all 40) and every pair is proven."""
+    import json
+    import os
+    pairs = mi.pairs_w()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "expected_w.json")) as f:
+        exp = json.load(f)
+    assert exp["digest"] == mi.workload_hash(pairs), "stored values are for other inputs"
+    _say(f"golden w: {len(pairs)} pairs")
+    res = _solve(pairs)
+    assert all(r.optimal for r in res)
+    assert all(e["complete"] for e in exp["pairs"])
+    _check(pairs, res, [e["size"] for e in exp["pairs"]])

@@ -55,3 +55,21 @@ def test_invariants_beyond_64():
                           mi.permute(H, list(rng.permutation(n2))))["size"] == s
         fine = lambda g: dict(g, label=[2 * l + (v % 2) for v, l in enumerate(g["label"])])
         assert oracle.mcs(fine(G), fine(H))["size"] <= s
+
+
+def test_w_stored_sizes_are_the_oracles():
+    """tests/golden/expected_w.json belongs to mcs_instances.pairs_w() and
+    holds the oracle's sizes (re-derived here for the pairs it proves
+    fastest)."""
+    import json
+    import os
+    pairs = mi.pairs_w()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "expected_w.json")) as f:
+        exp = json.load(f)
+    assert exp["digest"] == mi.workload_hash(pairs)
+    rows = sorted(range(len(pairs)), key=lambda i: exp["pairs"][i]["nodes"])[:4]
+    for i in rows:
+        G, H = pairs[i]
+        r = oracle.mcs(G, H)
+        assert r["complete"] and r["size"] == exp["pairs"][i]["size"]
+        assert oracle.check.is_valid(G, H, r["map"])
