@@ -240,3 +240,21 @@ def test_ordering_option_validated(mcs_lib):
         assert st == status, (ordering, st)
         if st == _abi.MCS_OK:
             mcs_lib.mcs_plan_destroy(h)
+
+
+def test_root_bounds_host_beyond_64(mcs_lib):
+    """Eq. 1 at the root on graphs with two-word rows: min(nG, nH)
+    unlabelled; with labels, the sum over shared labels of min(counts),
+    including labels whose vertices sit only above vertex 64."""
+    from paper_1908_06418_amd import _Marshal
+    G = mi.er_graph(128, 0.2, 11)
+    H = mi.er_graph(90, 0.2, 12)
+    Gl = dict(G, label=[0] * 64 + [1] * 60 + [2] * 4)
+    Hl = dict(H, label=[1] * 10 + [2] * 70 + [3] * 10)
+    m = _Marshal([(G, H), (Gl, Hl), (mi.empty_graph(70), mi.empty_graph(100))])
+    h = ctypes.c_void_p()
+    assert mcs_lib.mcs_plan_create(3, m.G, m.H, None, ctypes.byref(h)) == 0
+    out = (ctypes.c_int32 * 3)()
+    assert mcs_lib.mcs_plan_root_bounds(h, out) == 0
+    assert list(out) == [90, min(60, 10) + min(4, 70), 70]
+    mcs_lib.mcs_plan_destroy(h)
