@@ -282,3 +282,25 @@ def test_w_workload_matches_stored_oracle_sizes(gpu):
     assert all(r.optimal for r in res)
     assert all(e["complete"] for e in exp["pairs"])
     _check(pairs, res, [e["size"] for e in exp["pairs"]])
+
+
+def test_wide_limits_give_valid_partial_results(gpu):
+    """A node limit, then a time limit, on the 128-vertex directed labelled
+    recipe (about 2.9e9 nodes to prove 20 such pairs): the launch stops with
+    MCS_LIMIT, not every pair is proven, and every mapping returned is a
+    valid common induced subgraph of its reported size."""
+    from paper_1908_06418_amd import Plan, _abi
+    pairs = [(mi.er_graph(128, 0.1, mi.stream_seed(9, s, 0), True, True),
+              mi.er_graph(128, 0.1, mi.stream_seed(9, s, 1), True, True)) for s in range(8)]
+    for kw in ({"node_limit": 200000, "time_limit_s": 60}, {"time_limit_s": 0.02}):
+        _say(f"wide limit {kw}")
+        plan = Plan(pairs, **kw).upload()
+        try:
+            plan.run()
+            res = plan.results()
+            assert plan.status == _abi.MCS_LIMIT
+            assert not all(r.optimal for r in res)
+            _check(pairs, res, [r.size for r in res])
+            assert all(0 < r.size <= 128 for r in res)
+        finally:
+            plan.close()
