@@ -60,10 +60,10 @@ typedef enum {
  * must be symmetric.  No self loops (diagonal bits) and no bits at or above
  * n.  label is NULL (unlabelled) or n vertex labels; G and H of a pair must
  * agree on directed and on labelled.  One batch may mix directed and
- * undirected pairs, and labelled and unlabelled ones.  The search keeps one
- * class per lane up to 64 vertices and two per lane above (128-bit rows), so
- * a batch whose largest graph has more than 64 vertices runs the slower
- * wide kernel for all its pairs. */
+ * undirected pairs, and labelled and unlabelled ones.  A batch whose
+ * largest graph has more than 64 vertices runs the slower 128-bit kernel
+ * (two classes per lane in nodes of more than 64 classes) for all its
+ * pairs. */
 typedef struct {
     int32_t n;
     int32_t directed;
