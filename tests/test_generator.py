@@ -71,3 +71,32 @@ def test_workload_shapes():
     assert sum(1 for _, p in c5 if p == 0.2) == 512
     tr = [mi.c5_shape(i, train=True) for i in range(100)]
     assert all(20 <= n <= 30 for n, _ in tr)
+
+
+def test_workload_w_shape():
+    """The workload beyond 64 vertices: 40 directed labelled pairs, 20 of 80
+    and 20 of 100 vertices, labels over ceil(0.33 n) values, rows as Python
+    ints with bits above 63 in use."""
+    w = mi.pairs_w()
+    assert len(w) == 40
+    assert [G["n"] for G, _ in w] == [80] * 20 + [100] * 20
+    assert all(G["n"] == H["n"] and G["directed"] and H["directed"] for G, H in w)
+    for G, H in w:
+        for g in (G, H):
+            assert max(g["label"]) < mi.label_count(g["n"])
+            assert all(r >> g["n"] == 0 for r in g["rows"])
+            assert all(not (r >> i) & 1 for i, r in enumerate(g["rows"]))
+    assert any(r >> 64 for G, _ in w for r in G["rows"])
+    assert mi.pairs_w(ns=(100,), seeds=range(1)) == [w[20]]
+
+
+def test_bench_accounting_covers_every_word_size():
+    """bench.py prices every row width and direction it can meet, and every
+    workload it names resolves to pairs of the width it says."""
+    import bench
+    assert set(bench.OPS_PER_CLASS) == {(w, d) for w in (4, 8, 16) for d in (False, True)}
+    wl = bench.workloads()
+    assert {"c1", "c2", "c2_n30", "c3", "c4", "c4_1024", "w"} <= set(wl)
+    assert "128-bit" in wl["w"][0]
+    for name, t in bench.TRAFFIC.items():
+        assert name in wl and t["bytes"] > 0 and len(t["kernel_code_hash"]) == 16
