@@ -9,7 +9,7 @@ the oracle's stored results for the workload: equal where the oracle finished
 budget ran out, and every pair proven optimal by the search itself; anything
 else marks the line "exact": false.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c2_n30|c3|c4|c4_1024|c1|w]
 
 Prints one JSON line.
 """
