@@ -3,10 +3,10 @@ bound correction): same sizes as the oracle, valid mappings, and the goal
 semantics of mcs_plan_set_goals."""
 import ctypes
 import json
-import os
 
 import numpy as np
 import pytest
+from _report import write_report
 
 import mcs_instances as mi
 import oracle
@@ -99,6 +99,4 @@ def test_goal_search_report(gpu):
                     assert a.size == b.size
         report[f"c2_n{n}_p0.1"] = row
     _say("goal report: " + json.dumps(report))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "goal_report.json"), "w") as f:
-        json.dump(report, f, indent=1)
+    write_report("goal_report.json", report)

@@ -9,6 +9,7 @@ import os
 
 import numpy as np
 import pytest
+from _report import write_report
 
 import mcs_instances as mi
 import oracle
@@ -393,7 +394,8 @@ def test_batched_vs_one_at_a_time_report(gpu):
     """The batched launch against the plain search of one instance per
     launch (the whole GPU on one pair, library defaults, then at 24
     wavefronts per CU), on the 60 pairs G(30,p): equal sizes, and the
-    kernel time of each way, written to gpurun_out/batch_report.json."""
+    kernel time of each way, printed (and kept as batch_report.json, see
+    _report.py)."""
     from paper_1908_06418_amd import Plan
     pairs = mi.pairs_c2(ns=(30,))
     plan = Plan(pairs, time_limit_s=60).upload()
@@ -415,15 +417,13 @@ def test_batched_vs_one_at_a_time_report(gpu):
         report[name + "_ms"] = total
         _say(f"{name}: {total:.1f} ms for {len(pairs)} launches")
     _say("batch report: " + json.dumps(report))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "batch_report.json"), "w") as f:
-        json.dump(report, f, indent=1)
+    write_report("batch_report.json", report)
 
 
 def test_ordering_report(gpu):
     """Nodes and kernel time under the two static orders of Sec. IV.A, on the
     60 pairs G(30,p) and the 60 directed labelled pairs: equal sizes; the
-    comparison is written to gpurun_out/ordering_report.json."""
+    comparison is printed (and kept as ordering_report.json, see _report.py)."""
     from paper_1908_06418_amd import Plan
     report = {}
     for name, pairs in (("c2_n30", mi.pairs_c2(ns=(30,))), ("c3", mi.pairs_c3())):
@@ -443,6 +443,4 @@ def test_ordering_report(gpu):
             _say(f"ordering {name} {ordering}: {best:.1f} ms, {st.nodes} nodes")
         assert sizes["degree"] == sizes["btf"]
     _say("ordering report: " + json.dumps(report))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "ordering_report.json"), "w") as f:
-        json.dump(report, f, indent=1)
+    write_report("ordering_report.json", report)

@@ -7,6 +7,7 @@ from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 import pytest
+from _report import write_report
 
 import mcs_instances as mi
 import oracle
@@ -233,6 +234,4 @@ def test_policy_gain_report(gpu):
               "train_rows": _TRAINED["rows"],
               "train_loss_first_last": [curve[0], curve[-1]]}
     _say("policy gain: " + json.dumps(report))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "policy_gain.json"), "w") as f:
-        json.dump(report, f, indent=1)
+    write_report("policy_gain.json", report)
