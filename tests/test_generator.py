@@ -100,3 +100,14 @@ def test_bench_accounting_covers_every_word_size():
     assert "128-bit" in wl["w"][0]
     for name, t in bench.TRAFFIC.items():
         assert name in wl and t["bytes"] > 0 and len(t["kernel_code_hash"]) == 16
+
+
+def test_report_helper_writes_only_where_asked(tmp_path, monkeypatch):
+    from _report import write_report
+    monkeypatch.delenv("MCS_REPORT_DIR", raising=False)
+    write_report("r.json", {"a": 1})
+    assert not (tmp_path / "r.json").exists()
+    monkeypatch.setenv("MCS_REPORT_DIR", str(tmp_path / "out"))
+    write_report("r.json", {"a": 1})
+    import json
+    assert json.loads((tmp_path / "out" / "r.json").read_text()) == {"a": 1}
