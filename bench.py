@@ -1,17 +1,24 @@
 """Benchmark: McSplit search throughput on one MI355X.
 
-A step is one pass of the whole search over one batch of synthetic pairs: the
-search kernel (class split, Eq. 1 bound, prune/spawn, work queue, incumbent,
-termination) plus the result copy-back and un-permuting.  Inputs are uploaded
-to HBM once, before the timed region.  Every step's sizes are checked against
-the oracle's stored results for the workload: equal where the oracle finished
-(oracle_checked counts those pairs), at least its lower bound where its node
-budget ran out, and every pair proven optimal by the search itself; anything
-else marks the line "exact": false.
+A step is one pass of the whole search over one batch of synthetic pairs: a
+replay of the HIP graph that copies the packed inputs in, resets the search
+state, runs the search kernel (class split, Eq. 1 bound, prune/spawn, work
+queue, incumbent, termination) and copies the results back, followed by the
+un-permuting of the mappings on the host.  Inputs were packed and uploaded
+once before the timed region; the graph's input copy is part of every step.
+Every step's sizes are checked against the oracle's stored results for the
+workload: equal where the oracle finished (oracle_checked counts those
+pairs), at least its lower bound where its node budget ran out, and every
+pair proven optimal by the search itself; anything else marks the line
+"exact": false.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c2_n30|c3|c4|c4_1024|c1|w]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S]
+                    [--workload c4|c4_1024|c2|c2_n30|c3|c1|w]
 
-Prints one JSON line.
+The default workload is the batched one (4096 pairs).  Warmup and timed
+steps are cut to fit the wall-clock budget (default 420 s, the oracle leg
+included); "steps" and "warmup" in the output are the numbers actually run,
+beside "steps_requested" and "warmup_requested".  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -42,13 +49,22 @@ TRAFFIC = {
           "profile": "profiles/mcs_search_kernel_w.md"},
 }
 
-# Algorithmic 32-bit lane operations per class per evaluated child: remove v
-# and w (2), split L and R by the adjacency letters (4; directed 16), popcount
-# every part (4; 8), min() per letter (2; 4) and add into Eq. 1 (2; 4):
-# 14 undirected, 34 directed; 64-bit words double the and/popcount work
-# (24, 60) and 128-bit words quadruple it (44, 112).
-OPS_PER_CLASS = {(4, False): 14, (8, False): 24, (16, False): 44,
-                 (4, True): 34, (8, True): 60, (16, True): 112}
+# Algorithmic 32-bit lane operations of one matched child (v, w), per class
+# it splits.  Word-wise steps (each one lane-op per 32-bit word of a row):
+# remove v and w (2), split both sides by the adjacency letters (4; directed
+# 16), popcount every part (4; 8), test each part for emptiness (4; 8) and
+# store the surviving parts (2; 4).  Per-class scalar steps: min() per letter
+# (2; 4), add into Eq. 1 (2; 4), and both sides non-empty (2; 4).  Undirected
+# 16 word-wise + 6 = 22 at 32 bits, directed 38 + 12 = 50.  Each child also
+# costs a fixed 30 for the segment reduction of Eq. 1, the compare with the
+# incumbent and the ballot.
+WORD_OPS = {False: 16, True: 38}
+CLASS_OPS = {False: 6, True: 12}
+CHILD_OPS = 30
+
+
+def ops_per_class(word_bytes: int, directed: bool) -> int:
+    return WORD_OPS[directed] * (word_bytes // 4) + CLASS_OPS[directed]
 
 
 def workloads():
@@ -105,22 +121,57 @@ def expected_sizes(fname):
         return json.load(f)
 
 
-def cpu_baseline(pairs, exp, budget_s=20.0):
-    """The oracle, as it stands, on a bounded sample of the workload: the
-    pairs the stored oracle run proved fastest, up to about budget_s seconds
-    of single-core work, one process per pair over the host's cores."""
+def host_cpu() -> str:
+    """The host CPU model as lscpu names it (else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(pairs, exp, wall_s=15.0, seed=20260):
+    """The oracle, as it stands, on a bounded random sample of the workload.
+
+    Pairs are drawn in a seeded random order from those the stored oracle run
+    finished (the others cannot be timed to completion), and taken until
+    their stored one-core times add up to about wall_s x cores seconds; the
+    sample is then solved one process per pair on that many host cores."""
+    import random
     from concurrent.futures import ProcessPoolExecutor
 
     import oracle
     oracle._load()
-    cores = min(16, os.cpu_count() or 1)
+    cores = usable_cores()
     idx = list(range(len(pairs)))
+    finished = len(idx)
     if exp is not None:
-        idx = sorted((i for i in idx if exp["pairs"][i]["complete"]),
-                     key=lambda i: exp["pairs"][i]["seconds"])
+        idx = [i for i in idx if exp["pairs"][i]["complete"]]
+        finished = len(idx)
+        random.Random(seed).shuffle(idx)
         acc, keep = 0.0, []
         for i in idx:
-            if acc + exp["pairs"][i]["seconds"] > budget_s and keep:
+            if acc >= wall_s * cores:
                 break
             acc += exp["pairs"][i]["seconds"]
             keep.append(i)
@@ -132,11 +183,13 @@ def cpu_baseline(pairs, exp, budget_s=20.0):
     dt = time.time() - t0
     nodes = sum(n for n, _ in out)
     return {"value": nodes / dt, "unit": "nodes/s", "cores": cores, "kind": "oracle",
-            "instances_per_s": len(sample) / dt,
-            "sample": f"{len(sample)} of {len(pairs)} pairs of the same workload (those the "
-                      f"oracle proves fastest, about {budget_s:.0f} s of one-core work), solved "
-                      f"to optimality by the plain recursive C oracle, one process per pair on "
-                      f"{cores} host cores, {dt:.1f} s wall"}
+            "instances_per_s": len(sample) / dt, "cpu": host_cpu(),
+            "sample": f"{len(sample)} pairs drawn at random (seed {seed}) from the {finished} "
+                      f"of {len(pairs)} pairs of the same workload the oracle finishes within "
+                      f"its stored node budget, until their one-core times sum to about "
+                      f"{wall_s:.0f} s x {cores} cores; solved to optimality by the plain "
+                      f"recursive C oracle, one process per pair on {cores} host cores "
+                      f"({host_cpu()}), {dt:.1f} s wall"}
 
 
 def _spread(xs):
@@ -154,13 +207,21 @@ def _oracle_one(G, H):
 
 
 def main():
+    t_start = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--time-limit", type=float, default=120.0)
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--time-limit", type=float, default=300.0,
+                    help="per-launch search time limit, seconds")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget of the whole run: warmup and timed steps are cut "
+                         "to fit it (at least 1 warmup and 3 timed steps are always run), "
+                         "leaving room for the cpu_baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the kernels directly instead of replaying the HIP graph")
     ap.add_argument("--tuning", default="", help="JSON dict of mcs_tuning fields")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (outside the timed region), "
@@ -195,30 +256,54 @@ def main():
         from paper_1908_06418_amd import autotune
         tuning = autotune.tuned(pairs)
         tuning_src = "autotuner table" if tuning else "library defaults"
+    tuning = dict(tuning or {})
+    if not args.no_graph:
+        tuning["use_graph"] = 1
     plan = Plan(pairs, time_limit_s=args.time_limit, tuning=tuning).upload()
+    print(f"bench: {args.workload}, {len(pairs)} pairs, tuning {tuning} ({tuning_src})",
+          file=sys.stderr, flush=True)
 
     def step():
         plan.run()
         return plan.results()
 
-    for _ in range(args.warmup):
+    # The reserve kept for the oracle leg and for printing.
+    reserve = 5.0 if args.no_cpu_baseline else 40.0
+
+    def left():
+        return args.budget_s - (time.perf_counter() - t_start) - reserve
+
+    warm_done = 0
+    step_s = None
+    for _ in range(max(1, args.warmup)):
+        if warm_done >= 1 and step_s is not None and left() < step_s * (3 + 1):
+            break
+        t1 = time.perf_counter()
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        step_s = time.perf_counter() - t1
+        warm_done += 1
+        print(f"bench: warmup step {warm_done} took {step_s:.2f} s", file=sys.stderr, flush=True)
+    K = args.steps
+    if step_s is not None and step_s > 0:
+        K = max(min(3, args.steps), min(args.steps, int(left() / step_s)))
     exact = True
     nodes = 0
     kernel_ms = 0.0
-    lane_slots = batches = children = 0
+    lane_slots = batches = children = node_classes = 0
     lds_bytes = 0
     proven = 0
     busy = []
     t_best, t_proof = [], []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(K):
         res = step()
         st = plan.stats()
         nodes += st.nodes
         kernel_ms += st.kernel_ms
         lane_slots += st.lane_slots
+        node_classes += st.node_classes
         lds_bytes += st.lds_bytes
         batches += st.batches
         children += st.children
@@ -232,13 +317,15 @@ def main():
                     exact = False
         if not all(r.optimal for r in res):
             exact = False
+        print(f"bench: timed step {k + 1}/{K}: kernel {st.kernel_ms:.1f} ms, "
+              f"{st.nodes:.3e} nodes", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    K = args.steps
     nmax = max(max(G["n"], H["n"]) for G, H in pairs)
     word = 4 if nmax <= 32 else 8 if nmax <= 64 else 16
     directed = bool(pairs[0][0]["directed"])
-    ops = lane_slots * OPS_PER_CLASS[(word, directed)]
+    opc = ops_per_class(word, directed)
+    ops = node_classes * opc + nodes * CHILD_OPS
     kern_s = kernel_ms / 1e3
     achieved = ops / kern_s / 1e12 if kern_s > 0 else 0.0
     peak = PEAK_INT32_OPS / 1e12
@@ -248,7 +335,9 @@ def main():
         "unit": "nodes/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
+        "steps_requested": args.steps,
+        "warmup": warm_done,
+        "warmup_requested": args.warmup,
         "ms_per_step": elapsed / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -256,7 +345,7 @@ def main():
         "dtype": {4: "u32", 8: "u64", 16: "u128"}[word],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "pairs": len(pairs),
-                   "word_bits": 8 * word, "directed": directed,
+                   "word_bits": 8 * word, "directed": directed, "hip_graph": not args.no_graph,
                    "tuning": tuning, "tuning_source": tuning_src},
         "instances_per_s": len(pairs) * K / elapsed,
         "exact": exact,
@@ -275,8 +364,9 @@ def main():
                      "frac": achieved / peak if peak else 0.0,
                      "traffic": traffic_for(args.workload, 1),
                      "kernel": "mcs_search_kernel",
-                     "per_unit": f"{OPS_PER_CLASS[(word, directed)]} int32 lane-ops per class "
-                                 "per evaluated child"},
+                     "per_unit": f"{opc} int32 lane-ops per class of each matched child "
+                                 f"counted as a node, plus {CHILD_OPS} per node; "
+                                 "re-evaluated siblings are not counted"},
     }
     traffic = line["roofline"]["traffic"]
     line["bandwidth"] = {
@@ -296,6 +386,7 @@ def main():
     plan.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pairs, exp)
+    line["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(line), flush=True)
 
 

@@ -96,7 +96,12 @@ typedef struct {
                                   comparisons).  Its class stack is the whole
                                   worst case: in LDS up to 64 vertices, in
                                   HBM with 128-bit rows */
-    int32_t use_graph;         /* 1: mcs_plan_run replays a HIP graph */
+    int32_t use_graph;         /* 1: mcs_plan_run replays a HIP graph that holds
+                                  a whole solve: the input copy (from pinned
+                                  host memory the plan allocates once), the
+                                  reset and search kernels, and the result
+                                  copy back (mcs_plan_results then only waits
+                                  and decodes) */
     int32_t stack_classes;     /* capacity of one wavefront's class stack
                                   (0: the worst case m(m+1)/2, m the largest
                                   min(nG, nH), or less if that keeps
@@ -108,6 +113,16 @@ typedef struct {
     int32_t backoff_max;       /* an idle wavefront that finds no work sleeps
                                   1, 2, 4, ... up to this many times about
                                   3.4 us before polling again (0: 32) */
+    int32_t seg_lanes;         /* search layout: 16 or 8 -- each wavefront runs
+                                  64 / seg_lanes independent searches, one per
+                                  segment of that many lanes (a node's classes
+                                  across the segment); 64 -- one search per
+                                  wavefront, whose sibling children share the
+                                  lanes; 0: 16.  Rows of more than 64 bits and
+                                  the learned policy always use 64.  With
+                                  segments, waves_per_cu counts wavefronts
+                                  (default about 48 searches per CU) and
+                                  children_per_wave is not used. */
 } mcs_tuning;
 
 typedef struct {
@@ -177,6 +192,11 @@ typedef struct {
                                   partners'), and the classes of each pushed
                                   frame, written once and read twice (headers
                                   and mapping entries are not counted) */
+    int64_t node_classes;      /* classes split by the matched children counted
+                                  in nodes, each counted once (siblings that a
+                                  batch evaluates again after a descent are
+                                  not): the algorithmic unit of the split and
+                                  Eq. 1 work */
 } mcs_stats;
 
 typedef struct mcs_plan mcs_plan;

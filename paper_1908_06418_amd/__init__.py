@@ -48,12 +48,13 @@ class Tuning:
     use_graph: int = 0
     stack_classes: int = 0
     backoff_max: int = 0
+    seg_lanes: int = 0
 
     def to_c(self) -> _abi.mcs_tuning:
         return _abi.mcs_tuning(self.waves_per_cu, self.children_per_wave, self.ring_slots,
                                self.donate_low, self.donate_depth, self.check_interval,
                                self.no_reprune, self.single_wave, self.use_graph,
-                               self.stack_classes, self.backoff_max)
+                               self.stack_classes, self.backoff_max, self.seg_lanes)
 
 
 class _Marshal:
@@ -144,6 +145,7 @@ class Stats:
     max_stack_used: int = 0
     sleep_wave_s: float = 0.0
     lds_bytes: int = 0
+    node_classes: int = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -231,7 +233,8 @@ class Plan:
                      int(s.donations), int(s.pops), int(s.waves), int(s.blocks),
                      int(s.lds_per_wave), int(s.stopped), float(s.kernel_ms),
                      float(s.busy_wave_s), int(s.spills), int(s.stack_classes),
-                     int(s.max_stack_used), float(s.sleep_wave_s), int(s.lds_bytes))
+                     int(s.max_stack_used), float(s.sleep_wave_s), int(s.lds_bytes),
+                     int(s.node_classes))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -30,7 +30,8 @@ class mcs_tuning(ctypes.Structure):
                 ("donate_depth", ctypes.c_int32),
                 ("check_interval", ctypes.c_int32), ("no_reprune", ctypes.c_int32),
                 ("single_wave", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("stack_classes", ctypes.c_int32), ("backoff_max", ctypes.c_int32)]
+                ("stack_classes", ctypes.c_int32), ("backoff_max", ctypes.c_int32),
+                ("seg_lanes", ctypes.c_int32)]
 
 
 class mcs_opts(ctypes.Structure):
@@ -57,7 +58,7 @@ class mcs_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("busy_wave_s", ctypes.c_double),
                 ("spills", ctypes.c_int64), ("stack_classes", ctypes.c_int32),
                 ("max_stack_used", ctypes.c_int32), ("sleep_wave_s", ctypes.c_double),
-                ("lds_bytes", ctypes.c_int64)]
+                ("lds_bytes", ctypes.c_int64), ("node_classes", ctypes.c_int64)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/mcs.h

@@ -20,18 +20,18 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS
 
-SOURCES = ["mcs_search.hip", "mcs_policy.hip", "mcs_host.cpp"]
+SOURCES = ["mcs_search.hip", "mcs_seg.hip", "mcs_policy.hip", "mcs_host.cpp"]
 
 
 def build(verbose: bool = False) -> str:
     """Compile every source and link libmcs.so (atomically replaced)."""
+    from concurrent.futures import ThreadPoolExecutor
     with tempfile.TemporaryDirectory(prefix="mcs_build_") as tmp:
-        objs = []
-        for src in SOURCES:
-            obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
-            cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
-            _run(cmd, verbose)
-            objs.append(obj)
+        objs = [os.path.join(tmp, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+        cmds = [[HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(min(4, len(cmds))) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
         out = os.path.join(tmp, "libmcs.so")
         # No HIP runtime is linked in: the library binds to the runtime the
         # host process already has (torch's under Python, -lamdhip64 in C),

@@ -13,6 +13,7 @@
 #include "mcs_layout.h"
 
 extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed, int policy);
+extern "C" void *mcs_internal_seg_kernel(int word_bytes, int directed, int seg_log);
 extern "C" void *mcs_internal_reset_kernel(void);
 
 namespace {
@@ -279,6 +280,8 @@ struct mcs_plan {
            ws_bytes = 0;
     int ring_slots = 0, slot_bytes = 0, cap_classes = 0, frames = 0, lds_per_wave = 0;
     int waves_per_block = 4, blocks = 0, waves = 0, lds_per_block = 0;
+    int seg_log = 0;   // 3 or 4: searches of 2^seg_log lanes (mcs_seg.hip); 0: one per wavefront
+    int seg_bytes = 0, arows = 0;
     double tick_hz = 1e8;
 
     uint8_t *ws = nullptr;
@@ -288,6 +291,13 @@ struct mcs_plan {
     mcs::ResetParams rp{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipGraphNode_t gnode_search = nullptr;
+    mcs::SearchParams sp_graph{};  // the search parameters the graph's kernel node holds
+    // Graph mode stages the inputs and the results in pinned host memory:
+    // the graph copies the whole input image in, runs reset + search, and
+    // copies the whole result range out, so one replay is a complete solve.
+    uint8_t *pin = nullptr;
+    size_t pin_in_bytes = 0, pin_out_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_ms = 0.f;
 
@@ -295,10 +305,13 @@ struct mcs_plan {
     std::vector<int> h_inc, h_open;
     std::vector<unsigned long long> h_nodes, h_tbest, h_tproof;
     std::vector<uint16_t> h_maps;
+    std::vector<uint8_t> h_out;  // the result range as copied back
     mcs::DevGlobals h_glob{};
     bool have_results = false;
 
     ~mcs_plan() {
+        if (pin)
+            (void)hipHostFree(pin);
         if (gexec)
             (void)hipGraphExecDestroy(gexec);
         if (graph)
@@ -486,6 +499,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         di.map_off = (uint32_t)map_off;
         di.lb = 0;
         di.target = 0;
+        di.inc_slot = i;
+        di.twin = -1;
         p->inst[i] = di;
         p->K0.push_back(K0);
         // Eq. 1 at the root: the largest size any goal needs to consider
@@ -537,19 +552,47 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         clock_khz = 100000;
     (void)hipGetLastError();
     p->tick_hz = (double)clock_khz * 1000.0;
-    // Default: about 96 wavefronts per instance, between 8 and 24 per CU
-    // (4 and 16 with 128-bit rows, whose larger state fits fewer), so one
-    // hard instance alone still splits across thousands of them.  One
-    // wavefront's search is a long dependent chain of scalar and vector
-    // steps, so several per SIMD fill the issue slots while there is work
-    // for them; past what the instances can keep busy, more wavefronts only
-    // split the work into ever smaller donations.
     const bool wide = p->word_bytes == 16;
-    const int want_waves = p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
-                           : wide ? std::max(4 * cus, std::min(16 * cus, 96 * count))
-                                  : std::max(8 * cus, std::min(24 * cus, 96 * count));
+    // Search layout: one search per lane segment of 16 (or 8) lanes
+    // (mcs_seg.hip), or one per wavefront (mcs_search.hip: needed for
+    // 128-bit rows and for the learned policy, which scores one vertex per
+    // lane).
+    {
+        const int sl = p->tun.seg_lanes;
+        if (sl != 0 && sl != 8 && sl != 16 && sl != 64) {
+            delete p;
+            return fail(MCS_E_INVALID, "seg_lanes must be 0, 8, 16 or 64");
+        }
+        if (wide || p->policy || sl == 64)
+            p->seg_log = 0;
+        else
+            p->seg_log = sl == 8 ? 3 : 4;
+    }
+    const int nseg = p->seg_log ? 64 >> p->seg_log : 1;
+    // Default wavefronts: about 96 searches per instance, between 8 and 24
+    // per CU for one search per wavefront (4 and 16 with 128-bit rows, whose
+    // larger state fits fewer), and about 48 searches per CU (12 wavefronts
+    // of 4) for the segmented kernel, so one hard instance alone still
+    // splits across thousands of searches.  One search is a long dependent
+    // chain of steps, so several wavefronts per SIMD fill the issue slots
+    // while there is work for them; past what the instances can keep busy,
+    // more searches only split the work into ever smaller donations.
+    const int want_waves =
+        p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
+        : p->seg_log ? std::max(2 * cus, std::min((48 / nseg) * cus, (96 * count + nseg - 1) / nseg))
+        : wide       ? std::max(4 * cus, std::min(16 * cus, 96 * count))
+                     : std::max(8 * cus, std::min(24 * cus, 96 * count));
     const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
+    if (p->seg_log) {
+        // adjacency rows a segment keeps: the batch's largest graph, to 4
+        int nmax_all = 0;
+        for (int i = 0; i < count; i++)
+            nmax_all = std::max(nmax_all, std::max(G[i].n, H[i].n));
+        p->arows = std::min(NB, std::max(4, (nmax_all + 3) & ~3));
+    }
     auto per_wave = [&](int cap) {
+        if (p->seg_log)
+            return nseg * mcs::seg_layout(p->word_bytes, directed, cap, p->arows, p->frames).total;
         return mcs::lds_layout(p->word_bytes, directed, wide ? -1 : cap, p->frames,
                                p->policy_levels).total;
     };
@@ -570,13 +613,23 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         p->cap_classes = full_cap;
         const int share = lds_cu / target_wpc - 64;  // 64: a wave's part of the static LDS
         if (per_wave(full_cap) > share) {
-            const int room = share - per_wave(0) - 16;
+            const int room = share / nseg - per_wave(0) / nseg - 16;
             p->cap_classes = std::max(min_cap, std::min(full_cap, room / (2 * p->word_bytes)));
         }
     }
-    p->lds_per_wave = per_wave(p->cap_classes);
-    int wpb = 4;
+    // (the segmented kernel's headers hold a 16-bit class index)
+    if (p->seg_log && p->cap_classes > 65535)
+        p->cap_classes = 65535;
     max_lds_block -= 256;  // the kernel's static LDS (its parameter copy)
+    if (!wide && !p->tun.single_wave && per_wave(p->cap_classes) > max_lds_block) {
+        // one wavefront's stacks must fit in one workgroup's LDS
+        const int room = max_lds_block / nseg - per_wave(0) / nseg - 16;
+        p->cap_classes = std::max(min_cap, std::min(p->cap_classes, room / (2 * p->word_bytes)));
+    }
+    p->lds_per_wave = per_wave(p->cap_classes);
+    if (p->seg_log)
+        p->seg_bytes = p->lds_per_wave / nseg;
+    int wpb = 4;
     while (wpb > 1 && wpb * p->lds_per_wave > max_lds_block)
         wpb >>= 1;
     if (p->lds_per_wave > max_lds_block) {
@@ -590,7 +643,9 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     }
     p->waves_per_block = wpb;
     p->lds_per_block = wpb * p->lds_per_wave;
-    const void *kern = mcs_internal_search_kernel(p->word_bytes, directed, p->policy != nullptr);
+    const void *kern = p->seg_log ? mcs_internal_seg_kernel(p->word_bytes, directed, p->seg_log)
+                                  : mcs_internal_search_kernel(p->word_bytes, directed,
+                                                               p->policy != nullptr);
     int per_cu = 0;
     if (p->lds_per_block > 65536)
         (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -655,6 +710,7 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
         (void)hipGraphDestroy(p->graph);
         p->gexec = nullptr;
         p->graph = nullptr;
+        p->gnode_search = nullptr;
     }
     p->ws = (uint8_t *)workspace;
     hipStream_t s = as_stream(stream);
@@ -706,6 +762,9 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.node_limit = p->node_limit;
     sp.hstack = p->hstack_stride ? p->ws + p->off_hstack : nullptr;
     sp.hstack_stride = p->hstack_stride;
+    sp.seg_log = p->seg_log;
+    sp.seg_bytes = p->seg_bytes;
+    sp.arows = p->arows;
 
     mcs::ResetParams &rp = p->rp;
     rp.inst = sp.inst;
@@ -722,9 +781,14 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     return MCS_OK;
 }
 
+static void *search_fn(const mcs_plan *p) {
+    return p->seg_log ? mcs_internal_seg_kernel(p->word_bytes, p->directed, p->seg_log)
+                      : mcs_internal_search_kernel(p->word_bytes, p->directed, p->policy != nullptr);
+}
+
 static mcs_status launch_direct(mcs_plan *p, hipStream_t s) {
     const void *kr = mcs_internal_reset_kernel();
-    const void *ks = mcs_internal_search_kernel(p->word_bytes, p->directed, p->policy != nullptr);
+    const void *ks = search_fn(p);
     int n = std::max(p->count, mcs::kRings * p->ring_slots);
     int rb = std::min(1024, (n + 255) / 256);
     void *ra[] = {&p->rp};
@@ -739,9 +803,39 @@ static mcs_status launch_direct(mcs_plan *p, hipStream_t s) {
     return MCS_OK;
 }
 
+// The input image (descriptors, rows, root classes) and the result range
+// (incumbents through the globals) are each one contiguous part of the
+// workspace, so a graph moves each with a single copy.
+static size_t in_begin(const mcs_plan *p) { return p->off_inst; }
+static size_t in_end(const mcs_plan *p) { return p->off_cls + p->rootcls.size(); }
+static size_t out_begin(const mcs_plan *p) { return p->off_inc; }
+static size_t out_end(const mcs_plan *p) { return p->off_glob + sizeof(mcs::DevGlobals); }
+
+static void stage_inputs(mcs_plan *p) {
+    uint8_t *img = p->pin;
+    const size_t b = in_begin(p);
+    std::memset(img, 0, p->pin_in_bytes);
+    std::memcpy(img + (p->off_inst - b), p->inst.data(), sizeof(mcs::DevInst) * p->count);
+    std::memcpy(img + (p->off_adj - b), p->adj.data(), p->adj.size());
+    std::memcpy(img + (p->off_cls - b), p->rootcls.data(), p->rootcls.size());
+}
+
+// HIP graph of one complete solve: input copy, reset kernel, search kernel
+// (bracketed by the timing events), result copy.  No memset nodes: the reset
+// kernel clears the state with plain stores.
 static mcs_status build_graph(mcs_plan *p) {
+    if (!p->pin) {
+        p->pin_in_bytes = in_end(p) - in_begin(p);
+        p->pin_out_bytes = out_end(p) - out_begin(p);
+        HIP_TRY(hipHostMalloc((void **)&p->pin, p->pin_in_bytes + p->pin_out_bytes,
+                              hipHostMallocDefault));
+    }
+    stage_inputs(p);
     HIP_TRY(hipGraphCreate(&p->graph, 0));
-    hipGraphNode_t nr = nullptr, ns = nullptr;
+    hipGraphNode_t nin = nullptr, nr = nullptr, ne0 = nullptr, ns = nullptr, ne1 = nullptr,
+                   nout = nullptr;
+    HIP_TRY(hipGraphAddMemcpyNode1D(&nin, p->graph, nullptr, 0, p->ws + in_begin(p), p->pin,
+                                    p->pin_in_bytes, hipMemcpyHostToDevice));
     int n = std::max(p->count, mcs::kRings * p->ring_slots);
     void *ra[] = {&p->rp};
     void *sa[] = {&p->sp};
@@ -752,16 +846,42 @@ static mcs_status build_graph(mcs_plan *p) {
     kp.sharedMemBytes = 0;
     kp.kernelParams = ra;
     kp.extra = nullptr;
-    HIP_TRY(hipGraphAddKernelNode(&nr, p->graph, nullptr, 0, &kp));
+    HIP_TRY(hipGraphAddKernelNode(&nr, p->graph, &nin, 1, &kp));
+    HIP_TRY(hipGraphAddEventRecordNode(&ne0, p->graph, &nr, 1, p->ev0));
     hipKernelNodeParams ks{};
-    ks.func = mcs_internal_search_kernel(p->word_bytes, p->directed, p->policy != nullptr);
+    ks.func = search_fn(p);
     ks.gridDim = dim3(p->blocks);
     ks.blockDim = dim3(64 * p->waves_per_block);
     ks.sharedMemBytes = (unsigned)p->lds_per_block;
     ks.kernelParams = sa;
     ks.extra = nullptr;
-    HIP_TRY(hipGraphAddKernelNode(&ns, p->graph, &nr, 1, &ks));
+    HIP_TRY(hipGraphAddKernelNode(&ns, p->graph, &ne0, 1, &ks));
+    HIP_TRY(hipGraphAddEventRecordNode(&ne1, p->graph, &ns, 1, p->ev1));
+    HIP_TRY(hipGraphAddMemcpyNode1D(&nout, p->graph, &ne1, 1, p->pin + p->pin_in_bytes,
+                                    p->ws + out_begin(p), p->pin_out_bytes,
+                                    hipMemcpyDeviceToHost));
     HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+    p->gnode_search = ns;
+    p->sp_graph = p->sp;
+    return MCS_OK;
+}
+
+// Kernel-node arguments are copied when the node is made: a run after the
+// search parameters changed (a goal run dropping the node limit, say) must
+// hand the new ones to the instantiated graph.
+static mcs_status refresh_graph_params(mcs_plan *p) {
+    if (std::memcmp(&p->sp_graph, &p->sp, sizeof(p->sp)) == 0)
+        return MCS_OK;
+    void *sa[] = {&p->sp};
+    hipKernelNodeParams ks{};
+    ks.func = search_fn(p);
+    ks.gridDim = dim3(p->blocks);
+    ks.blockDim = dim3(64 * p->waves_per_block);
+    ks.sharedMemBytes = (unsigned)p->lds_per_block;
+    ks.kernelParams = sa;
+    ks.extra = nullptr;
+    HIP_TRY(hipGraphExecKernelNodeSetParams(p->gexec, p->gnode_search, &ks));
+    p->sp_graph = p->sp;
     return MCS_OK;
 }
 
@@ -777,15 +897,18 @@ mcs_status mcs_plan_run(mcs_plan *p, void *stream) {
         HIP_TRY(hipEventCreate(&p->ev1));
     }
     p->have_results = false;
+    p->launched = false;
     if (p->tun.use_graph) {
         if (!p->gexec) {
             mcs_status st = build_graph(p);
             if (st != MCS_OK)
                 return st;
+        } else {
+            mcs_status st = refresh_graph_params(p);
+            if (st != MCS_OK)
+                return st;
         }
-        HIP_TRY(hipEventRecord(p->ev0, s));
         HIP_TRY(hipGraphLaunch(p->gexec, s));
-        HIP_TRY(hipEventRecord(p->ev1, s));
     } else {
         mcs_status st = launch_direct(p, s);
         if (st != MCS_OK)
@@ -803,28 +926,32 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
         return fail(MCS_E_INVALID, "mcs_plan_run has not been called");
     hipStream_t s = as_stream(stream);
     int n = p->count;
-    p->h_inc.resize(n);
-    p->h_open.resize(n);
-    p->h_nodes.resize(n);
-    p->h_tbest.resize(n);
-    p->h_tproof.resize(n);
-    p->h_maps.resize(p->map_pairs);
-    HIP_TRY(hipMemcpyAsync(p->h_inc.data(), p->ws + p->off_inc, sizeof(int) * n,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(p->h_open.data(), p->ws + p->off_open, sizeof(int) * n,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(p->h_nodes.data(), p->ws + p->off_nodes, 8 * (size_t)n,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(p->h_tbest.data(), p->ws + p->off_tbest, 8 * (size_t)n,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(p->h_tproof.data(), p->ws + p->off_tproof, 8 * (size_t)n,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(p->h_maps.data(), p->ws + p->off_maps, 2 * p->map_pairs,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&p->h_glob, p->ws + p->off_glob, sizeof(mcs::DevGlobals),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    const size_t ob = out_begin(p);
+    p->h_out.resize(out_end(p) - ob);
+    if (p->tun.use_graph && p->gexec) {
+        // the graph's last node already copied the result range to pinned memory
+        HIP_TRY(hipStreamSynchronize(s));
+        std::memcpy(p->h_out.data(), p->pin + p->pin_in_bytes, p->h_out.size());
+    } else {
+        HIP_TRY(hipMemcpyAsync(p->h_out.data(), p->ws + ob, p->h_out.size(),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     HIP_TRY(hipGetLastError());
+    const uint8_t *o = p->h_out.data();
+    p->h_inc.assign((const int *)(o + (p->off_inc - ob)), (const int *)(o + (p->off_inc - ob)) + n);
+    p->h_open.assign((const int *)(o + (p->off_open - ob)),
+                     (const int *)(o + (p->off_open - ob)) + n);
+    auto u64s = [&](size_t off) {
+        const unsigned long long *q = (const unsigned long long *)(o + (off - ob));
+        return std::vector<unsigned long long>(q, q + n);
+    };
+    p->h_nodes = u64s(p->off_nodes);
+    p->h_tbest = u64s(p->off_tbest);
+    p->h_tproof = u64s(p->off_tproof);
+    p->h_maps.assign((const uint16_t *)(o + (p->off_maps - ob)),
+                     (const uint16_t *)(o + (p->off_maps - ob)) + p->map_pairs);
+    std::memcpy(&p->h_glob, o + (p->off_glob - ob), sizeof(mcs::DevGlobals));
     if (p->ev0 && hipEventElapsedTime(&p->last_ms, p->ev0, p->ev1) != hipSuccess) {
         (void)hipGetLastError();
         p->last_ms = 0.f;
@@ -841,7 +968,7 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
     bool all_proven = true;
     for (int i = 0; i < n; i++) {
         mcs_result &r = res[i];
-        int size = p->h_inc[i];
+        int size = p->h_inc[p->inst[i].inc_slot];
         bool proven = p->h_tproof[i] != 0 && p->h_open[i] == 0;
         all_proven = all_proven && proven;
         r.size = size;
@@ -850,7 +977,9 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
         unsigned long long kb = p->h_tbest[i];
         r.t_best_s = kb ? (double)(((kb & mask48) - (t0 & mask48)) & mask48) / p->tick_hz : 0.0;
         r.t_proof_s = proven ? (double)(p->h_tproof[i] - t0) / p->tick_hz : 0.0;
-        if (size > p->inst[i].lb && size > 0) {
+        // the mapping of the final size sits in the slots of the instance
+        // that raised the incumbent to it (a portfolio twin may not have)
+        if (size > p->inst[i].lb && size > 0 && (int)(kb >> 48) == size) {
             size_t off = p->inst[i].map_off + (size_t)size * (size - 1) / 2;
             for (int j = 0; j < size; j++) {
                 uint16_t e = p->h_maps[off + j];
@@ -891,10 +1020,13 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     // classes (L and R words) are written once and read twice (at the descent
     // and when the search returns to the frame).
     {
-        const int64_t rows = (int64_t)p->h_glob.batches + (int64_t)p->h_glob.children;
+        // (the segmented kernel reads both rows per child; "batches" are its steps)
+        const int64_t rows = p->seg_log ? 2 * (int64_t)p->h_glob.children
+                                        : (int64_t)p->h_glob.batches + (int64_t)p->h_glob.children;
         const int rw = (p->directed ? 2 : 1) * p->word_bytes;
         z.lds_bytes = rows * rw + (int64_t)p->h_glob.pushed_classes * 3 * 2 * p->word_bytes;
     }
+    z.node_classes = (int64_t)p->h_glob.node_classes;
     z.stack_classes = p->cap_classes;
     z.max_stack_used = p->h_glob.max_stack;
     *st = z;
@@ -915,6 +1047,8 @@ mcs_status mcs_plan_set_goals(mcs_plan *p, const int32_t *goal, void *stream) {
         di.lb = goal[i] > 0 ? goal[i] - 1 : 0;
         di.target = goal[i] > 0 ? goal[i] : 0;
     }
+    if (p->pin)
+        stage_inputs(p);  // a graph replay copies the descriptors in from here
     HIP_TRY(hipMemcpyAsync(p->ws + p->off_inst, p->inst.data(), sizeof(mcs::DevInst) * p->count,
                            hipMemcpyHostToDevice, as_stream(stream)));
     HIP_TRY(hipStreamSynchronize(as_stream(stream)));

@@ -13,6 +13,10 @@ struct DevInst {
     uint32_t map_off;  // first mapping pair of this instance's per-size slots
     int32_t lb;        // initial incumbent size (0: none)
     int32_t target;    // > 0: stop this instance once a mapping of this size is found
+    int32_t inc_slot;  // incumbent word this instance reads and raises (its own
+                       // index, or its portfolio twin's: twins share one)
+    int32_t twin;      // the same pair entered under another vertex order, or -1;
+                       // once either twin's search is finished the other stops
     int32_t pad2;
 };
 
@@ -63,6 +67,9 @@ struct DevGlobals {
     unsigned long long spills;      // children queued for want of stack room
     unsigned long long sleep_ticks; // realtime ticks idle wavefronts spent sleeping
     unsigned long long pushed_classes;  // classes in the frames pushed onto LDS stacks
+    unsigned long long node_classes;    // classes split, summed over the matched
+                                        // children counted as nodes (first
+                                        // evaluations only)
     int max_stack;                  // most classes any wavefront's stack held
     int pad1;
 };
@@ -101,6 +108,11 @@ struct SearchParams {
     long long node_limit;            // 0: none
     uint8_t *hstack;                 // (128-bit rows) [waves][hstack_stride] class stacks
     long long hstack_stride;         // bytes per wavefront: (cap_classes + 1) (L, R) pairs
+    int seg_log;                     // segmented kernel: 2^seg_log lanes per search (0: one
+                                     // search per wavefront)
+    int seg_bytes;                   // segmented kernel: LDS bytes per search (seg_layout)
+    int arows;                       // segmented kernel: adjacency rows kept per graph in LDS
+    int pad_seg;
 };
 
 struct ResetParams {
@@ -162,6 +174,30 @@ inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_clas
     L.hdr = align16(L.map + 2 * nb);
     L.ord = align16(L.hdr + frames * hdr_bytes);
     L.total = align16(L.ord + policy_levels * 64);
+    return L;
+}
+
+// LDS of one search of the segmented kernel (one per lane segment), each
+// part 16-byte aligned:
+//   classes   [cap_classes + 1] (L, R) word pairs; the last is a trash slot
+//   adjacency [R][arows] words (rows past arows are never read: arows is at
+//             least the largest vertex count of the batch)
+//   mapping   [NB] byte pairs
+//   headers   [frames] frame headers of four 32-bit words
+struct SegLayout {
+    int cls, adj, map, hdr, total;
+};
+
+inline constexpr SegLayout seg_layout(int word_bytes, int directed, int cap_classes, int arows,
+                                      int frames) {
+    int nb = 8 * word_bytes;
+    int rows = directed ? 4 : 2;
+    SegLayout L{0, 0, 0, 0, 0};
+    L.cls = 0;
+    L.adj = align16((cap_classes + 1) * 2 * word_bytes);
+    L.map = align16(L.adj + rows * arows * word_bytes);
+    L.hdr = align16(L.map + 2 * nb);
+    L.total = align16(L.hdr + frames * 16);
     return L;
 }
 

@@ -43,231 +43,10 @@
 //     waves), per instance and in total; the wave that ends the last unit
 //     raises a done flag (one copy per XCD, so polling it is cheap); every
 //     wave also leaves at the time limit, so the grid always drains.
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include <hip/hip_fp16.h>
-
-#include "mcs_layout.h"
+#include "mcs_device.h"
 #include "mcs_policy.h"
 
 namespace mcs {
-
-#define DEV static __device__ __forceinline__
-
-// Rows of graphs with 65..128 vertices.
-using u128 = unsigned __int128;
-
-template <typename W>
-struct Cls {
-    W L, R;
-};
-
-// A frame header in LDS: one 32-bit word per field, written from lane f of
-// one register (v_writelane, then a single masked LDS store) and read back
-// with one LDS load and v_readlane -- no byte packing on the scalar unit.
-enum HdrField {
-    kHRremLo = 0,  // children (w of the selected class) not yet taken
-    kHRremHi,
-    kHBase,        // first class of the frame in the LDS class stack
-    kHK,
-    kHD,
-    kHV,
-    kHSel,
-    kHBound,
-    kHFlags,
-    kHLsel,
-    kHRsel,
-    kHRrem2,  // (128-bit rows) bits 64..95 and 96..127 of the partner mask
-    kHRrem3,
-};
-
-template <typename W>
-struct RecHdr {
-    uint32_t inst;
-    uint8_t K, d, v, sel, bound, flags, lsel, rsel;
-    uint8_t pad[4];
-    W rrem;
-};
-
-static_assert(kHRsel < kHdrWords && kHRrem3 < kHdrWordsWide, "header layout");
-static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>) <= kRecHeader &&
-                  sizeof(RecHdr<u128>) <= kRecHeader,
-              "record header layout");
-
-constexpr int kFlagUnmatched = 1;  // the "v unmatched" child is still to do
-constexpr int kFlagOrdered = 2;    // partners are tried in the policy's order
-constexpr int kFlagFresh = 4;      // (records only) a child whose class and v are not chosen yet
-
-// ---- bit helpers -----------------------------------------------------------
-
-DEV int popc(uint32_t x) { return __builtin_popcount(x); }
-DEV int popc(uint64_t x) { return __builtin_popcountll(x); }
-DEV int ctz(uint32_t x) { return __builtin_ctz(x); }
-DEV int ctz(uint64_t x) { return __builtin_ctzll(x); }
-
-DEV int popc(u128 x) { return popc((uint64_t)x) + popc((uint64_t)(x >> 64)); }
-DEV int ctz(u128 x) {
-    const uint64_t lo = (uint64_t)x;
-    return lo ? ctz(lo) : 64 + ctz((uint64_t)(x >> 64));
-}
-
-// ---- wave helpers ----------------------------------------------------------
-
-DEV int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
-
-DEV int sc(int x) { return __builtin_amdgcn_readfirstlane(x); }
-DEV uint32_t sc(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
-DEV uint64_t sc(uint64_t x) {
-    uint32_t lo = sc((uint32_t)x), hi = sc((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-DEV int rl(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
-DEV uint32_t rl(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
-DEV uint64_t rl(uint64_t x, int l) {
-    uint32_t lo = rl((uint32_t)x, l), hi = rl((uint32_t)(x >> 32), l);
-    return ((uint64_t)hi << 32) | lo;
-}
-DEV unsigned long long rl_ull(unsigned long long x, int l) { return (unsigned long long)rl((uint64_t)x, l); }
-DEV u128 sc(u128 x) { return ((u128)sc((uint64_t)(x >> 64)) << 64) | sc((uint64_t)x); }
-DEV u128 rl(u128 x, int l) { return ((u128)rl((uint64_t)(x >> 64), l) << 64) | rl((uint64_t)x, l); }
-
-DEV uint64_t ballot(bool p) { return __ballot(p); }
-DEV int mbcnt(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-}
-
-template <int CTRL>
-DEV int dpp(int x) { return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false); }
-
-// quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
-// row_half_mirror = 0x141, row_mirror = 0x140: all lanes of an 8-lane
-// (resp. 16-lane) group end with the group's sum.
-DEV int sum8(int x) {
-    x += dpp<0xB1>(x);
-    x += dpp<0x4E>(x);
-    x += dpp<0x141>(x);
-    return x;
-}
-DEV int sum16(int x) {
-    x = sum8(x);
-    x += dpp<0x140>(x);
-    return x;
-}
-DEV int wave_sum(int x) {
-    int s = sum16(x);
-    return rl(s, 0) + rl(s, 16) + rl(s, 32) + rl(s, 48);
-}
-DEV uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
-
-// Segmented reductions over segments of 2^logS lanes.  The result is valid
-// in the last lane of each segment (lane (c << logS) + 2^logS - 1); for
-// logS <= 4 every lane of a segment holds it.  row_bcast:15 (0x142) adds
-// lane 15 of each row into the next row (rows 1 and 3 enabled), and
-// row_bcast:31 (0x143) adds lane 31 into rows 2 and 3.
-DEV int seg_sum(int x, int logS) {
-    x = sum8(x);
-    if (logS >= 4)
-        x += dpp<0x140>(x);
-    if (logS >= 5)
-        x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);
-    if (logS >= 6)
-        x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);
-    return x;
-}
-template <int CTRL, int ROWS>
-DEV uint32_t dpp_min_id(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, CTRL, ROWS, 0xF, false);
-}
-// Minimum over the first segment (lanes 0 .. 2^logS - 1), as a scalar.
-DEV uint32_t seg0_min(uint32_t x, int logS) {
-    x = umin(x, (uint32_t)dpp<0xB1>((int)x));
-    x = umin(x, (uint32_t)dpp<0x4E>((int)x));
-    x = umin(x, (uint32_t)dpp<0x141>((int)x));
-    if (logS >= 4)
-        x = umin(x, (uint32_t)dpp<0x140>((int)x));
-    if (logS >= 5)
-        x = umin(x, dpp_min_id<0x142, 0xA>(x));
-    if (logS >= 6)
-        x = umin(x, dpp_min_id<0x143, 0xC>(x));
-    return rl(x, (1 << logS) - 1);
-}
-DEV uint32_t wave_min(uint32_t x) {
-    x = umin(x, (uint32_t)dpp<0xB1>((int)x));
-    x = umin(x, (uint32_t)dpp<0x4E>((int)x));
-    x = umin(x, (uint32_t)dpp<0x141>((int)x));
-    x = umin(x, (uint32_t)dpp<0x140>((int)x));
-    return umin(umin(rl(x, 0), rl(x, 16)), umin(rl(x, 32), rl(x, 48)));
-}
-
-// Orders LDS traffic between lanes of one wave (LDS executes a wave's
-// operations in order; this keeps the compiler from moving them).
-DEV void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-// The same for a wave's stores to global memory read back by other lanes of
-// the wave: the stores complete (reach the CU's L1 and L2) before any later
-// load issues.
-DEV void wave_sync_global() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// ---- device-scope atomics ----------------------------------------------------
-
-// Counters are relaxed: the only data handed between wavefronts is a queued
-// node record, ordered by the release/acquire pair on its slot's sequence.
-DEV int a_add_rlx(int *p, int v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-DEV unsigned a_addu(unsigned *p, unsigned v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-DEV unsigned long long a_add64(unsigned long long *p, unsigned long long v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-DEV int a_max(int *p, int v) {
-    return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-DEV void a_max64(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-DEV void a_min64(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-DEV T ld_rlx(T *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-template <typename T>
-DEV void st_rel(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); }
-template <typename T>
-DEV void st_rlx(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-// Ticket claims are relaxed: the data a ticket guards is ordered by the
-// slot's sequence number alone (see take_record and reserve).  At agent
-// scope an acquire or release costs a write-back or invalidation of the
-// XCD's whole L2, so the queue uses exactly one of each per record.
-DEV bool cas64(unsigned long long *p, unsigned long long expect, unsigned long long want) {
-    return __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_RELAXED,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-DEV unsigned long long now_ticks() { return wall_clock64(); }
-
-DEV float hf(uint16_t h) { return __half2float(__ushort_as_half(h)); }
-DEV float rlf(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
-template <int CTRL>
-DEV float fdpp(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-DEV float fwave_sum(float x) {
-    x += fdpp<0xB1>(x);
-    x += fdpp<0x4E>(x);
-    x += fdpp<0x141>(x);
-    x += fdpp<0x140>(x);
-    return (rlf(x, 0) + rlf(x, 16)) + (rlf(x, 32) + rlf(x, 48));
-}
 
 // ---- one wavefront's search ------------------------------------------------
 
@@ -289,6 +68,7 @@ struct Searcher {
 
     uint8_t *sord;  // [policy levels][64]: partner order of policy-ordered frames
     int inst, map_off, nG, nH, target;
+    int inc_slot, twin;  // shared incumbent word; portfolio twin (or -1)
     // top frame, wave-uniform
     int t, base, K, d, v, sel, bound, flags, lsel, rsel;
     W rrem;
@@ -309,11 +89,11 @@ struct Searcher {
     int max_used;  // most classes this wavefront's stack has held
     // per-step counts since the last fold into the 64-bit totals (at most
     // check_interval steps, so 32 bits cannot overflow)
-    uint32_t c_nodes, c_batches, c_children, c_lanes;
+    uint32_t c_nodes, c_batches, c_children, c_lanes, c_ncls;
     // classes in frames pushed since the last fold (the host turns this and
     // the batch counts into the bytes the search moves through LDS)
     uint32_t c_pushed;
-    unsigned long long n_pushed;
+    unsigned long long n_pushed, n_ncls;
 
     __device__ Searcher(const SearchParams &p, uint8_t *lds, int wave) : P(p) {
         lane = lane_id();
@@ -337,6 +117,8 @@ struct Searcher {
         map_off = 0;
         nG = nH = 1;
         target = 0;
+        inc_slot = 0;
+        twin = -1;
         stop = false;
         roots_left = true;
         my_ring = (int)(blockIdx.x & (kRings - 1));
@@ -344,8 +126,8 @@ struct Searcher {
         d0 = 0;
         since_check = 0;
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = n_busy = 0;
-        c_nodes = c_batches = c_children = c_lanes = c_pushed = 0;
-        n_pushed = 0;
+        c_nodes = c_batches = c_children = c_lanes = c_pushed = c_ncls = 0;
+        n_pushed = n_ncls = 0;
         n_spill = n_sleep = 0;
         max_used = 0;
         inc = 0;
@@ -682,10 +464,16 @@ struct Searcher {
             nG = (int)P.inst[i].nG;
             nH = (int)P.inst[i].nH;
             target = (int)P.inst[i].target;
+            inc_slot = (int)P.inst[i].inc_slot;
+            twin = (int)P.inst[i].twin;
         }
         int g = 0;
-        if (lane == 0)
-            g = ld_rlx(&P.inc[i]);
+        if (lane == 0) {
+            g = ld_rlx(&P.inc[inc_slot]);
+            // the twin's search already finished: nothing is left to prove
+            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0)
+                g = 255;
+        }
         inc = cap_inc(rl(g, 0));
         sync();
     }
@@ -742,7 +530,7 @@ struct Searcher {
     __device__ void improve(int size) {
         int old = 0;
         if (lane == 0)
-            old = a_max(&P.inc[inst], size);
+            old = a_max(&P.inc[inc_slot], size);
         old = rl(old, 0);
         if (old < size) {
             uint16_t *dst = P.maps + map_off + size * (size - 1) / 2;
@@ -864,6 +652,7 @@ struct Searcher {
         c_batches += 1;
         c_children += (uint32_t)C;
         c_lanes += (uint32_t)(C * K);
+        c_ncls += (uint32_t)((C - nsurv + (nsurv ? 1 : 0)) * K);
 
         // drop the pruned children and the one we descend into; the other
         // survivors stay in rrem and are evaluated again after the descent
@@ -1027,6 +816,7 @@ struct Searcher {
         c_batches += 1;
         c_children += (uint32_t)C;
         c_lanes += (uint32_t)(C * (K < S ? K : S));
+        c_ncls += (uint32_t)((C - nsurv + (nsurv ? 1 : 0)) * K);
 
         // the child of rank r took the r-th lowest vertex of rrem
         const uint64_t mlo = (uint64_t)rrem, mhi = (uint64_t)(rrem >> 64);
@@ -1524,7 +1314,8 @@ struct Searcher {
         n_children += c_children;
         n_lanes += c_lanes;
         n_pushed += c_pushed;
-        c_nodes = c_batches = c_children = c_lanes = c_pushed = 0;
+        n_ncls += c_ncls;
+        c_nodes = c_batches = c_children = c_lanes = c_pushed = c_ncls = 0;
     }
 
     __device__ void flush_nodes() {
@@ -1552,7 +1343,9 @@ struct Searcher {
         int gi = 0;
         unsigned fl = 0;
         if (lane == 0) {
-            gi = ld_rlx(&P.inc[inst]);
+            gi = ld_rlx(&P.inc[inc_slot]);
+            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0)
+                gi = 255;
             fl = ld_rlx(&P.g->xcd[my_ring].flag);
             if (may_donate) {
                 tl = ld_rlx(&P.g->ring[my_ring].tail);
@@ -1685,6 +1478,7 @@ struct Searcher {
             a_add64(&P.g->busy_ticks, n_busy);
             a_add64(&P.g->spills, n_spill);
             a_add64(&P.g->pushed_classes, n_pushed);
+            a_add64(&P.g->node_classes, n_ncls);
             a_add64(&P.g->sleep_ticks, n_sleep);
             __hip_atomic_fetch_max(&P.g->max_stack, max_used, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);

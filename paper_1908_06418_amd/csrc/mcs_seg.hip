@@ -1,0 +1,1183 @@
+// McSplit search with one depth-first search per lane segment (gfx950).
+//
+// The work per search node is the paper's Solve body (Sec. II.B, Algorithm 1):
+// split every label class by adjacency to v (G side) and to w (H side) --
+// filterDomain -- and bound the child with Eq. 1,
+//     bound = |M| + sum over classes of min(|L|, |R|),
+// pruning it when the bound cannot beat the incumbent.
+//
+// Layout (ours): a wavefront is cut into 64 / S segments of S = 8 or 16
+// lanes, and each segment runs its own search.  Lane k of a segment holds
+// class k of the segment's top frame (classes k + S, k + 2S, ... of a frame
+// with more than S classes are read from LDS in further passes).  Every
+// per-search value -- the frame (depth, selected class, v, remaining
+// partners, bound), the instance, the incumbent -- is a vector register that
+// is uniform within the segment, so the search's bookkeeping runs on the
+// vector unit for all segments at once instead of on the CU's single scalar
+// unit.  Segment reductions (the Eq. 1 sum, the class-choice minimum) are
+// DPP steps that stay inside 8- or 16-lane groups.
+//
+// The segments advance in lock step.  One step is, for each segment, in this
+// order and only where it applies:
+//   pop       -- the top frame has nothing left: return to the parent frame;
+//   unmatched -- the top frame's partners are done: take its "v unmatched"
+//                child in place (its bound follows from the parent's);
+//   evaluate  -- split the classes for the next partner w of v, bound the
+//                child, and either prune it or push it as the new top frame
+//                and choose its class and v.
+// A phase no segment needs is skipped (a uniform branch on a ballot).
+// Children are evaluated one per step, in ascending w, each exactly once.
+//
+// Work sharing, incumbents and termination are those of the one-search-per-
+// wavefront kernel (mcs_search.hip), applied per segment: node records in
+// per-XCD rings in HBM (a segment with no work takes one, or claims the next
+// unstarted instance), a busy segment donates its shallowest open frame when
+// its XCD's ring runs low, per-instance incumbents raised by atomicMax, and a
+// count of live work units whose last decrement raises the done flag.
+#include "mcs_device.h"
+
+namespace mcs {
+
+// Frame header of a segment: four 32-bit words (one 16-byte LDS access).
+//   x, y: the remaining partners of v (low and high word)
+//   z:    base (first class, 16 bits) | K << 16 | d << 24
+//   w:    v | sel << 8 | bound << 16 | flags << 24
+// |L_sel| and |R_sel| are not stored: the selected class itself is not
+// changed while its frame is open (only its partner copy is), so they are
+// counted again when the search returns to the frame.
+
+template <int CTRL>
+DEV uint32_t dpp_min_step(uint32_t x) {
+    return umin(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false));
+}
+
+template <typename W, bool DIR, int LOGS>
+struct SegSearch {
+    static constexpr int S = 1 << LOGS;    // lanes per segment
+    static constexpr int NSEG = 64 / S;    // searches per wavefront
+    static constexpr int NB = bits_of<W>();
+    static constexpr int NR = DIR ? 4 : 2;
+    static constexpr uint32_t SEGMASK = S == 32 ? 0xFFFFFFFFu : ((1u << S) - 1);
+
+    const SearchParams &P;
+    // knobs (wave-uniform)
+    int cap, check_interval, reprune, arows;
+    // lane identity
+    int lane, lk, seg;
+    // this lane's segment's LDS
+    Cls<W> *scls;     // [cap + 1]: the last entry is a trash slot
+    W *sadj;          // [NR][arows]
+    uint16_t *smap;   // [NB] g | h << 8 per depth
+    uint4 *shdr;      // [frames]
+    uint8_t *wlds;    // the wavefront's LDS (segment j at j * seg_bytes)
+    int seg_bytes;
+
+    // ---- per-segment state (uniform within a segment) ----
+    int inst;         // instance of the segment's unit, -1: no unit
+    int adj_inst;     // instance whose rows are in the segment's LDS
+    int inc_slot, twin, map_off, target;
+    int t, base, K, d, v, sel, bound, flags, lsel, rsel, inc, d0;
+    W rrem;
+    W cL, cR;         // this lane's class of the top frame (class lk)
+    uint32_t nodes_pend;  // nodes of the unit not yet added to the instance's count
+    bool fin;         // the unit is finished (its stack emptied)
+    bool spill;       // the child just evaluated did not fit: queue it
+    int spill_w, spill_b;
+    unsigned long long pushed;  // classes in the frames this segment pushed
+
+    // ---- wave-level ----
+    bool stop;
+    bool roots_left;
+    int my_ring, steal_from;
+    int since_check;
+    int donor;        // segment considered first for the next donation
+    unsigned long long t_start;
+    unsigned long long n_steps, n_evals, n_nodes_wave, n_lanes, n_don, n_pops, n_busy, n_spill,
+        n_sleep, n_pushed, n_ncls;
+    int max_used;
+
+    __device__ SegSearch(const SearchParams &p, uint8_t *wave_lds) : P(p) {
+        lane = lane_id();
+        lk = lane & (S - 1);
+        seg = lane >> LOGS;
+        cap = sc(p.cap_classes);
+        check_interval = sc(p.check_interval);
+        reprune = sc(p.reprune);
+        arows = sc(p.arows);
+        seg_bytes = sc(p.seg_bytes);
+        wlds = wave_lds;
+        const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes, p.arows,
+                                       p.frames);
+        uint8_t *mine = wave_lds + (size_t)seg * (size_t)seg_bytes;
+        scls = (Cls<W> *)(mine + L.cls);
+        sadj = (W *)(mine + L.adj);
+        smap = (uint16_t *)(mine + L.map);
+        shdr = (uint4 *)(mine + L.hdr);
+        inst = -1;
+        adj_inst = -1;
+        inc_slot = 0;
+        twin = -1;
+        map_off = 0;
+        target = 0;
+        t = -1;
+        base = K = d = v = sel = bound = flags = lsel = rsel = inc = d0 = 0;
+        rrem = cL = cR = 0;
+        nodes_pend = 0;
+        fin = false;
+        spill = false;
+        spill_w = spill_b = 0;
+        pushed = 0;
+        stop = false;
+        roots_left = true;
+        my_ring = (int)(blockIdx.x & (kRings - 1));
+        steal_from = my_ring;
+        since_check = 0;
+        donor = 0;
+        n_steps = n_evals = n_nodes_wave = n_lanes = n_don = n_pops = n_busy = n_spill = 0;
+        n_sleep = n_pushed = n_ncls = 0;
+        max_used = 0;
+    }
+
+    // ---- segment helpers ----
+
+    // Sum over the segment, in every lane of it.
+    __device__ int ssum(int x) const {
+        x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+        x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+        x += dpp<0x141>(x);  // row_half_mirror: the other quad of the 8-lane half
+        if (LOGS >= 4)
+            x += dpp<0x140>(x);  // row_mirror: the other half of the 16-lane row
+        return x;
+    }
+    // Minimum over the segment, in every lane of it.
+    __device__ uint32_t smin(uint32_t x) const {
+        x = dpp_min_step<0xB1>(x);
+        x = dpp_min_step<0x4E>(x);
+        x = dpp_min_step<0x141>(x);
+        if (LOGS >= 4)
+            x = dpp_min_step<0x140>(x);
+        return x;
+    }
+    // Lane 0 of the segment's value, in every lane of it.
+    __device__ int sfirst(int x) const {
+        return __builtin_amdgcn_ds_bpermute((lane & ~(S - 1)) << 2, x);
+    }
+    // This segment's bits of a ballot.
+    __device__ uint32_t sbits(uint64_t m) const { return (uint32_t)(m >> (seg << LOGS)) & SEGMASK; }
+    __device__ int below(uint32_t bits) const {
+        return __builtin_popcount(bits & ((1u << lk) - 1u));
+    }
+    // Segment j's value of a per-segment register, as a scalar.
+    DEV int of(int x, int j) { return rl(x, j << LOGS); }
+    DEV W ofw(W x, int j) { return (W)rl((uint64_t)x, j << LOGS); }
+
+    // Segment j's LDS.
+    __device__ Cls<W> *cls_of(int j) const {
+        const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
+        return (Cls<W> *)(wlds + (size_t)j * seg_bytes + L.cls);
+    }
+    __device__ W *adj_of(int j) const {
+        const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
+        return (W *)(wlds + (size_t)j * seg_bytes + L.adj);
+    }
+    __device__ uint16_t *map_of(int j) const {
+        const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
+        return (uint16_t *)(wlds + (size_t)j * seg_bytes + L.map);
+    }
+    __device__ uint4 *hdr_of(int j) const {
+        const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
+        return (uint4 *)(wlds + (size_t)j * seg_bytes + L.hdr);
+    }
+
+    // ---- frames ----
+
+    __device__ uint4 pack_hdr() const {
+        uint4 h;
+        h.x = (uint32_t)rrem;
+        h.y = sizeof(W) >= 8 ? (uint32_t)((uint64_t)rrem >> 32) : 0u;
+        h.z = (uint32_t)base | ((uint32_t)K << 16) | ((uint32_t)d << 24);
+        h.w = (uint32_t)v | ((uint32_t)sel << 8) | ((uint32_t)bound << 16) |
+              ((uint32_t)flags << 24);
+        return h;
+    }
+    __device__ void save_hdr() {
+        const uint4 h = pack_hdr();
+        if (lk == 0)
+            shdr[t] = h;
+    }
+    __device__ void read_hdr(int i) {
+        const uint4 h = shdr[i];
+        W r = (W)h.x;
+        if constexpr (sizeof(W) >= 8)
+            r |= (W)h.y << 32;
+        rrem = r;
+        base = (int)(h.z & 0xFFFFu);
+        K = (int)((h.z >> 16) & 0xFFu);
+        d = (int)(h.z >> 24);
+        v = (int)(h.w & 0xFFu);
+        sel = (int)((h.w >> 8) & 0xFFu);
+        bound = (int)((h.w >> 16) & 0xFFu);
+        flags = (int)(h.w >> 24);
+    }
+
+    // Class lk of the top frame into registers.
+    __device__ void load_regs() {
+        const bool in = lk < K;
+        const Cls<W> c = scls[base + (in ? lk : 0)];
+        cL = in ? c.L : (W)0;
+        cR = in ? c.R : (W)0;
+    }
+
+    // selectLabelClass + selectVertex: the class of smallest max(|L|, |R|),
+    // ties to the one holding the smallest G vertex; v = that vertex.  The
+    // key carries the class index in its low byte (never deciding: L sets
+    // are disjoint, so ctz(L) already differs between classes).
+    __device__ void select() {
+        uint32_t key = 0xFFFFFFFFu;
+        if (lk < K) {
+            const int nl = popc(cL), nr = popc(cR);
+            key = ((uint32_t)(nl > nr ? nl : nr) << 16) | ((uint32_t)ctz(cL) << 8) | (uint32_t)lk;
+        }
+        for (int c = 1; ballot(c * S < K) != 0; ++c) {
+            const int k = c * S + lk;
+            if (k < K) {
+                const Cls<W> x = scls[base + k];
+                const int nl = popc(x.L), nr = popc(x.R);
+                key = umin(key, ((uint32_t)(nl > nr ? nl : nr) << 16) |
+                                    ((uint32_t)ctz(x.L) << 8) | (uint32_t)k);
+            }
+        }
+        const uint32_t mk = smin(key);
+        v = (int)((mk >> 8) & 0xFFu);
+        sel = (int)(mk & 0xFFu);
+        const Cls<W> cs = scls[base + sel];
+        rrem = cs.R;
+        lsel = popc(cs.L);
+        rsel = popc(cs.R);
+    }
+
+    // |L_sel| and |R_sel| of a frame the search returns to.
+    __device__ void recount_sel() {
+        const Cls<W> cs = scls[base + sel];
+        lsel = popc(cs.L);
+        rsel = popc(cs.R);
+    }
+
+    // ---- incumbent ----
+
+    __device__ int cap_inc(int x) const { return (target > 0 && x >= target) ? 255 : x; }
+    __device__ void set_inc(int x) {
+        x = cap_inc(x);
+        inc = x > inc ? x : inc;
+    }
+
+    // The path smap[0 .. size-1] is a common induced subgraph of `size`
+    // vertices: raise the instance's incumbent; the segment that raised it
+    // to `size` writes the mapping into that size's slot.
+    __device__ void improve(int size) {
+        int old = 0;
+        if (lk == 0)
+            old = a_max(&P.inc[inc_slot], size);
+        old = sfirst(old);
+        if (old < size) {
+            uint16_t *dst = P.maps + map_off + size * (size - 1) / 2;
+            for (int j = lk; j < size; j += S)
+                dst[j] = smap[j];
+            if (lk == 0)
+                a_max64(&P.t_best[inst], ((unsigned long long)size << 48) |
+                                             (now_ticks() & 0xFFFFFFFFFFFFull));
+        }
+        set_inc(old > size ? old : size);
+    }
+
+    // ---- the three phases of a step ----
+
+    __device__ void pop() {
+        t -= 1;
+        if (t < 0) {
+            fin = true;
+            rrem = 0;
+            flags = 0;
+            return;
+        }
+        read_hdr(t);
+        if (reprune && bound <= inc) {
+            rrem = 0;
+            flags = 0;  // nothing here can beat the incumbent: pop again
+            return;
+        }
+        if (rrem == 0 && !(flags & kFlagUnmatched))
+            return;
+        load_regs();
+        recount_sel();
+    }
+
+    // The "v unmatched" child, in place: only the selected class loses v.
+    __device__ void unmatched() {
+        flags = 0;
+        const int ub = bound - (lsel <= rsel ? 1 : 0);
+        nodes_pend += 1;
+        if (ub <= inc)
+            return;
+        const W vb = (W)1 << v;
+        if (lsel == 1) {
+            // the class empties on the G side: the last class takes its place
+            const int last = K - 1;
+            if (sel != last) {
+                const Cls<W> c = scls[base + last];
+                if (lk == 0)
+                    scls[base + sel] = c;
+            }
+            K = last;
+        } else {
+            const Cls<W> c = scls[base + sel];
+            if (lk == 0)
+                scls[base + sel].L = c.L & ~vb;
+        }
+        wave_sync();
+        bound = ub;
+        if (K == 0)
+            return;
+        flags = kFlagUnmatched;
+        load_regs();
+        select();
+    }
+
+    // Parts of class (L, R) for the child (v, w), by adjacency letter.
+    __device__ void split(W L, W R, W go, W ho, W gi, W hi, W *pl, W *pr) const {
+        if constexpr (!DIR) {
+            pl[0] = L & ~go;
+            pr[0] = R & ~ho;
+            pl[1] = L & go;
+            pr[1] = R & ho;
+        } else {
+            pl[0] = L & ~go & ~gi;
+            pr[0] = R & ~ho & ~hi;
+            pl[1] = L & go & ~gi;
+            pr[1] = R & ho & ~hi;
+            pl[2] = L & ~go & gi;
+            pr[2] = R & ~ho & hi;
+            pl[3] = L & go & gi;
+            pr[3] = R & ho & hi;
+        }
+    }
+    DEV int part_min(const W *pl, const W *pr) {
+        int s = 0;
+#pragma unroll
+        for (int a = 0; a < NR; ++a) {
+            const int nl = popc(pl[a]), nr = popc(pr[a]);
+            s += nl < nr ? nl : nr;
+        }
+        return s;
+    }
+
+    // The next partner w of v: split, Eq. 1, then prune or descend.
+    __device__ void evaluate() {
+        const int w = ctz(rrem);
+        rrem &= rrem - 1;
+        const W vb = (W)1 << v;
+        const W wb = (W)1 << w;
+        const W go = sadj[v], ho = sadj[arows + w];
+        W gi = 0, hi = 0;
+        if constexpr (DIR) {
+            gi = sadj[2 * arows + v];
+            hi = sadj[3 * arows + w];
+        }
+        W pl[NR], pr[NR];
+        split(cL & ~vb, cR & ~wb, go, ho, gi, hi, pl, pr);
+        int contrib = part_min(pl, pr);
+        for (int c = 1; ballot(c * S < K) != 0; ++c) {
+            const int k = c * S + lk;
+            if (k < K) {
+                const Cls<W> x = scls[base + k];
+                W ql[NR], qr[NR];
+                split(x.L & ~vb, x.R & ~wb, go, ho, gi, hi, ql, qr);
+                contrib += part_min(ql, qr);
+            }
+        }
+        const int b = d + 1 + ssum(contrib);
+        nodes_pend += 1;
+        if (b > inc)
+            descend(w, b, go, ho, gi, hi, pl, pr);
+    }
+
+    // The child (v, w) survived its bound: compact its non-empty classes
+    // into a new frame above the top one and make it the top frame.
+    __device__ void descend(int w, int b, W go, W ho, W gi, W hi, const W *pl, const W *pr) {
+        const int nb = base + K;
+        int K2 = 0;
+#pragma unroll
+        for (int a = 0; a < NR; ++a) {
+            const bool ne = pl[a] != 0 && pr[a] != 0;
+            const uint32_t m = sbits(ballot(ne));
+            const int at = nb + K2 + below(m);
+            Cls<W> c;
+            c.L = pl[a];
+            c.R = pr[a];
+            scls[(ne && at < cap) ? at : cap] = c;
+            K2 += __builtin_popcount(m);
+        }
+        const W vb = (W)1 << v;
+        const W wb = (W)1 << w;
+        for (int c = 1; ballot(c * S < K) != 0; ++c) {
+            const int k = c * S + lk;
+            W ql[NR], qr[NR];
+            const bool in = k < K;
+            const Cls<W> x = scls[base + (in ? k : 0)];
+            split(in ? x.L & ~vb : (W)0, in ? x.R & ~wb : (W)0, go, ho, gi, hi, ql, qr);
+#pragma unroll
+            for (int a = 0; a < NR; ++a) {
+                const bool ne = ql[a] != 0 && qr[a] != 0;
+                const uint32_t m = sbits(ballot(ne));
+                const int at = nb + K2 + below(m);
+                Cls<W> y;
+                y.L = ql[a];
+                y.R = qr[a];
+                scls[(ne && at < cap) ? at : cap] = y;
+                K2 += __builtin_popcount(m);
+            }
+        }
+        // the parent frame, with w gone from its partners
+        save_hdr();
+        if (lk == 0)
+            smap[d] = (uint16_t)(v | (w << 8));
+        wave_sync();
+        if (d + 1 > inc)
+            improve(d + 1);
+        if (K2 == 0)
+            return;  // a leaf: nothing left to split
+        if (nb + K2 > cap) {
+            spill = true;  // no room on the stack: the child goes to the queue
+            spill_w = w;
+            spill_b = b;
+            return;
+        }
+        if (nb + K2 > max_used)
+            max_used = nb + K2;
+        pushed += (unsigned long long)K2;
+        t += 1;
+        base = nb;
+        K = K2;
+        d += 1;
+        bound = b;
+        flags = kFlagUnmatched;
+        load_regs();
+        select();
+    }
+
+    // One lock-step search step of every segment that holds a unit.
+    __device__ void step() {
+        const bool act = inst >= 0 && !fin;
+        const bool need_pop = act && rrem == 0 && !(flags & kFlagUnmatched);
+        if (ballot(need_pop))
+            if (need_pop)
+                pop();
+        const bool act2 = inst >= 0 && !fin;
+        const bool need_unm = act2 && rrem == 0 && (flags & kFlagUnmatched);
+        if (ballot(need_unm))
+            if (need_unm)
+                unmatched();
+        const bool need_eval = inst >= 0 && !fin && rrem != 0;
+        const uint64_t em = ballot(need_eval);
+        if (em) {
+            const int Kb = K;
+            if (need_eval)
+                evaluate();
+            // statistics: children evaluated, and the classes they split
+            const int ne = __builtin_popcountll(em) >> LOGS;
+            n_evals += (unsigned)ne;
+            n_lanes += (unsigned)__builtin_popcountll(ballot(need_eval && lk < Kb));
+            n_ncls += (unsigned long long)wave_sum_u(need_eval && lk == 0 ? Kb : 0);
+        }
+        n_steps += 1;
+        if (ballot(spill))
+            spill_children();
+        if (ballot(fin))
+            finish_units();
+    }
+
+    DEV unsigned wave_sum_u(int x) { return (unsigned)wave_sum(x); }
+
+    // ---- work sharing ----
+
+    // A free slot in this XCD's ring, else in the next rings.
+    __device__ bool reserve(int &ring, unsigned long long &ticket, int tries_per_ring) {
+        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+        int ok = 0, rr = 0;
+        unsigned long long tk = 0;
+        if (lane == 0) {
+            for (int k = 0; k < kRings && !ok; ++k) {
+                const int r = (my_ring + k) & (kRings - 1);
+                unsigned long long *sq = P.seq + (size_t)r * P.ring_slots;
+                for (int tries = 0; tries < tries_per_ring; ++tries) {
+                    unsigned long long tl = ld_rlx(&P.g->ring[r].tail);
+                    unsigned long long s = ld_rlx(&sq[tl & mask]);
+                    if (s == tl) {
+                        if (cas64(&P.g->ring[r].tail, tl, tl + 1)) {
+                            ok = 1;
+                            rr = r;
+                            tk = tl;
+                            break;
+                        }
+                    } else if (s < tl) {
+                        break;  // this ring is full
+                    }
+                }
+            }
+        }
+        ok = rl(ok, 0);
+        ring = rl(rr, 0);
+        ticket = rl_ull(tk, 0);
+        return ok != 0;
+    }
+
+    __device__ void raise_flag(unsigned bits) {
+        if (lane == 0) {
+            if (bits & kFlagStop)
+                __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 0; k < kRings; ++k)
+                __hip_atomic_fetch_or(&P.g->xcd[k].flag, bits, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    __device__ void fail(unsigned code) {
+        if (lane == 0)
+            __hip_atomic_store(&P.g->error, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        raise_flag(kFlagStop);
+        stop = true;
+    }
+
+    // Queue each child that found no room on its segment's stack, as a fresh
+    // record (the taker chooses its class and v).
+    __device__ void spill_children() {
+        uint64_t sm = ballot(spill && lk == 0);
+        while (sm) {
+            const int j = ctz(sm) >> LOGS;
+            sm &= sm - 1;
+            if (P.single_wave) {
+                fail(1);  // (one wavefront alone has the worst-case stack)
+                break;
+            }
+            unsigned long long ticket;
+            int ring;
+            if (!reserve(ring, ticket, 1024)) {
+                fail(2);
+                break;
+            }
+            const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+            const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
+            uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
+            const int ji = of(inst, j), jd = of(d, j);
+            if (seg == j) {
+                // the child's classes, compacted in the same order as descend()
+                const W vb = (W)1 << v;
+                const W wb = (W)1 << spill_w;
+                const W go = sadj[v], ho = sadj[arows + spill_w];
+                W gi = 0, hi = 0;
+                if constexpr (DIR) {
+                    gi = sadj[2 * arows + v];
+                    hi = sadj[3 * arows + spill_w];
+                }
+                Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
+                int K2 = 0;
+                for (int c = 0; ballot(c * S < K) != 0; ++c) {
+                    const int k = c * S + lk;
+                    const bool in = k < K;
+                    const Cls<W> x = scls[base + (in ? k : 0)];
+                    W ql[NR], qr[NR];
+                    split(in ? x.L & ~vb : (W)0, in ? x.R & ~wb : (W)0, go, ho, gi, hi, ql, qr);
+#pragma unroll
+                    for (int a = 0; a < NR; ++a) {
+                        const bool ne = ql[a] != 0 && qr[a] != 0;
+                        const uint32_t m = sbits(ballot(ne));
+                        if (ne) {
+                            Cls<W> y;
+                            y.L = ql[a];
+                            y.R = qr[a];
+                            rcls[K2 + below(m)] = y;
+                        }
+                        K2 += __builtin_popcount(m);
+                    }
+                }
+                uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
+                for (int i = lk; i <= d; i += S)
+                    rmap[i] = smap[i];
+                if (lk == 0) {
+                    RecHdr<W> rh;
+                    rh.inst = (uint32_t)inst;
+                    rh.K = (uint8_t)K2;
+                    rh.d = (uint8_t)(d + 1);
+                    rh.v = 0;
+                    rh.sel = 0;
+                    rh.bound = (uint8_t)spill_b;
+                    rh.flags = (uint8_t)kFlagFresh;
+                    rh.lsel = 0;
+                    rh.rsel = 0;
+                    rh.pad[0] = rh.pad[1] = rh.pad[2] = rh.pad[3] = 0;
+                    rh.rrem = 0;
+                    *(RecHdr<W> *)slot = rh;
+                }
+                spill = false;
+            }
+            if (lane == 0) {
+                a_add_rlx(&P.open[ji], 1);
+                a_add_rlx(&P.g->open_total, 1);
+                st_rel(&P.seq[idx], ticket + 1);
+            }
+            (void)jd;
+            n_spill += 1;
+        }
+    }
+
+    // Give segment j's shallowest open frame's remaining children to the
+    // queue (the frame keeps the rest; the top frame keeps half).
+    __device__ void donate(int j) {
+        const int jt = of(t, j);
+        const uint4 *h = hdr_of(j);
+        int b = -1;
+        W grr = 0;
+        int gfl = 0;
+        for (int i = 0; i < jt; ++i) {
+            const uint4 x = h[i];
+            const uint32_t hz = sc(x.z), hw = sc(x.w);
+            W r = (W)sc(x.x);
+            if constexpr (sizeof(W) >= 8)
+                r |= (W)sc(x.y) << 32;
+            const int f = (int)(hw >> 24);
+            if ((int)(hz >> 24) > P.donate_depth)
+                return;  // deeper frames hold too little work to hand out
+            if (r != 0 || (f & kFlagUnmatched)) {
+                b = i;
+                grr = r;
+                gfl = f & kFlagUnmatched;
+                break;
+            }
+        }
+        W keep_r = 0;
+        const W jr = ofw(rrem, j);
+        const int jf = of(flags, j);
+        if (b < 0) {
+            if (of(d, j) > P.donate_depth)
+                return;
+            const int n = popc(jr);
+            if (n >= 2) {
+                W r = jr, kept = 0;
+                for (int c = 0; c < n - n / 2; ++c) {
+                    kept |= r & (~r + 1);
+                    r &= r - 1;
+                }
+                grr = r;
+                gfl = jf & kFlagUnmatched;
+                keep_r = kept;
+            } else if (n == 1 && (jf & kFlagUnmatched)) {
+                grr = 0;
+                gfl = kFlagUnmatched;
+                keep_r = jr;
+            } else {
+                return;
+            }
+            b = jt;
+        }
+        unsigned long long ticket;
+        int ring;
+        if (!reserve(ring, ticket, 4))
+            return;
+        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+        const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
+        uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
+        int fK, fd, fbase;
+        RecHdr<W> rh;
+        if (b == jt) {
+            fK = of(K, j);
+            fd = of(d, j);
+            fbase = of(base, j);
+            rh.v = (uint8_t)of(v, j);
+            rh.sel = (uint8_t)of(sel, j);
+            rh.bound = (uint8_t)of(bound, j);
+            rh.lsel = (uint8_t)of(lsel, j);
+            rh.rsel = (uint8_t)of(rsel, j);
+        } else {
+            const uint4 x = h[b];
+            const uint32_t hz = sc(x.z), hw = sc(x.w);
+            fbase = (int)(hz & 0xFFFFu);
+            fK = (int)((hz >> 16) & 0xFFu);
+            fd = (int)(hz >> 24);
+            rh.v = (uint8_t)(hw & 0xFFu);
+            const int fsel = (int)((hw >> 8) & 0xFFu);
+            rh.sel = (uint8_t)fsel;
+            rh.bound = (uint8_t)((hw >> 16) & 0xFFu);
+            const Cls<W> cs = cls_of(j)[fbase + fsel];
+            rh.lsel = (uint8_t)popc(sc(cs.L));
+            rh.rsel = (uint8_t)popc(sc(cs.R));
+        }
+        const int ji = of(inst, j);
+        rh.inst = (uint32_t)ji;
+        rh.K = (uint8_t)fK;
+        rh.d = (uint8_t)fd;
+        rh.flags = (uint8_t)gfl;
+        rh.pad[0] = rh.pad[1] = rh.pad[2] = rh.pad[3] = 0;
+        rh.rrem = grr;
+        if (lane == 0)
+            *(RecHdr<W> *)slot = rh;
+        uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
+        Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
+        const uint16_t *jm = map_of(j);
+        const Cls<W> *jc = cls_of(j);
+        for (int i = lane; i < fd; i += 64)
+            rmap[i] = jm[i];
+        for (int i = lane; i < fK; i += 64)
+            rcls[i] = jc[fbase + i];
+        if (lane == 0) {
+            a_add_rlx(&P.open[ji], 1);
+            a_add_rlx(&P.g->open_total, 1);
+            st_rel(&P.seq[idx], ticket + 1);
+        }
+        if (b == jt) {
+            if (seg == j) {
+                rrem = keep_r;
+                flags = 0;
+            }
+        } else if (lane == 0) {
+            uint4 *hw = hdr_of(j);
+            uint4 x = hw[b];
+            x.x = 0;
+            x.y = 0;
+            x.w &= 0x00FFFFFFu;  // flags = 0
+            hw[b] = x;
+        }
+        wave_sync();
+        n_don += 1;
+    }
+
+    // Segment j starts on instance i: its rows, incumbent, and identity.
+    __device__ void set_instance(int j, int i) {
+        if (of(adj_inst, j) != i) {
+            const W *src = (const W *)P.adj + (size_t)i * NR * NB;
+            W *dst = adj_of(j);
+            for (int q = lane; q < NR * arows; q += 64)
+                dst[q] = src[(q / arows) * NB + (q % arows)];
+        }
+        const DevInst di = P.inst[i];
+        const int slot = sc((int)di.inc_slot);
+        const int tw = sc((int)di.twin);
+        int g = 0;
+        if (lane == 0) {
+            g = ld_rlx(&P.inc[slot]);
+            if (tw >= 0 && ld_rlx(&P.open[tw]) == 0)
+                g = 255;  // the twin's search already finished
+        }
+        g = rl(g, 0);
+        if (seg == j) {
+            adj_inst = i;
+            inst = i;
+            inc_slot = slot;
+            twin = tw;
+            map_off = sc((int)di.map_off);
+            target = sc((int)di.target);
+            inc = 0;
+            set_inc(g);
+            nodes_pend = 0;
+            fin = false;
+            spill = false;
+        }
+    }
+
+    // Take a queued node into segment j: from this XCD's ring, else from
+    // one other ring, a different one on each call.
+    __device__ bool take_record(int j) {
+        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
+        int ok = 0, rr = 0;
+        unsigned long long hd = 0;
+        if (lane == 0) {
+            steal_from = (steal_from + 1) & (kRings - 1);
+            if (steal_from == my_ring)
+                steal_from = (steal_from + 1) & (kRings - 1);
+            for (int k = 0; k < 2 && !ok; ++k) {
+                const int r = k == 0 ? my_ring : steal_from;
+                unsigned long long *sq = P.seq + (size_t)r * P.ring_slots;
+                for (int tries = 0; tries < 4; ++tries) {
+                    unsigned long long h = ld_rlx(&P.g->ring[r].head);
+                    unsigned long long s = ld_rlx(&sq[h & mask]);
+                    if (s == h + 1) {
+                        if (cas64(&P.g->ring[r].head, h, h + 1)) {
+                            ok = 1;
+                            rr = r;
+                            hd = h;
+                            break;
+                        }
+                    } else if (s < h + 1) {
+                        break;  // empty, or its producer is still writing
+                    }
+                }
+            }
+        }
+        steal_from = rl(steal_from, 0);
+        ok = rl(ok, 0);
+        if (!ok)
+            return false;
+        // pairs with the producer's release store of the slot's sequence number
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        hd = rl_ull(hd, 0);
+        const int ring = rl(rr, 0);
+        const size_t idx = (size_t)ring * P.ring_slots + (size_t)(hd & mask);
+        const uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
+        const RecHdr<W> rh = *(const RecHdr<W> *)slot;
+        const int ri = sc((int)rh.inst);
+        const int rK = sc((int)rh.K), rd = sc((int)rh.d), rv = sc((int)rh.v);
+        const int rsel_ = sc((int)rh.sel), rb = sc((int)rh.bound), rf = sc((int)rh.flags);
+        const int rls = sc((int)rh.lsel), rrs = sc((int)rh.rsel);
+        const W rr_ = sc((W)rh.rrem);
+        const uint16_t *rmap = (const uint16_t *)(slot + rec_map_off<W>());
+        const Cls<W> *rcls = (const Cls<W> *)(slot + rec_cls_off<W>());
+        uint16_t mp = 0;
+        Cls<W> cc;
+        cc.L = 0;
+        cc.R = 0;
+        if (lane < rd)
+            mp = rmap[lane];
+        if (lane < rK)
+            cc = rcls[lane];
+        // every lane's loads of the slot have returned before it is handed back
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane == 0)
+            st_rlx(&P.seq[idx], hd + (unsigned long long)P.ring_slots);
+        set_instance(j, ri);
+        uint16_t *jm = map_of(j);
+        Cls<W> *jc = cls_of(j);
+        if (lane < rd)
+            jm[lane] = mp;
+        if (lane < rK)
+            jc[lane] = cc;
+        wave_sync();
+        if (seg == j) {
+            t = 0;
+            base = 0;
+            K = rK;
+            d = rd;
+            d0 = rd;
+            v = rv;
+            sel = rsel_;
+            bound = rb;
+            lsel = rls;
+            rsel = rrs;
+            rrem = rr_;
+            flags = rf & kFlagUnmatched;
+            load_regs();
+            if (bound <= inc) {
+                rrem = 0;
+                flags = 0;
+            } else if (rf & kFlagFresh) {
+                flags = kFlagUnmatched;
+                select();
+            }
+        }
+        n_pops += 1;
+        return true;
+    }
+
+    // Segment j takes the next unstarted instance (its work unit was counted
+    // by the reset).
+    __device__ bool claim_instance(int j) {
+        if (!roots_left)
+            return false;
+        int i = -1;
+        if (lane == 0) {
+            unsigned nx = ld_rlx(&P.g->next_inst);
+            if (nx < (unsigned)P.count) {
+                unsigned x = a_addu(&P.g->next_inst, 1u);
+                if (x < (unsigned)P.count)
+                    i = (int)x;
+            }
+        }
+        i = rl(i, 0);
+        if (i < 0) {
+            roots_left = false;
+            return false;
+        }
+        set_instance(j, i);
+        const DevInst di = P.inst[i];
+        const int k0 = sc((int)di.K0);
+        const Cls<W> *rc = (const Cls<W> *)P.rootcls + sc((int)di.cls_off);
+        Cls<W> *jc = cls_of(j);
+        for (int q = lane; q < k0; q += 64)
+            jc[q] = rc[q];
+        wave_sync();
+        if (seg == j) {
+            t = 0;
+            base = 0;
+            d = 0;
+            d0 = 0;
+            K = k0;
+            load_regs();
+            int contrib = 0;
+            for (int c = 0; ballot(c * S < K) != 0; ++c) {
+                const int k = c * S + lk;
+                if (k < K) {
+                    const Cls<W> x = c == 0 ? Cls<W>{cL, cR} : scls[base + k];
+                    const int nl = popc(x.L), nr = popc(x.R);
+                    contrib += nl < nr ? nl : nr;
+                }
+            }
+            bound = ssum(contrib);
+            nodes_pend += 1;  // the root
+            if (K == 0 || bound <= inc) {
+                rrem = 0;
+                flags = 0;
+            } else {
+                flags = kFlagUnmatched;
+                select();
+            }
+        }
+        return true;
+    }
+
+    // Units whose stacks emptied: count their nodes and end them.
+    __device__ void finish_units() {
+        uint64_t fm = ballot(fin && lk == 0);
+        while (fm) {
+            const int j = ctz(fm) >> LOGS;
+            fm &= fm - 1;
+            const int ji = of(inst, j);
+            const unsigned np = (unsigned)of((int)nodes_pend, j);
+            if (lane == 0) {
+                a_add64(&P.nodes[ji], (unsigned long long)np);
+                if (P.node_limit > 0) {
+                    unsigned long long tot = a_add64(&P.g->node_total, np) + np;
+                    if ((long long)tot > P.node_limit)
+                        raise_flag(kFlagStop);
+                }
+                if (!stop) {
+                    const int r = a_add_rlx(&P.open[ji], -1);
+                    if (r == 1)
+                        __hip_atomic_store(&P.t_proof[ji], now_ticks(), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (a_add_rlx(&P.g->open_total, -1) == 1)
+                        raise_flag(kFlagDone);
+                }
+            }
+            n_nodes_wave += np;
+            if (seg == j) {
+                inst = -1;
+                fin = false;
+                nodes_pend = 0;
+            }
+        }
+    }
+
+    // Nodes counted so far, flushed to the instances (for the node limit).
+    __device__ void flush_nodes() {
+        uint64_t am = ballot(inst >= 0 && lk == 0);
+        unsigned long long tot_add = 0;
+        while (am) {
+            const int j = ctz(am) >> LOGS;
+            am &= am - 1;
+            const int ji = of(inst, j);
+            const unsigned np = (unsigned)of((int)nodes_pend, j);
+            if (lane == 0 && np)
+                a_add64(&P.nodes[ji], (unsigned long long)np);
+            tot_add += np;
+            if (seg == j)
+                nodes_pend = 0;
+        }
+        n_nodes_wave += tot_add;
+        if (lane == 0 && tot_add && P.node_limit > 0) {
+            unsigned long long tot = a_add64(&P.g->node_total, tot_add) + tot_add;
+            if ((long long)tot > P.node_limit)
+                raise_flag(kFlagStop);
+        }
+    }
+
+    // Periodic: refresh incumbents, honour limits, keep the queue stocked.
+    __device__ void check() {
+        since_check = 0;
+        unsigned fl = 0;
+        unsigned long long hd = 0, tl = 0;
+        const bool may_donate = !P.single_wave && P.donate_low >= 0;
+        if (lane == 0) {
+            fl = ld_rlx(&P.g->xcd[my_ring].flag);
+            if (may_donate) {
+                tl = ld_rlx(&P.g->ring[my_ring].tail);
+                hd = ld_rlx(&P.g->ring[my_ring].head);
+            }
+        }
+        if (inst >= 0) {
+            int g = ld_rlx(&P.inc[inc_slot]);
+            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0)
+                g = 255;
+            set_inc(g);
+        }
+        if (rl(fl, 0)) {
+            stop = true;
+            return;
+        }
+        if (now_ticks() - t_start > P.limit_ticks) {
+            raise_flag(kFlagStop);
+            stop = true;
+            return;
+        }
+        // (counts are also flushed before a 32-bit per-unit count could wrap)
+        if (P.node_limit > 0 || ballot(nodes_pend > (1u << 30)))
+            flush_nodes();
+        if (may_donate) {
+            const long long waiting = (long long)(rl_ull(tl, 0) - rl_ull(hd, 0));
+            if (waiting < P.donate_low) {
+                // one donation per check, from the segments in turn
+                const uint64_t cand = ballot(inst >= 0 && !fin && lk == 0 && d0 <= P.donate_depth);
+                if (cand) {
+                    const uint64_t rot = cand >> (donor << LOGS);
+                    const int j = rot ? (ctz(rot) >> LOGS) + donor : ctz(cand) >> LOGS;
+                    donor = (j + 1) & (NSEG - 1);
+                    donate(j);
+                }
+            }
+        }
+    }
+
+    // Give idle segments work; false if none was found.
+    __device__ bool refill() {
+        uint64_t im = ballot(inst < 0 && lk == 0);
+        if (P.single_wave)
+            im &= 1ull;  // one search only: the sequential order
+        bool any = false;
+        while (im) {
+            const int j = ctz(im) >> LOGS;
+            im &= im - 1;
+            bool got = false;
+            if (!P.single_wave)
+                got = take_record(j);
+            if (!got)
+                got = claim_instance(j);
+            if (!got)
+                break;
+            any = true;
+        }
+        return any;
+    }
+
+    __device__ void main_loop() {
+        t_start = now_ticks();
+        if (lane == 0)
+            a_min64(&P.g->t0, t_start);
+        int backoff = 0;
+        int idle_steps = 0;
+        int refill_gap = 16;  // steps between refills while some segments are busy
+        unsigned long long t_busy0 = 0;
+        bool busy = false;
+        for (;;) {
+            // idle segments look for work when the wavefront has none at all,
+            // and otherwise every few steps
+            // (a failed look costs the busy segments a queue round trip, so
+            // the gap doubles while the queue stays empty)
+            const uint64_t am = ballot(inst >= 0);
+            if (am == 0 || (am != ~0ull && ++idle_steps >= refill_gap)) {
+                idle_steps = 0;
+                if (refill())
+                    refill_gap = 16;
+                else if (am != 0)
+                    refill_gap = refill_gap < 1024 ? 2 * refill_gap : 1024;
+            }
+            if (ballot(inst >= 0) == 0) {
+                if (busy) {
+                    n_busy += now_ticks() - t_busy0;
+                    busy = false;
+                }
+                unsigned fl = 0;
+                if (lane == 0)
+                    fl = ld_rlx(&P.g->xcd[my_ring].flag);
+                if (rl(fl, 0))
+                    break;  // stopped, or no work is left anywhere
+                if (now_ticks() - t_start > P.limit_ticks) {
+                    raise_flag(kFlagStop);
+                    break;
+                }
+                const int bmax = P.backoff_max;
+                backoff = backoff ? (2 * backoff < bmax ? 2 * backoff : bmax) : 1;
+                const unsigned long long t_sleep = now_ticks();
+                for (int i = 0; i < backoff; ++i)
+                    __builtin_amdgcn_s_sleep(127);
+                n_sleep += now_ticks() - t_sleep;
+                continue;
+            }
+            backoff = 0;
+            if (!busy) {
+                t_busy0 = now_ticks();
+                busy = true;
+            }
+            step();
+            if (stop)
+                break;
+            if (++since_check >= check_interval) {
+                check();
+                if (stop)
+                    break;
+            }
+        }
+        if (busy)
+            n_busy += now_ticks() - t_busy0;
+        {
+            // classes pushed, summed over the segments (lane 0 of each)
+            const unsigned long long x = lk == 0 ? pushed : 0ull;
+            n_pushed = (unsigned long long)(unsigned)wave_sum((int)(unsigned)x) +
+                       ((unsigned long long)(unsigned)wave_sum((int)(unsigned)(x >> 32)) << 32);
+        }
+        if (lane == 0) {
+            a_add64(&P.g->batches, n_steps);
+            a_add64(&P.g->children, n_evals);
+            a_add64(&P.g->lane_slots, n_lanes);
+            a_add64(&P.g->donations, n_don);
+            a_add64(&P.g->pops, n_pops);
+            a_add64(&P.g->busy_ticks, n_busy);
+            a_add64(&P.g->spills, n_spill);
+            a_add64(&P.g->pushed_classes, n_pushed);
+            a_add64(&P.g->sleep_ticks, n_sleep);
+            a_add64(&P.g->node_classes, n_ncls);
+        }
+        const int mu = wave_max_i(max_used);
+        if (lane == 0)
+            __hip_atomic_fetch_max(&P.g->max_stack, mu, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    DEV int wave_max_i(int x) { return (int)~wave_min(~(uint32_t)x); }
+};
+
+template <typename W, bool DIR, int LOGS>
+__global__ void __launch_bounds__(256) mcs_seg_kernel(SearchParams Pk) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ SearchParams P;
+    if (threadIdx.x == 0)
+        P = Pk;
+    __syncthreads();
+    const int wv = threadIdx.x >> 6;
+    if (Pk.single_wave && (blockIdx.x != 0 || wv != 0))
+        return;
+    SegSearch<W, DIR, LOGS> s(P, smem + (size_t)wv * (size_t)(Pk.seg_bytes * (64 >> LOGS)));
+    s.main_loop();
+}
+
+}  // namespace mcs
+
+// Launch entry point used by the host driver: the kernel for rows of
+// word_bytes (4 or 8), directed or not, with segments of 2^seg_log lanes
+// (3 or 4); null for anything else.
+extern "C" void *mcs_internal_seg_kernel(int word_bytes, int directed, int seg_log) {
+    using namespace mcs;
+    if (word_bytes == 4) {
+        if (seg_log == 3)
+            return directed ? (void *)mcs_seg_kernel<uint32_t, true, 3>
+                            : (void *)mcs_seg_kernel<uint32_t, false, 3>;
+        if (seg_log == 4)
+            return directed ? (void *)mcs_seg_kernel<uint32_t, true, 4>
+                            : (void *)mcs_seg_kernel<uint32_t, false, 4>;
+    } else if (word_bytes == 8) {
+        if (seg_log == 3)
+            return directed ? (void *)mcs_seg_kernel<uint64_t, true, 3>
+                            : (void *)mcs_seg_kernel<uint64_t, false, 3>;
+        if (seg_log == 4)
+            return directed ? (void *)mcs_seg_kernel<uint64_t, true, 4>
+                            : (void *)mcs_seg_kernel<uint64_t, false, 4>;
+    }
+    return nullptr;
+}

@@ -5,6 +5,10 @@ workloads of mcs_instances.  A pair the oracle cannot finish within the node
 limit is stored with complete = false and its size as a lower bound.
 
     python tests/golden/make_expected.py c2_n30 c3 c4_1024
+    python tests/golden/make_expected.py --deepen c2 1.5e9
+
+The second form reruns a stored set's unfinished pairs under a larger node
+limit (1.5e9 nodes is about 600 s of one core for this oracle).
 """
 from __future__ import annotations
 
@@ -12,7 +16,7 @@ import json
 import os
 import sys
 import time
-from concurrent.futures import ProcessPoolExecutor
+from concurrent.futures import ProcessPoolExecutor, as_completed
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -79,7 +83,7 @@ def _known_rows(pairs, lim):
         for (G, H), row in zip(opairs, data["pairs"]):
             for i in want.get(mi.workload_hash([(G, H)]), []):
                 mine = _limit(lim, *pairs[i])
-                theirs = _limit(olim, G, H)
+                theirs = row.get("node_limit", _limit(olim, G, H))
                 same = (row["complete"] and (mine == 0 or row["nodes"] <= mine)) or \
                        (not row["complete"] and theirs == mine)
                 if same and rows[i] is None:
@@ -110,7 +114,64 @@ def make(name: str, workers: int = 8) -> str:
     return path
 
 
+def _row_limit(data, i):
+    """The node limit row i of a stored set was computed under."""
+    row = data["pairs"][i]
+    if "node_limit" in row:
+        return row["node_limit"]
+    lim = data["node_limit"]
+    return lim[i] if isinstance(lim, list) else lim
+
+
+def _write(path, data):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=0)
+    os.replace(tmp, path)
+
+
+def deepen(name: str, limit: int, workers: int = 8) -> str:
+    """Rerun, under the larger node limit ``limit``, every row of a stored set
+    the oracle did not finish.  Rows are taken smallest graph first (the ones
+    most likely to finish) and the file is rewritten after each result, so an
+    interrupted run keeps what it finished; each row records the limit it was
+    computed under."""
+    factory, _, _ = SETS[name]
+    pairs = factory()
+    path = os.path.join(HERE, f"expected_{name}.json")
+    with open(path) as f:
+        data = json.load(f)
+    if data["digest"] != mi.workload_hash(pairs):
+        raise SystemExit(f"{path} does not belong to the current {name} pairs")
+    for i in range(len(pairs)):
+        data["pairs"][i]["node_limit"] = _row_limit(data, i)
+    todo = [i for i, r in enumerate(data["pairs"])
+            if not r["complete"] and 0 < r["node_limit"] < limit]
+    todo.sort(key=lambda i: (pairs[i][0]["n"] + pairs[i][1]["n"], i))
+    oracle._load()
+    done = 0
+    with ProcessPoolExecutor(workers) as ex:
+        futs = [ex.submit(_one, (i, pairs[i][0], pairs[i][1], limit)) for i in todo]
+        for fut in as_completed(futs):
+            i, size, complete, nodes, dt = fut.result()
+            old = data["pairs"][i]
+            if size < old["size"]:
+                raise SystemExit(f"pair {i}: size {size} below the stored bound {old['size']}")
+            data["pairs"][i] = {"size": size, "complete": complete, "nodes": nodes,
+                                "seconds": round(dt, 4), "node_limit": limit}
+            done += 1
+            _write(path, data)
+            print(f"{name} pair {i}: size {size} complete {complete} "
+                  f"nodes {nodes} {dt:.1f}s ({done}/{len(todo)})", flush=True)
+    return path
+
+
 if __name__ == "__main__":
     workers = int(os.environ.get("MAKE_EXPECTED_WORKERS", "8"))
-    for name in sys.argv[1:] or list(SETS):
-        print(make(name, workers), flush=True)
+    args = sys.argv[1:]
+    if args[:1] == ["--deepen"]:
+        # --deepen NAME LIMIT: rerun a stored set's unfinished rows under LIMIT nodes
+        print(deepen(args[1], int(float(args[2])), workers), flush=True)
+    else:
+        for name in args or list(SETS):
+            print(make(name, workers), flush=True)

@@ -13,6 +13,7 @@
 static char g_dummy_kernel;
 extern "C" void *mcs_internal_search_kernel(int, int, int) { return &g_dummy_kernel; }
 extern "C" void *mcs_internal_reset_kernel(void) { return &g_dummy_kernel; }
+extern "C" void *mcs_internal_seg_kernel(int, int, int) { return &g_dummy_kernel; }
 
 static uint64_t g_state = 0x1234567ull;
 static uint64_t next_u64() {  // splitmix64

@@ -94,7 +94,11 @@ def test_bench_accounting_covers_every_word_size():
     """bench.py prices every row width and direction it can meet, and every
     workload it names resolves to pairs of the width it says."""
     import bench
-    assert set(bench.OPS_PER_CLASS) == {(w, d) for w in (4, 8, 16) for d in (False, True)}
+    # the per-class counts written out in bench.py: 22 / 50 lane-ops at 32
+    # bits (undirected / directed), the word-wise part scaling with the word
+    assert bench.ops_per_class(4, False) == 22 and bench.ops_per_class(4, True) == 50
+    assert bench.ops_per_class(8, False) == 38 and bench.ops_per_class(8, True) == 88
+    assert bench.ops_per_class(16, False) == 70 and bench.ops_per_class(16, True) == 164
     wl = bench.workloads()
     assert {"c1", "c2", "c2_n30", "c3", "c4", "c4_1024", "w"} <= set(wl)
     assert "128-bit" in wl["w"][0]

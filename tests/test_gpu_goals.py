@@ -43,6 +43,22 @@ def test_goal_search_matches_oracle(gpu, strategy):
     assert launches >= 1
 
 
+def test_bisect_through_graph_drops_node_limit(gpu):
+    """Bound correction with the HIP graph: the first (plain) run is node
+    limited, the goal runs after it are not -- the graph's kernel node must
+    take the changed parameters, or every goal run would stop at the node
+    limit and end unsettled."""
+    from paper_1908_06418_amd import solve_goals
+    pairs = _pairs()
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    _say(f"bisect through the graph: {len(pairs)} pairs")
+    res = solve_goals(pairs, strategy="bisect", node_limit=20000, time_limit_s=60,
+                      tuning={"use_graph": 1})
+    for (G, H), r, w in zip(pairs, res, want):
+        assert r.optimal and r.size == w
+        assert oracle.check.is_valid(G, H, r.mapping)
+
+
 def test_set_goals_semantics(gpu):
     """goal = optimum: found (size >= goal); goal = optimum + 1: refuted
     (size below goal, settled)."""

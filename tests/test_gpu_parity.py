@@ -47,10 +47,17 @@ def test_c1_single_pair(gpu):
         assert oracle.check.is_valid(G, H, r.mapping)
 
 
+# search layouts: one search per 16-lane segment (the default), per 8-lane
+# segment, and one per wavefront
+LAYOUTS = [16, 8, 64]
+
+
+@pytest.mark.parametrize("lanes", LAYOUTS)
 @pytest.mark.parametrize("kind", ["undirected", "directed", "labelled", "directed_labelled"])
-def test_single_wave_reproduces_oracle_node_count(gpu, kind):
-    """One wavefront, one child per batch, no re-pruning: the GPU walks the
-    same tree as the sequential oracle, so even the node counts agree."""
+def test_single_wave_reproduces_oracle_node_count(gpu, kind, lanes):
+    """One search alone, one child at a time, no re-pruning: the GPU walks
+    the same tree as the sequential oracle, so even the node counts agree --
+    in every search layout."""
     rng = np.random.default_rng({"undirected": 1, "directed": 2, "labelled": 3,
                                  "directed_labelled": 4}[kind])
     directed = kind.startswith("directed")
@@ -63,8 +70,8 @@ def test_single_wave_reproduces_oracle_node_count(gpu, kind):
                       mi.random_small(rng, n2, p, directed, nlab)))
     if kind == "undirected":
         pairs += mi.pair_c1()
-    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1}
-    _say(f"single-wave {kind}: {len(pairs)} pairs")
+    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1, "seg_lanes": lanes}
+    _say(f"single-wave {kind}, {lanes}-lane layout: {len(pairs)} pairs")
     res = _solve_batch(pairs, tuning=tun, time_limit_s=60)
     for (G, H), r in zip(pairs, res):
         o = oracle.mcs(G, H)
@@ -74,8 +81,9 @@ def test_single_wave_reproduces_oracle_node_count(gpu, kind):
         assert oracle.check.is_valid(G, H, r.mapping)
 
 
+@pytest.mark.parametrize("lanes", [16, 64])
 @pytest.mark.parametrize("kind", ["undirected", "directed", "labelled"])
-def test_block_triangular_order_matches_oracle(gpu, kind):
+def test_block_triangular_order_matches_oracle(gpu, kind, lanes):
     """The alternative order of Sec. IV.A (mcs_opts.ordering = 1): the host
     library's implementation and the oracle's (oracle/ordering.py, written
     separately from the paper) induce the same search -- one wavefront
@@ -92,8 +100,8 @@ def test_block_triangular_order_matches_oracle(gpu, kind):
         p = float(rng.uniform(0.05, 0.5))
         pairs.append((mi.random_small(rng, n1, p, directed, nlab),
                       mi.random_small(rng, n2, p, directed, nlab)))
-    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1}
-    _say(f"block-triangular order, {kind}: {len(pairs)} pairs")
+    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1, "seg_lanes": lanes}
+    _say(f"block-triangular order, {kind}, {lanes}-lane layout: {len(pairs)} pairs")
     res = solve_batch(pairs, tuning=tun, time_limit_s=60, ordering="btf")
     for (G, H), r in zip(pairs, res):
         o = oracle.mcs(G, H, order="btf")
@@ -104,10 +112,7 @@ def test_block_triangular_order_matches_oracle(gpu, kind):
     assert [r.size for r in batched] == [r.size for r in res]
 
 
-@pytest.mark.parametrize("directed,nlab", [(False, 0), (True, 0), (False, 4), (True, 3)])
-def test_random_sweep_batched(gpu, directed, nlab):
-    """Random pairs of every size from 0 to 24 vertices and densities 0..1,
-    solved in one batched launch."""
+def _sweep_case(directed, nlab):
     rng = np.random.default_rng(1000 + 10 * directed + nlab)
     pairs = []
     for i in range(160):
@@ -120,9 +125,23 @@ def test_random_sweep_batched(gpu, directed, nlab):
     ora = [oracle.mcs(G, H, node_limit=2_000_000) for G, H in pairs]
     pairs = [pq for pq, o in zip(pairs, ora) if o["complete"]]
     want = [o["size"] for o in ora if o["complete"]]
+    return pairs, want
+
+
+_SWEEPS = {}
+
+
+@pytest.mark.parametrize("lanes", LAYOUTS)
+@pytest.mark.parametrize("directed,nlab", [(False, 0), (True, 0), (False, 4), (True, 3)])
+def test_random_sweep_batched(gpu, directed, nlab, lanes):
+    """Random pairs of every size from 0 to 24 vertices and densities 0..1,
+    solved in one batched launch, in every search layout."""
+    if (directed, nlab) not in _SWEEPS:
+        _SWEEPS[(directed, nlab)] = _sweep_case(directed, nlab)
+    pairs, want = _SWEEPS[(directed, nlab)]
     assert len(pairs) >= 140
-    _say(f"sweep directed={directed} nlab={nlab}: {len(pairs)} pairs")
-    res = _solve_batch(pairs, time_limit_s=60)
+    _say(f"sweep directed={directed} nlab={nlab} {lanes}-lane layout: {len(pairs)} pairs")
+    res = _solve_batch(pairs, time_limit_s=60, tuning={"seg_lanes": lanes})
     _check(pairs, res, want)
     assert all(r.optimal for r in res)
 
@@ -358,11 +377,30 @@ def test_c2_n30_all(gpu):
 
 def test_c4_all_4096_one_launch(gpu):
     """The batched workload: 4096 pairs of uneven size in one persistent
-    launch.  Sizes equal the oracle's where it finished (3077 pairs within
-    its 2e7-node budget) and reach at least its lower bound elsewhere; the
-    search proves every pair."""
-    res, proven = _golden_parity("c4", mi.pairs_c4(4096), 300)
-    assert proven == len(res)
+    launch, replayed twice from the HIP graph that holds the whole solve
+    (input copy, reset, search, result copy), with the tuning the autotuner
+    table ships for it.  Sizes equal the oracle's where it finished and
+    reach at least its lower bound elsewhere; the search proves every pair
+    on both replays."""
+    from paper_1908_06418_amd import Plan, autotune
+    pairs = mi.pairs_c4(4096)
+    exp = _expected("c4")
+    assert exp["digest"] == mi.workload_hash(pairs), "stored values are for other inputs"
+    tuning = dict(autotune.tuned(pairs) or {})
+    tuning["use_graph"] = 1
+    plan = Plan(pairs, time_limit_s=300, tuning=tuning).upload()
+    for rep in range(2):
+        _say(f"c4 graph replay {rep}, tuning {tuning}")
+        plan.run()
+        res = plan.results()
+        for i, (r, e) in enumerate(zip(res, exp["pairs"])):
+            if e["complete"]:
+                assert r.size == e["size"], (i, r.size, e["size"])
+            else:
+                assert r.size >= e["size"], (i, r.size, e["size"])
+        assert all(r.optimal for r in res)
+        _check(pairs, res)
+    plan.close()
 
 
 def test_c2_all_180(gpu):
