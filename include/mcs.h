@@ -11,9 +11,10 @@
  * Each open search node holds label classes (L subset of V_G, R subset of V_H);
  * a child (v, w) splits every class by adjacency to v in G and to w in H, and
  * is pruned when |M| + sum over classes of min(|L|, |R|) cannot beat the
- * incumbent.  The library runs this on the GPU: one wavefront per open node,
- * bitset classes across its lanes, a device work queue shared by all
- * wavefronts, and a per-instance incumbent updated with atomics.
+ * incumbent.  The library runs this on the GPU: many depth-first searches per
+ * wavefront (one per segment of 16 or 8 lanes, a node's bitset classes
+ * across the segment's lanes), a device work queue shared by all of them for
+ * load balancing, and a per-instance incumbent updated with atomics.
  *
  * Conventions for every entry point:
  *   - No exception crosses the ABI; every call returns an mcs_status.
@@ -46,10 +47,7 @@ typedef enum {
     MCS_E_TOO_LARGE = -2, /* a graph has more than MCS_MAX_N vertices */
     MCS_E_DEVICE = -3,    /* a HIP call or the search kernel failed */
     MCS_E_WORKSPACE = -4, /* workspace missing, too small or misaligned */
-    MCS_E_INTERNAL = -5,  /* an internal capacity check fired (a bug) */
-    MCS_E_QUEUE_FULL = -6 /* a child with no room on a wavefront's class stack
-                             found every node-queue slot taken: raise
-                             mcs_tuning.ring_slots or stack_classes */
+    MCS_E_INTERNAL = -5   /* an internal capacity check fired (a bug) */
 } mcs_status;
 
 #define MCS_MAX_N 128
@@ -91,25 +89,29 @@ typedef struct {
     int32_t check_interval;    /* search steps between queue/limit checks (0: 128) */
     int32_t no_reprune;        /* 1: do not re-test a frame's bound against the
                                   incumbent when the search returns to it */
-    int32_t single_wave;       /* 1: whole search on one wavefront, in the
-                                  sequential order (debugging and node-count
-                                  comparisons).  Its class stack is the whole
-                                  worst case: in LDS up to 64 vertices, in
-                                  HBM with 128-bit rows */
+    int32_t single_wave;       /* 1: one search alone (the first segment of one
+                                  wavefront, or one wavefront with seg_lanes
+                                  64), in the sequential order: no queue, no
+                                  donations (debugging and node-count
+                                  comparisons with the oracle) */
     int32_t use_graph;         /* 1: mcs_plan_run replays a HIP graph that holds
                                   a whole solve: the input copy (from pinned
                                   host memory the plan allocates once), the
                                   reset and search kernels, and the result
                                   copy back (mcs_plan_results then only waits
                                   and decodes) */
-    int32_t stack_classes;     /* capacity of one wavefront's class stack
-                                  (0: the worst case m(m+1)/2, m the largest
-                                  min(nG, nH), or less if that keeps
-                                  waves_per_cu from fitting in LDS; never
-                                  below 2m + 1).  With 128-bit rows the
-                                  stack is in HBM and 0 means the whole
-                                  worst case.  A child that does not fit
-                                  goes to the node queue as a record. */
+    int32_t stack_classes;     /* segmented searches: classes of each search's
+                                  stack kept in LDS (0: the worst case
+                                  m(m+1)/2, m the largest min(nG, nH), or
+                                  less if that keeps waves_per_cu from
+                                  fitting in LDS; never below 2m + 1).  The
+                                  rest of the worst case is in HBM, so a
+                                  child always has room: a frame that might
+                                  not fit in the LDS part goes to the HBM
+                                  part.  One search per wavefront always
+                                  keeps the whole worst case (in LDS, or in
+                                  HBM with 128-bit rows); this field does not
+                                  apply to it. */
     int32_t backoff_max;       /* an idle wavefront that finds no work sleeps
                                   1, 2, 4, ... up to this many times about
                                   3.4 us before polling again (0: 32) */
@@ -182,7 +184,8 @@ typedef struct {
     double busy_wave_s;        /* wavefront-seconds spent searching; the rest
                                   of waves x kernel time went to looking for
                                   work (load imbalance and queue latency) */
-    int64_t spills;            /* children queued because the class stack was full */
+    int64_t hbm_frames;        /* frames placed in the HBM part of a segmented
+                                  search's class stack */
     int32_t stack_classes;     /* class-stack capacity per wavefront */
     int32_t max_stack_used;    /* most classes any wavefront's stack held */
     double sleep_wave_s;       /* wavefront-seconds idle wavefronts spent in

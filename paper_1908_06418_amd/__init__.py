@@ -140,7 +140,7 @@ class Stats:
     stopped: int = 0
     kernel_ms: float = 0.0
     busy_wave_s: float = 0.0
-    spills: int = 0
+    hbm_frames: int = 0
     stack_classes: int = 0
     max_stack_used: int = 0
     sleep_wave_s: float = 0.0
@@ -232,7 +232,7 @@ class Plan:
         return Stats(int(s.nodes), int(s.batches), int(s.children), int(s.lane_slots),
                      int(s.donations), int(s.pops), int(s.waves), int(s.blocks),
                      int(s.lds_per_wave), int(s.stopped), float(s.kernel_ms),
-                     float(s.busy_wave_s), int(s.spills), int(s.stack_classes),
+                     float(s.busy_wave_s), int(s.hbm_frames), int(s.stack_classes),
                      int(s.max_stack_used), float(s.sleep_wave_s), int(s.lds_bytes),
                      int(s.node_classes))
 

@@ -14,7 +14,6 @@ MCS_E_TOO_LARGE = -2
 MCS_E_DEVICE = -3
 MCS_E_WORKSPACE = -4
 MCS_E_INTERNAL = -5
-MCS_E_QUEUE_FULL = -6
 MCS_MAX_N = 128
 
 
@@ -56,7 +55,7 @@ class mcs_stats(ctypes.Structure):
                 ("waves", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("lds_per_wave", ctypes.c_int32), ("stopped", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("busy_wave_s", ctypes.c_double),
-                ("spills", ctypes.c_int64), ("stack_classes", ctypes.c_int32),
+                ("hbm_frames", ctypes.c_int64), ("stack_classes", ctypes.c_int32),
                 ("max_stack_used", ctypes.c_int32), ("sleep_wave_s", ctypes.c_double),
                 ("lds_bytes", ctypes.c_int64), ("node_classes", ctypes.c_int64)]
 

@@ -363,7 +363,6 @@ const char *mcs_status_string(mcs_status s) {
     case MCS_E_DEVICE: return "device error";
     case MCS_E_WORKSPACE: return "workspace missing or too small";
     case MCS_E_INTERNAL: return "internal capacity check failed";
-    case MCS_E_QUEUE_FULL: return "node queue full while queueing a child";
     }
     return "unknown status";
 }
@@ -596,20 +595,18 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         return mcs::lds_layout(p->word_bytes, directed, wide ? -1 : cap, p->frames,
                                p->policy_levels).total;
     };
-    if (wide) {
-        // 128-bit rows: each wavefront's class stack is a slice of HBM
-        // holding the whole worst case (so it never overflows) unless the
-        // caller asks for a smaller one
-        p->cap_classes = p->tun.stack_classes > 0 && !p->tun.single_wave
-                             ? std::max(min_cap, std::min(full_cap, p->tun.stack_classes))
-                             : full_cap;
-    } else if (p->tun.single_wave) {
-        p->cap_classes = full_cap;  // one wavefront never takes queued work back
+    if (!p->seg_log) {
+        // One search per wavefront: the whole worst case, in LDS (at most
+        // 2081 classes of 16 bytes for 64 vertices) or, with 128-bit rows,
+        // in the wavefront's slice of HBM (up to 264 KB), so a child always
+        // has room on its stack.
+        p->cap_classes = full_cap;
     } else if (p->tun.stack_classes > 0) {
         p->cap_classes = std::max(min_cap, std::min(full_cap, p->tun.stack_classes));
     } else {
-        // the whole worst case if target_wpc wavefronts still fit in a CU's
-        // LDS, else the largest stack that lets them
+        // Segments: the whole worst case in LDS if target_wpc wavefronts
+        // still fit in a CU, else the largest LDS part that lets them; the
+        // rest of each search's worst case is in HBM.
         p->cap_classes = full_cap;
         const int share = lds_cu / target_wpc - 64;  // 64: a wave's part of the static LDS
         if (per_wave(full_cap) > share) {
@@ -617,11 +614,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
             p->cap_classes = std::max(min_cap, std::min(full_cap, room / (2 * p->word_bytes)));
         }
     }
-    // (the segmented kernel's headers hold a 16-bit class index)
-    if (p->seg_log && p->cap_classes > 65535)
-        p->cap_classes = 65535;
     max_lds_block -= 256;  // the kernel's static LDS (its parameter copy)
-    if (!wide && !p->tun.single_wave && per_wave(p->cap_classes) > max_lds_block) {
+    if (p->seg_log && per_wave(p->cap_classes) > max_lds_block) {
         // one wavefront's stacks must fit in one workgroup's LDS
         const int room = max_lds_block / nseg - per_wave(0) / nseg - 16;
         p->cap_classes = std::max(min_cap, std::min(p->cap_classes, room / (2 * p->word_bytes)));
@@ -633,13 +627,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     while (wpb > 1 && wpb * p->lds_per_wave > max_lds_block)
         wpb >>= 1;
     if (p->lds_per_wave > max_lds_block) {
-        const bool single = p->tun.single_wave != 0;
         delete p;
-        // only the single-wavefront mode asks for the whole worst-case stack
-        if (single)
-            return fail(MCS_E_INVALID, "single_wave needs the worst-case class stack in one "
-                                       "workgroup's LDS: min(nG, nH) is too large for it");
-        return fail(MCS_E_INTERNAL, "LDS stack of one wavefront exceeds the workgroup limit");
+        return fail(MCS_E_INTERNAL, "LDS of one wavefront exceeds the workgroup limit");
     }
     p->waves_per_block = wpb;
     p->lds_per_block = wpb * p->lds_per_wave;
@@ -668,8 +657,18 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         p->ring_slots = next_pow2(std::max(2, (total + mcs::kRings - 1) / mcs::kRings));
     }
     p->slot_bytes = mcs::slot_bytes_for(p->word_bytes, p->mmax);
-    if (wide)
+    // HBM class stacks: a wavefront's whole stack with 128-bit rows; with
+    // segments, the part of each search's worst case above its LDS part
+    // (frames placed there start at cap_classes and total at most full_cap
+    // classes)
+    size_t hstacks = 0;
+    if (wide) {
         p->hstack_stride = (long long)align256((size_t)(p->cap_classes + 1) * 2 * p->word_bytes);
+        hstacks = (size_t)p->waves;
+    } else if (p->seg_log && p->cap_classes < full_cap) {
+        p->hstack_stride = (long long)align256((size_t)full_cap * 2 * p->word_bytes);
+        hstacks = (size_t)p->waves * (size_t)nseg;
+    }
 
     // workspace layout
     size_t o = 0;
@@ -690,7 +689,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     p->off_glob = take(sizeof(mcs::DevGlobals));
     p->off_seq = take(sizeof(unsigned long long) * mcs::kRings * p->ring_slots);
     p->off_slots = take((size_t)p->slot_bytes * mcs::kRings * p->ring_slots);
-    p->off_hstack = take((size_t)p->hstack_stride * (size_t)p->waves);
+    p->off_hstack = take((size_t)p->hstack_stride * hstacks);
     p->ws_bytes = o;
     *out = p;
     return MCS_OK;
@@ -957,9 +956,6 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
         p->last_ms = 0.f;
     }
     p->have_results = true;
-    if (p->h_glob.error == 2)
-        return fail(MCS_E_QUEUE_FULL, "a child had no room on a wavefront's class stack and every "
-                                      "node-queue slot was taken; raise ring_slots or stack_classes");
     if (p->h_glob.error)
         return fail(MCS_E_INTERNAL, "a search wavefront hit an internal capacity check");
 
@@ -1013,7 +1009,7 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     z.stopped = p->h_glob.stop ? 1 : 0;
     z.kernel_ms = p->last_ms;
     z.busy_wave_s = (double)p->h_glob.busy_ticks / p->tick_hz;
-    z.spills = (int64_t)p->h_glob.spills;
+    z.hbm_frames = (int64_t)p->h_glob.hbm_frames;
     z.sleep_wave_s = (double)p->h_glob.sleep_ticks / p->tick_hz;
     // Algorithmic LDS bytes: each child batch reads the rows of v and of
     // its C partners (one word each, two when directed); each pushed frame's

@@ -64,7 +64,7 @@ struct DevGlobals {
     unsigned long long donations;
     unsigned long long pops;
     unsigned long long busy_ticks;  // realtime ticks wavefronts spent searching
-    unsigned long long spills;      // children queued for want of stack room
+    unsigned long long hbm_frames;  // frames placed in the HBM part of a class stack
     unsigned long long sleep_ticks; // realtime ticks idle wavefronts spent sleeping
     unsigned long long pushed_classes;  // classes in the frames pushed onto LDS stacks
     unsigned long long node_classes;    // classes split, summed over the matched

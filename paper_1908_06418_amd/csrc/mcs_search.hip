@@ -85,7 +85,7 @@ struct Searcher {
     int d0;           // depth of the unit's first frame (the shallowest)
     int since_check;
     unsigned long long t_start, pend_nodes, n_batches, n_children, n_lanes, n_don, n_pops, n_busy;
-    unsigned long long n_spill, n_sleep;
+    unsigned long long n_sleep;
     int max_used;  // most classes this wavefront's stack has held
     // per-step counts since the last fold into the 64-bit totals (at most
     // check_interval steps, so 32 bits cannot overflow)
@@ -128,7 +128,7 @@ struct Searcher {
         pend_nodes = n_batches = n_children = n_lanes = n_don = n_pops = n_busy = 0;
         c_nodes = c_batches = c_children = c_lanes = c_pushed = c_ncls = 0;
         n_pushed = n_ncls = 0;
-        n_spill = n_sleep = 0;
+        n_sleep = 0;
         max_used = 0;
         inc = 0;
         t = -1;
@@ -694,20 +694,11 @@ struct Searcher {
             pos[a] = K2 + mbcnt(m);
             K2 += __builtin_popcountll(m);
         }
+        // (the stack holds the worst case, m(m+1)/2 classes: this capacity
+        // check cannot fire)
         const int nb = base + K;
         if (nb + K2 > cap_classes) {
-            // no room on this wavefront's stack: the child goes to the queue
-            // as a record (its mapping may still raise the incumbent)
-            if (lane == 0)
-                smap[d] = (uint16_t)(v | (wF << 8));
-            sync();
-            if (d + 1 > inc)
-                improve(d + 1);
-            // (one wavefront alone has the worst-case stack: no spill there)
-            if (P.single_wave)
-                fail(1);
-            else if (!spill_child<NR>(fb, K2, ne, pos, pl, pr))
-                fail(2);
+            fail(1);
             return;
         }
         if (nb + K2 > max_used)
@@ -851,19 +842,10 @@ struct Searcher {
             pos[j] = K2 + mbcnt(m);
             K2 += __builtin_popcountll(m);
         }
-        // (the stack holds the worst case here: this cannot fire unless the
-        // caller asked for a smaller one)
+        // (the stack holds the worst case: this capacity check cannot fire)
         const int nb = base + K;
         if (nb + K2 > cap_classes) {
-            if (lane == 0)
-                smap[d] = (uint16_t)(v | (wF << 8));
-            sync();
-            if (d + 1 > inc)
-                improve(d + 1);
-            if (P.single_wave)
-                fail(1);
-            else if (!spill_child<2 * NR>(fb, K2, ne, pos, pl, pr))
-                fail(2);
+            fail(1);
             return;
         }
         if (nb + K2 > max_used)
@@ -1123,59 +1105,6 @@ struct Searcher {
         }
         sync();
         n_don += 1;
-    }
-
-    // Queue the child whose classes segment `first` holds (compacted at
-    // pos[j] for the NP parts with ne[j]) as a fresh record: the taker
-    // chooses its class and v.  Its mapping is the current path plus smap[d].
-    template <int NP>
-    __device__ bool spill_child(int fb, int K2, const bool *ne, const int *pos, const W *pl,
-                                const W *pr) {
-        unsigned long long ticket;
-        int ring;
-        if (!reserve(ring, ticket, 1024))
-            return false;
-        const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
-        const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
-        uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
-        RecHdr<W> rh;
-        rh.inst = (uint32_t)inst;
-        rh.K = (uint8_t)K2;
-        rh.d = (uint8_t)(d + 1);
-        rh.v = 0;
-        rh.sel = 0;
-        rh.bound = (uint8_t)fb;
-        rh.flags = (uint8_t)kFlagFresh;
-        rh.lsel = 0;
-        rh.rsel = 0;
-        rh.pad[0] = rh.pad[1] = rh.pad[2] = rh.pad[3] = 0;
-        rh.rrem = 0;
-        if (lane == 0)
-            *(RecHdr<W> *)slot = rh;
-        uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
-        if constexpr (Q == 1) {
-            if (lane <= d)
-                rmap[lane] = smap[lane];
-        } else {
-            for (int j = lane; j <= d; j += 64)
-                rmap[j] = smap[j];
-        }
-        Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
-#pragma unroll
-        for (int a = 0; a < NP; ++a)
-            if (ne[a]) {
-                Cls<W> c;
-                c.L = pl[a];
-                c.R = pr[a];
-                rcls[pos[a]] = c;
-            }
-        if (lane == 0) {
-            a_add_rlx(&P.open[inst], 1);
-            a_add_rlx(&P.g->open_total, 1);
-            st_rel(&P.seq[idx], ticket + 1);
-        }
-        n_spill += 1;
-        return true;
     }
 
     // Take a queued node: from this XCD's ring, else (steal) from one other
@@ -1476,7 +1405,6 @@ struct Searcher {
             a_add64(&P.g->donations, n_don);
             a_add64(&P.g->pops, n_pops);
             a_add64(&P.g->busy_ticks, n_busy);
-            a_add64(&P.g->spills, n_spill);
             a_add64(&P.g->pushed_classes, n_pushed);
             a_add64(&P.g->node_classes, n_ncls);
             a_add64(&P.g->sleep_ticks, n_sleep);

@@ -65,7 +65,12 @@ struct SegSearch {
     // lane identity
     int lane, lk, seg;
     // this lane's segment's LDS
-    Cls<W> *scls;     // [cap + 1]: the last entry is a trash slot
+    Cls<W> *scls;     // [cap + 1]: class stack entries 0 .. cap - 1; the last
+                      // entry is a trash slot
+    Cls<W> *hcls;     // class stack entries cap and above, in HBM (the worst
+                      // case fits: frames never straddle the two parts)
+    Cls<W> *hwave;    // the wavefront's HBM class stacks (segment j at j * hstride)
+    long long hstride;  // classes per segment's HBM part
     W *sadj;          // [NR][arows]
     uint16_t *smap;   // [NB] g | h << 8 per depth
     uint4 *shdr;      // [frames]
@@ -81,8 +86,6 @@ struct SegSearch {
     W cL, cR;         // this lane's class of the top frame (class lk)
     uint32_t nodes_pend;  // nodes of the unit not yet added to the instance's count
     bool fin;         // the unit is finished (its stack emptied)
-    bool spill;       // the child just evaluated did not fit: queue it
-    int spill_w, spill_b;
     unsigned long long pushed;  // classes in the frames this segment pushed
 
     // ---- wave-level ----
@@ -92,11 +95,11 @@ struct SegSearch {
     int since_check;
     int donor;        // segment considered first for the next donation
     unsigned long long t_start;
-    unsigned long long n_steps, n_evals, n_nodes_wave, n_lanes, n_don, n_pops, n_busy, n_spill,
+    unsigned long long n_steps, n_evals, n_nodes_wave, n_lanes, n_don, n_pops, n_busy, n_hbm,
         n_sleep, n_pushed, n_ncls;
     int max_used;
 
-    __device__ SegSearch(const SearchParams &p, uint8_t *wave_lds) : P(p) {
+    __device__ SegSearch(const SearchParams &p, uint8_t *wave_lds, long long wave) : P(p) {
         lane = lane_id();
         lk = lane & (S - 1);
         seg = lane >> LOGS;
@@ -110,6 +113,9 @@ struct SegSearch {
                                        p.frames);
         uint8_t *mine = wave_lds + (size_t)seg * (size_t)seg_bytes;
         scls = (Cls<W> *)(mine + L.cls);
+        hstride = p.hstack_stride / (long long)sizeof(Cls<W>);
+        hwave = (Cls<W> *)p.hstack + wave * NSEG * hstride;
+        hcls = hwave + seg * hstride;
         sadj = (W *)(mine + L.adj);
         smap = (uint16_t *)(mine + L.map);
         shdr = (uint4 *)(mine + L.hdr);
@@ -124,8 +130,6 @@ struct SegSearch {
         rrem = cL = cR = 0;
         nodes_pend = 0;
         fin = false;
-        spill = false;
-        spill_w = spill_b = 0;
         pushed = 0;
         stop = false;
         roots_left = true;
@@ -133,7 +137,7 @@ struct SegSearch {
         steal_from = my_ring;
         since_check = 0;
         donor = 0;
-        n_steps = n_evals = n_nodes_wave = n_lanes = n_don = n_pops = n_busy = n_spill = 0;
+        n_steps = n_evals = n_nodes_wave = n_lanes = n_don = n_pops = n_busy = n_hbm = 0;
         n_sleep = n_pushed = n_ncls = 0;
         max_used = 0;
     }
@@ -176,6 +180,34 @@ struct SegSearch {
         const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
         return (Cls<W> *)(wlds + (size_t)j * seg_bytes + L.cls);
     }
+    // Class stack entry i of this lane's segment (LDS below cap, HBM above).
+    __device__ Cls<W> cget(int i) const {
+        if (i < cap)
+            return scls[i];
+        return hcls[i - cap];
+    }
+    __device__ void cput(int i, const Cls<W> &c) const {
+        if (i < cap)
+            scls[i] = c;
+        else
+            hcls[i - cap] = c;
+    }
+    // Entry i of segment j's class stack.
+    __device__ Cls<W> cget_of(int j, int i) const {
+        if (i < cap)
+            return cls_of(j)[i];
+        return hwave[(long long)j * hstride + (i - cap)];
+    }
+    // Orders a segment's class stores before other lanes of the wavefront
+    // read them: an LDS frame needs only the wave's in-order LDS; a frame in
+    // HBM needs its stores completed first.
+    __device__ void sync_frame(bool in_hbm) const {
+        if (ballot(in_hbm))
+            wave_sync_global();
+        else
+            wave_sync();
+    }
+
     __device__ W *adj_of(int j) const {
         const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
         return (W *)(wlds + (size_t)j * seg_bytes + L.adj);
@@ -223,7 +255,7 @@ struct SegSearch {
     // Class lk of the top frame into registers.
     __device__ void load_regs() {
         const bool in = lk < K;
-        const Cls<W> c = scls[base + (in ? lk : 0)];
+        const Cls<W> c = cget(base + (in ? lk : 0));
         cL = in ? c.L : (W)0;
         cR = in ? c.R : (W)0;
     }
@@ -241,7 +273,7 @@ struct SegSearch {
         for (int c = 1; ballot(c * S < K) != 0; ++c) {
             const int k = c * S + lk;
             if (k < K) {
-                const Cls<W> x = scls[base + k];
+                const Cls<W> x = cget(base + k);
                 const int nl = popc(x.L), nr = popc(x.R);
                 key = umin(key, ((uint32_t)(nl > nr ? nl : nr) << 16) |
                                     ((uint32_t)ctz(x.L) << 8) | (uint32_t)k);
@@ -250,7 +282,7 @@ struct SegSearch {
         const uint32_t mk = smin(key);
         v = (int)((mk >> 8) & 0xFFu);
         sel = (int)(mk & 0xFFu);
-        const Cls<W> cs = scls[base + sel];
+        const Cls<W> cs = cget(base + sel);
         rrem = cs.R;
         lsel = popc(cs.L);
         rsel = popc(cs.R);
@@ -258,7 +290,7 @@ struct SegSearch {
 
     // |L_sel| and |R_sel| of a frame the search returns to.
     __device__ void recount_sel() {
-        const Cls<W> cs = scls[base + sel];
+        const Cls<W> cs = cget(base + sel);
         lsel = popc(cs.L);
         rsel = popc(cs.R);
     }
@@ -324,17 +356,18 @@ struct SegSearch {
             // the class empties on the G side: the last class takes its place
             const int last = K - 1;
             if (sel != last) {
-                const Cls<W> c = scls[base + last];
+                const Cls<W> c = cget(base + last);
                 if (lk == 0)
-                    scls[base + sel] = c;
+                    cput(base + sel, c);
             }
             K = last;
         } else {
-            const Cls<W> c = scls[base + sel];
+            Cls<W> c = cget(base + sel);
+            c.L &= ~vb;
             if (lk == 0)
-                scls[base + sel].L = c.L & ~vb;
+                cput(base + sel, c);
         }
-        wave_sync();
+        sync_frame(base >= cap);
         bound = ub;
         if (K == 0)
             return;
@@ -389,7 +422,7 @@ struct SegSearch {
         for (int c = 1; ballot(c * S < K) != 0; ++c) {
             const int k = c * S + lk;
             if (k < K) {
-                const Cls<W> x = scls[base + k];
+                const Cls<W> x = cget(base + k);
                 W ql[NR], qr[NR];
                 split(x.L & ~vb, x.R & ~wb, go, ho, gi, hi, ql, qr);
                 contrib += part_min(ql, qr);
@@ -402,9 +435,15 @@ struct SegSearch {
     }
 
     // The child (v, w) survived its bound: compact its non-empty classes
-    // into a new frame above the top one and make it the top frame.
+    // into a new frame above the top one and make it the top frame.  Every
+    // kept class adds at least one to the Eq. 1 sum, so the child has at most
+    // b - d - 1 classes: a frame that might not fit below cap starts at cap,
+    // in the HBM part of the stack, so no frame straddles the two parts.
     __device__ void descend(int w, int b, W go, W ho, W gi, W hi, const W *pl, const W *pr) {
-        const int nb = base + K;
+        int nb = base + K;
+        if (nb < cap && nb + (b - d - 1) > cap)
+            nb = cap;
+        const bool hbm = nb >= cap;
         int K2 = 0;
 #pragma unroll
         for (int a = 0; a < NR; ++a) {
@@ -414,7 +453,10 @@ struct SegSearch {
             Cls<W> c;
             c.L = pl[a];
             c.R = pr[a];
-            scls[(ne && at < cap) ? at : cap] = c;
+            if (!hbm)
+                scls[ne ? at : cap] = c;
+            else if (ne)
+                hcls[at - cap] = c;
             K2 += __builtin_popcount(m);
         }
         const W vb = (W)1 << v;
@@ -423,7 +465,7 @@ struct SegSearch {
             const int k = c * S + lk;
             W ql[NR], qr[NR];
             const bool in = k < K;
-            const Cls<W> x = scls[base + (in ? k : 0)];
+            const Cls<W> x = cget(base + (in ? k : 0));
             split(in ? x.L & ~vb : (W)0, in ? x.R & ~wb : (W)0, go, ho, gi, hi, ql, qr);
 #pragma unroll
             for (int a = 0; a < NR; ++a) {
@@ -433,7 +475,10 @@ struct SegSearch {
                 Cls<W> y;
                 y.L = ql[a];
                 y.R = qr[a];
-                scls[(ne && at < cap) ? at : cap] = y;
+                if (!hbm)
+                    scls[ne ? at : cap] = y;
+                else if (ne)
+                    hcls[at - cap] = y;
                 K2 += __builtin_popcount(m);
             }
         }
@@ -441,19 +486,15 @@ struct SegSearch {
         save_hdr();
         if (lk == 0)
             smap[d] = (uint16_t)(v | (w << 8));
-        wave_sync();
+        sync_frame(hbm);
         if (d + 1 > inc)
             improve(d + 1);
         if (K2 == 0)
             return;  // a leaf: nothing left to split
-        if (nb + K2 > cap) {
-            spill = true;  // no room on the stack: the child goes to the queue
-            spill_w = w;
-            spill_b = b;
-            return;
-        }
         if (nb + K2 > max_used)
             max_used = nb + K2;
+        if (hbm)
+            n_hbm += 1;
         pushed += (unsigned long long)K2;
         t += 1;
         base = nb;
@@ -490,8 +531,6 @@ struct SegSearch {
             n_ncls += (unsigned long long)wave_sum_u(need_eval && lk == 0 ? Kb : 0);
         }
         n_steps += 1;
-        if (ballot(spill))
-            spill_children();
         if (ballot(fin))
             finish_units();
     }
@@ -546,88 +585,6 @@ struct SegSearch {
             __hip_atomic_store(&P.g->error, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         raise_flag(kFlagStop);
         stop = true;
-    }
-
-    // Queue each child that found no room on its segment's stack, as a fresh
-    // record (the taker chooses its class and v).
-    __device__ void spill_children() {
-        uint64_t sm = ballot(spill && lk == 0);
-        while (sm) {
-            const int j = ctz(sm) >> LOGS;
-            sm &= sm - 1;
-            if (P.single_wave) {
-                fail(1);  // (one wavefront alone has the worst-case stack)
-                break;
-            }
-            unsigned long long ticket;
-            int ring;
-            if (!reserve(ring, ticket, 1024)) {
-                fail(2);
-                break;
-            }
-            const unsigned long long mask = (unsigned long long)P.ring_slots - 1;
-            const size_t idx = (size_t)ring * P.ring_slots + (size_t)(ticket & mask);
-            uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
-            const int ji = of(inst, j), jd = of(d, j);
-            if (seg == j) {
-                // the child's classes, compacted in the same order as descend()
-                const W vb = (W)1 << v;
-                const W wb = (W)1 << spill_w;
-                const W go = sadj[v], ho = sadj[arows + spill_w];
-                W gi = 0, hi = 0;
-                if constexpr (DIR) {
-                    gi = sadj[2 * arows + v];
-                    hi = sadj[3 * arows + spill_w];
-                }
-                Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
-                int K2 = 0;
-                for (int c = 0; ballot(c * S < K) != 0; ++c) {
-                    const int k = c * S + lk;
-                    const bool in = k < K;
-                    const Cls<W> x = scls[base + (in ? k : 0)];
-                    W ql[NR], qr[NR];
-                    split(in ? x.L & ~vb : (W)0, in ? x.R & ~wb : (W)0, go, ho, gi, hi, ql, qr);
-#pragma unroll
-                    for (int a = 0; a < NR; ++a) {
-                        const bool ne = ql[a] != 0 && qr[a] != 0;
-                        const uint32_t m = sbits(ballot(ne));
-                        if (ne) {
-                            Cls<W> y;
-                            y.L = ql[a];
-                            y.R = qr[a];
-                            rcls[K2 + below(m)] = y;
-                        }
-                        K2 += __builtin_popcount(m);
-                    }
-                }
-                uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
-                for (int i = lk; i <= d; i += S)
-                    rmap[i] = smap[i];
-                if (lk == 0) {
-                    RecHdr<W> rh;
-                    rh.inst = (uint32_t)inst;
-                    rh.K = (uint8_t)K2;
-                    rh.d = (uint8_t)(d + 1);
-                    rh.v = 0;
-                    rh.sel = 0;
-                    rh.bound = (uint8_t)spill_b;
-                    rh.flags = (uint8_t)kFlagFresh;
-                    rh.lsel = 0;
-                    rh.rsel = 0;
-                    rh.pad[0] = rh.pad[1] = rh.pad[2] = rh.pad[3] = 0;
-                    rh.rrem = 0;
-                    *(RecHdr<W> *)slot = rh;
-                }
-                spill = false;
-            }
-            if (lane == 0) {
-                a_add_rlx(&P.open[ji], 1);
-                a_add_rlx(&P.g->open_total, 1);
-                st_rel(&P.seq[idx], ticket + 1);
-            }
-            (void)jd;
-            n_spill += 1;
-        }
     }
 
     // Give segment j's shallowest open frame's remaining children to the
@@ -707,7 +664,7 @@ struct SegSearch {
             const int fsel = (int)((hw >> 8) & 0xFFu);
             rh.sel = (uint8_t)fsel;
             rh.bound = (uint8_t)((hw >> 16) & 0xFFu);
-            const Cls<W> cs = cls_of(j)[fbase + fsel];
+            const Cls<W> cs = cget_of(j, fbase + fsel);
             rh.lsel = (uint8_t)popc(sc(cs.L));
             rh.rsel = (uint8_t)popc(sc(cs.R));
         }
@@ -723,11 +680,10 @@ struct SegSearch {
         uint16_t *rmap = (uint16_t *)(slot + rec_map_off<W>());
         Cls<W> *rcls = (Cls<W> *)(slot + rec_cls_off<W>());
         const uint16_t *jm = map_of(j);
-        const Cls<W> *jc = cls_of(j);
         for (int i = lane; i < fd; i += 64)
             rmap[i] = jm[i];
         for (int i = lane; i < fK; i += 64)
-            rcls[i] = jc[fbase + i];
+            rcls[i] = cget_of(j, fbase + i);
         if (lane == 0) {
             a_add_rlx(&P.open[ji], 1);
             a_add_rlx(&P.g->open_total, 1);
@@ -779,7 +735,6 @@ struct SegSearch {
             set_inc(g);
             nodes_pend = 0;
             fin = false;
-            spill = false;
         }
     }
 
@@ -915,7 +870,7 @@ struct SegSearch {
             for (int c = 0; ballot(c * S < K) != 0; ++c) {
                 const int k = c * S + lk;
                 if (k < K) {
-                    const Cls<W> x = c == 0 ? Cls<W>{cL, cR} : scls[base + k];
+                    const Cls<W> x = c == 0 ? Cls<W>{cL, cR} : cget(base + k);
                     const int nl = popc(x.L), nr = popc(x.R);
                     contrib += nl < nr ? nl : nr;
                 }
@@ -1116,12 +1071,10 @@ struct SegSearch {
         }
         if (busy)
             n_busy += now_ticks() - t_busy0;
-        {
-            // classes pushed, summed over the segments (lane 0 of each)
-            const unsigned long long x = lk == 0 ? pushed : 0ull;
-            n_pushed = (unsigned long long)(unsigned)wave_sum((int)(unsigned)x) +
-                       ((unsigned long long)(unsigned)wave_sum((int)(unsigned)(x >> 32)) << 32);
-        }
+        // classes pushed and frames placed in HBM, summed over the segments
+        // (lane 0 of each)
+        n_pushed = seg_total(pushed);
+        n_hbm = seg_total(n_hbm);
         if (lane == 0) {
             a_add64(&P.g->batches, n_steps);
             a_add64(&P.g->children, n_evals);
@@ -1129,7 +1082,7 @@ struct SegSearch {
             a_add64(&P.g->donations, n_don);
             a_add64(&P.g->pops, n_pops);
             a_add64(&P.g->busy_ticks, n_busy);
-            a_add64(&P.g->spills, n_spill);
+            a_add64(&P.g->hbm_frames, n_hbm);
             a_add64(&P.g->pushed_classes, n_pushed);
             a_add64(&P.g->sleep_ticks, n_sleep);
             a_add64(&P.g->node_classes, n_ncls);
@@ -1141,6 +1094,11 @@ struct SegSearch {
     }
 
     DEV int wave_max_i(int x) { return (int)~wave_min(~(uint32_t)x); }
+    __device__ unsigned long long seg_total(unsigned long long x) const {
+        x = lk == 0 ? x : 0ull;
+        return (unsigned long long)(unsigned)wave_sum((int)(unsigned)x) +
+               ((unsigned long long)(unsigned)wave_sum((int)(unsigned)(x >> 32)) << 32);
+    }
 };
 
 template <typename W, bool DIR, int LOGS>
@@ -1153,7 +1111,8 @@ __global__ void __launch_bounds__(256) mcs_seg_kernel(SearchParams Pk) {
     const int wv = threadIdx.x >> 6;
     if (Pk.single_wave && (blockIdx.x != 0 || wv != 0))
         return;
-    SegSearch<W, DIR, LOGS> s(P, smem + (size_t)wv * (size_t)(Pk.seg_bytes * (64 >> LOGS)));
+    SegSearch<W, DIR, LOGS> s(P, smem + (size_t)wv * (size_t)(Pk.seg_bytes * (64 >> LOGS)),
+                              (long long)blockIdx.x * (blockDim.x >> 6) + wv);
     s.main_loop();
 }
 

@@ -142,47 +142,73 @@ def test_policy_search_is_exact(gpu, trained):
     assert [r.size for r in res] == want[:20]
 
 
-def _feature_net(sign: float) -> np.ndarray:
-    """Parameters whose network output is sign * feature 0 (degree / n):
-    W1[0][0] = 1, W2[0][0] = 1, w3[0] = sign, everything else 0 (exact in
-    half precision)."""
+def _feature_net(k: int, sign: float) -> np.ndarray:
+    """Parameters whose network output is sign * feature k: W1[0][k] = 1,
+    W2[0][0] = 1, w3[0] = sign, everything else 0 (exact in half precision;
+    every feature is non-negative, so the ReLUs pass it unchanged)."""
     p = ref.unflat(np.zeros(ref.N_PARAMS))
-    p = {k: a.copy() for k, a in p.items()}
-    p["W1"][0, 0] = 1.0
+    p = {key: a.copy() for key, a in p.items()}
+    p["W1"][0, k] = 1.0
     p["W2"][0, 0] = 1.0
     p["w3"][0] = sign
     return ref.flat(p)
 
 
-def test_in_search_scorer_plumbing(gpu):
-    """The in-search scorer, end to end: with a network whose score is the
-    candidate's degree / n, choosing v by the policy and ordering partners
-    by it reproduce the plain rule exactly (vertices are numbered by
-    descending degree, ties by index, and the policy breaks score ties by the
-    lowest index), so a single wavefront expands exactly the plain search's
-    nodes.  With the negated score the search changes (other node counts)
-    but every size stays the oracle's."""
+def _scorer_pairs():
+    rng = np.random.default_rng(11)
+    pairs = []
+    while len(pairs) < 16:
+        n = int(rng.integers(10, 15))
+        p = float(rng.uniform(0.25, 0.6))
+        nl = int(rng.integers(0, 3)) if len(pairs) % 4 == 3 else 0
+        pairs.append((mi.random_small(rng, n, p, False, nl), mi.random_small(rng, n, p, False, nl)))
+    return pairs
+
+
+def _python_nodes(pairs, k, sign, depth, mode):
+    """Node counts of the plain Python recursion ordered by sign * feature k
+    of oracle.policy.features at nodes with |M| <= depth."""
+    from _mcsplit_py import Counter, root
+    out = []
+    for G, H in pairs:
+        def score(u, side, classes, sel, d, cand, G=G, H=H):
+            return sign * ref.features(G if side == 0 else H, u, side, classes, sel, d, cand)[k]
+        c = Counter(G, H, 0, score=score, depth_max=depth, mode=mode)
+        c.rec(root(G, H), 0)
+        out.append(c.nodes)
+    return out
+
+
+def test_in_search_scorer_features(gpu):
+    """The in-search scorer computes the features the policy is trained on.
+    For every feature k, a network whose score is +feature k (and, for the
+    features that differ between candidates, -feature k) orders the search
+    at |M| <= 3: choosing v (mode 1), the partners (mode 2) or both (3).
+    One search alone, one child at a time and no re-pruning expands exactly
+    the nodes of the plain Python recursion ordered by the float64 features
+    of oracle.policy; sizes stay the oracle's."""
     from paper_1908_06418_amd import solve_batch
     from paper_1908_06418_amd.policy import Policy
-    rng = np.random.default_rng(5)
-    pairs = [pq for pq in mi.pairs_c4(120, start=2000) if pq[0]["n"] <= 22][:24]
-    pairs += [(mi.random_small(rng, 14, 0.4, False, 3), mi.random_small(rng, 15, 0.4, False, 3))
-              for _ in range(6)]
-    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
-    tun = {"single_wave": 1}
+    pairs = _scorer_pairs()
+    want = [oracle.mcs(G, H) for G, H in pairs]
+    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1, "seg_lanes": 64}
     plain = solve_batch(pairs, time_limit_s=60, tuning=tun)
-    deg = Policy(params=_feature_net(1.0))
-    neg = Policy(params=_feature_net(-1.0))
-    for mode in (1, 2, 3):
-        _say(f"scorer plumbing, mode {mode}")
-        same = solve_batch(pairs, time_limit_s=60, tuning=tun, policy=deg, policy_depth=8,
-                           policy_mode=mode)
-        assert [r.nodes for r in same] == [r.nodes for r in plain], mode
-        assert [r.size for r in same] == want
-    other = solve_batch(pairs, time_limit_s=60, tuning=tun, policy=neg, policy_depth=8,
-                        policy_mode=1)
-    assert [r.size for r in other] == want
-    assert [r.nodes for r in other] != [r.nodes for r in plain]
+    assert [r.nodes for r in plain] == [o["nodes"] for o in want]
+    varying = (0, 5, 6, 7, 8, 9, 13)
+    changed = 0
+    for k in range(ref.F):
+        for sign in ((1.0, -1.0) if k in varying else (1.0,)):
+            for mode in (1, 2, 3):
+                _say(f"scorer feature {k} sign {sign:+.0f} mode {mode}")
+                res = solve_batch(pairs, time_limit_s=60, tuning=tun,
+                                  policy=Policy(params=_feature_net(k, sign)), policy_depth=3,
+                                  policy_mode=mode)
+                exp = _python_nodes(pairs, k, sign, 3, mode)
+                assert [r.nodes for r in res] == exp, (k, sign, mode)
+                assert [r.size for r in res] == [o["size"] for o in want]
+                changed += exp != [o["nodes"] for o in want]
+    # the orders really differ from the plain rule in many of these runs
+    assert changed >= 10
 
 
 def test_policy_gain_report(gpu):
