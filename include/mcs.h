@@ -149,8 +149,29 @@ typedef struct {
                                   components, a component with more non-zero
                                   rows per non-zero column first, each in a
                                   bordered block-triangular order (the column
-                                  meeting the most shortest active rows next).
-                                  Sizes do not depend on it; node counts do. */
+                                  meeting the most shortest active rows next);
+                                  2: both, as a portfolio (Sec. IV): each pair
+                                  is searched twice in the same launch, under
+                                  order 0 and under order 1, and the two
+                                  searches share one incumbent (a mapping
+                                  either finds prunes the other) and stop
+                                  together once either has finished; nodes
+                                  are summed over both, the mapping is the
+                                  one of the search that found the final
+                                  size.  Sizes do not depend on the order;
+                                  node counts do. */
+    int32_t deadend_ratio;     /* dead-end forecast (paper Sec. IV.A), with
+                                  deadend_nodes: an instance is given up once
+                                  its search has gone more than deadend_nodes
+                                  nodes and more than deadend_ratio times the
+                                  nodes that led to its last improvement
+                                  (0: the absolute threshold alone) without
+                                  raising its incumbent.  Its result is then
+                                  the best mapping so far, optimal = 0, and
+                                  the call returns MCS_LIMIT;
+                                  mcs_solve_goals strategies 2 and 3 answer a
+                                  forecast by stepping the bound. */
+    int64_t deadend_nodes;     /* 0: no dead-end forecast */
 } mcs_opts;
 
 /* Per-instance result.  map_g/map_h are caller-owned arrays of capacity

@@ -87,14 +87,15 @@ class _Marshal:
                               rows.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), lab)
 
 
-ORDERINGS = {"degree": 0, "btf": 1}
+ORDERINGS = {"degree": 0, "btf": 1, "portfolio": 2}
 
 
 def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0, policy_mode=0,
-          ordering="degree"):
+          ordering="degree", deadend_nodes=0, deadend_ratio=0):
     """policy: a torch half tensor of packed parameters on the device (or an
-    object with .half_params, see policy.Policy).  ordering: "degree" or
-    "btf" (mcs_opts.ordering)."""
+    object with .half_params, see policy.Policy).  ordering: "degree",
+    "btf" or "portfolio" (both orders racing on one incumbent;
+    mcs_opts.ordering)."""
     t = None
     tc = None
     if tuning is not None:
@@ -105,7 +106,8 @@ def _opts(node_limit, time_limit_s, tuning, policy=None, policy_depth=0, policy_
         hp = getattr(policy, "half_params", policy)
         ptr = ctypes.c_void_p(hp.data_ptr())
     o = _abi.mcs_opts(int(node_limit or 0), float(time_limit_s or 0.0), t, ptr,
-                      int(policy_depth), int(policy_mode), ORDERINGS[ordering])
+                      int(policy_depth), int(policy_mode), ORDERINGS[ordering],
+                      int(deadend_ratio), int(deadend_nodes))
     return o, tc
 
 
@@ -161,13 +163,14 @@ class Plan:
     (mcs_plan_run) -- inputs stay resident in HBM between runs."""
 
     def __init__(self, pairs, node_limit=0, time_limit_s=0.0, tuning=None, policy=None,
-                 policy_depth=1, policy_mode=0, ordering="degree"):
+                 policy_depth=1, policy_mode=0, ordering="degree", deadend_nodes=0,
+                 deadend_ratio=0):
         self.lib = _abi.load()
         self.pairs = list(pairs)
         self._m = _Marshal(self.pairs)
         self._policy = policy  # keeps the device parameters alive
         self._o, self._t = _opts(node_limit, time_limit_s, tuning, policy, policy_depth,
-                                 policy_mode, ordering)
+                                 policy_mode, ordering, deadend_nodes, deadend_ratio)
         h = ctypes.c_void_p()
         st = self.lib.mcs_plan_create(len(self.pairs), self._m.G, self._m.H,
                                       ctypes.byref(self._o), ctypes.byref(h))
@@ -249,10 +252,11 @@ class Plan:
 
 
 def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=False,
-                policy=None, policy_depth=1, policy_mode=0, ordering="degree"):
+                policy=None, policy_depth=1, policy_mode=0, ordering="degree",
+                deadend_nodes=0, deadend_ratio=0):
     """MCS of every pair in one launch.  Returns a list of Result (and Stats)."""
     p = Plan(pairs, node_limit, time_limit_s, tuning, policy, policy_depth, policy_mode,
-             ordering).upload()
+             ordering, deadend_nodes, deadend_ratio).upload()
     p.run()
     res = p.results()
     st = p.stats() if with_stats else None
@@ -260,17 +264,25 @@ def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=F
     return (res, st) if with_stats else res
 
 
+GOAL_STRATEGIES = {"top-down": 0, "bisect": 1, "dead-end+1": 2, "dead-end*2": 3}
+
+
 def solve_goals(pairs, strategy="top-down", node_limit=0, time_limit_s=0.0, tuning=None,
-                with_launches=False):
+                with_launches=False, ordering="degree", deadend_nodes=0, deadend_ratio=0):
     """Goal-directed search (mcs_solve_goals): strategy "top-down" asks for
     the root bound, then one less, ...; "bisect" takes a node-limited plain
-    run's size as a lower bound and binary-searches the goal."""
+    run's size as a lower bound and binary-searches the goal; "dead-end+1"
+    and "dead-end*2" run the plain search with the dead-end forecast
+    (deadend_nodes, deadend_ratio) and answer each forecast by raising the
+    incumbent by 1, or by an increment that doubles at each forecast, then
+    binary-search once a raised bound proves unreachable."""
     import torch
     lib = _abi.load()
     _torch()
     pairs = list(pairs)
     m = _Marshal(pairs)
-    o, _t = _opts(node_limit, time_limit_s, tuning)
+    o, _t = _opts(node_limit, time_limit_s, tuning, ordering=ordering,
+                  deadend_nodes=deadend_nodes, deadend_ratio=deadend_ratio)
     nbytes = int(lib.mcs_workspace_size(len(pairs), m.G, m.H, ctypes.byref(o)))
     if nbytes == 0:
         raise McsError(-1, _last_error())
@@ -286,7 +298,7 @@ def solve_goals(pairs, strategy="top-down", node_limit=0, time_limit_s=0.0, tuni
         bufs.append((mg, mh))
         res[i].map_g, res[i].map_h = mg, mh
     launches = ctypes.c_int32(0)
-    strat = {"top-down": 0, "bisect": 1}[strategy]
+    strat = GOAL_STRATEGIES[strategy]
     st = lib.mcs_solve_goals(n, m.G, m.H, ctypes.byref(o), strat, ctypes.c_void_p(base), nbytes,
                              ctypes.c_void_p(stream.cuda_stream), res, ctypes.byref(launches))
     if st < 0:

@@ -37,7 +37,8 @@ class mcs_opts(ctypes.Structure):
     _fields_ = [("node_limit", ctypes.c_int64), ("time_limit_s", ctypes.c_double),
                 ("tuning", ctypes.POINTER(mcs_tuning)),
                 ("policy", ctypes.c_void_p), ("policy_depth", ctypes.c_int32),
-                ("policy_mode", ctypes.c_int32), ("ordering", ctypes.c_int32)]
+                ("policy_mode", ctypes.c_int32), ("ordering", ctypes.c_int32),
+                ("deadend_ratio", ctypes.c_int32), ("deadend_nodes", ctypes.c_int64)]
 
 
 class mcs_result(ctypes.Structure):

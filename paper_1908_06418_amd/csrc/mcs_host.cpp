@@ -253,16 +253,24 @@ hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 }  // namespace
 
 struct mcs_plan {
-    int count = 0;
+    int count = 0;     // search instances on the device
+    int pairs = 0;     // the caller's pairs (count, or count / 2 for a portfolio)
+    int portfolio = 0; // 1: pair k is instances 2k (degree order) and 2k + 1
+                       // (block-triangular order), sharing incumbent word 2k
     int directed = 0;
     int word_bytes = 8;
     int mmax = 0;
     mcs_tuning tun{};
     int64_t node_limit = 0;
+    int64_t dead_abs = 0, dead_rel = 0;  // dead-end forecast thresholds (0: off)
     double time_limit_s = 600.0;
     const uint16_t *policy = nullptr;
     int policy_depth = 0, policy_levels = 0, policy_mode = 0;
-    int ordering = 0;  // 0: descending degree; 1: components, block-triangular (Sec. IV.A)
+    int ordering = 0;  // 0: descending degree; 1: components, block-triangular (Sec. IV.A);
+                       // 2: both, as a portfolio
+
+    // first device instance of the caller's pair k
+    int dev(int k) const { return portfolio ? 2 * k : k; }
 
     std::vector<mcs::DevInst> inst;
     std::vector<uint8_t> adj;      // packed rows, word_bytes each (4, 8 or 16)
@@ -275,7 +283,7 @@ struct mcs_plan {
 
     // device layout
     size_t off_inst = 0, off_adj = 0, off_cls = 0, off_inc = 0, off_open = 0, off_nodes = 0,
-           off_tbest = 0, off_tproof = 0, off_maps = 0, off_glob = 0, off_seq = 0, off_slots = 0,
+           off_tbest = 0, off_tproof = 0, off_bestn = 0, off_dead = 0, off_maps = 0, off_glob = 0, off_seq = 0, off_slots = 0,
            off_hstack = 0, hstack_stride = 0,
            ws_bytes = 0;
     int ring_slots = 0, slot_bytes = 0, cap_classes = 0, frames = 0, lds_per_wave = 0;
@@ -302,7 +310,7 @@ struct mcs_plan {
     float last_ms = 0.f;
 
     // results of the last run
-    std::vector<int> h_inc, h_open;
+    std::vector<int> h_inc, h_open, h_dead;
     std::vector<unsigned long long> h_nodes, h_tbest, h_tproof;
     std::vector<uint16_t> h_maps;
     std::vector<uint8_t> h_out;  // the result range as copied back
@@ -398,6 +406,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     }
 
     mcs_plan *p = new mcs_plan();
+    p->pairs = count;
     p->count = count;
     p->directed = directed;
     if (opts) {
@@ -418,11 +427,22 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
             p->policy_levels = opts->policy_depth + 1;
         }
         p->node_limit = opts->node_limit > 0 ? opts->node_limit : 0;
-        if (opts->ordering < 0 || opts->ordering > 1) {
+        if (opts->deadend_nodes < 0 || opts->deadend_ratio < 0) {
             delete p;
-            return fail(MCS_E_INVALID, "ordering must be 0 (degree) or 1 (block-triangular)");
+            return fail(MCS_E_INVALID, "deadend_nodes and deadend_ratio must be >= 0");
+        }
+        p->dead_abs = opts->deadend_nodes;
+        p->dead_rel = opts->deadend_ratio;
+        if (opts->ordering < 0 || opts->ordering > 2) {
+            delete p;
+            return fail(MCS_E_INVALID, "ordering must be 0 (degree), 1 (block-triangular) or "
+                                       "2 (both, as a portfolio)");
         }
         p->ordering = opts->ordering;
+        if (p->ordering == 2) {
+            p->portfolio = 1;
+            p->count = 2 * count;
+        }
         if (opts->time_limit_s > 0)
             p->time_limit_s = opts->time_limit_s;
     }
@@ -437,16 +457,19 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     const int NB = 8 * p->word_bytes;
     const int R = directed ? 4 : 2;
 
-    p->inst.resize(count);
-    p->ordG.resize(count);
-    p->ordH.resize(count);
-    p->m.resize(count);
+    const int ndev = p->count;
+    p->inst.resize(ndev);
+    p->ordG.resize(ndev);
+    p->ordH.resize(ndev);
+    p->m.resize(ndev);
     uint32_t cls_off = 0;
     size_t map_off = 0;
-    for (int i = 0; i < count; i++) {
-        const mcs_graph &g = G[i], &h = H[i];
-        p->ordG[i] = p->ordering == 1 ? btf_order(g) : degree_order(g);
-        p->ordH[i] = p->ordering == 1 ? btf_order(h) : degree_order(h);
+    for (int i = 0; i < ndev; i++) {
+        const int k = p->portfolio ? i >> 1 : i;
+        const mcs_graph &g = G[k], &h = H[k];
+        const int order = p->portfolio ? (i & 1) : p->ordering;
+        p->ordG[i] = order == 1 ? btf_order(g) : degree_order(g);
+        p->ordH[i] = order == 1 ? btf_order(h) : degree_order(h);
         std::vector<Bits> rg = permuted_rows(g, p->ordG[i]);
         std::vector<Bits> rh = permuted_rows(h, p->ordH[i]);
         std::vector<std::vector<Bits>> sets = {rg, rh};
@@ -498,8 +521,9 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         di.map_off = (uint32_t)map_off;
         di.lb = 0;
         di.target = 0;
-        di.inc_slot = i;
-        di.twin = -1;
+        di.inc_slot = p->portfolio ? (i & ~1) : i;
+        di.twin = p->portfolio ? (i ^ 1) : -1;
+        di.dead_on = p->dead_abs > 0 ? 1 : 0;
         p->inst[i] = di;
         p->K0.push_back(K0);
         // Eq. 1 at the root: the largest size any goal needs to consider
@@ -531,7 +555,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         pack_word(p->rootcls, p->word_bytes, Bits{}), pack_word(p->rootcls, p->word_bytes, Bits{});
     p->map_pairs = std::max<size_t>(map_off, 1);
     // The worst case of the depth-first class stack: frame t holds at most
-    // m - t classes.  Smaller stacks queue the children that do not fit.
+    // m - t classes.
     const int full_cap = std::max(1, p->mmax * (p->mmax + 1) / 2);
     const int min_cap = std::min(full_cap, 2 * p->mmax + 1);
     p->frames = p->mmax + 1;
@@ -578,9 +602,9 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     // more searches only split the work into ever smaller donations.
     const int want_waves =
         p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
-        : p->seg_log ? std::max(2 * cus, std::min((48 / nseg) * cus, (96 * count + nseg - 1) / nseg))
-        : wide       ? std::max(4 * cus, std::min(16 * cus, 96 * count))
-                     : std::max(8 * cus, std::min(24 * cus, 96 * count));
+        : p->seg_log ? std::max(2 * cus, std::min((48 / nseg) * cus, (96 * ndev + nseg - 1) / nseg))
+        : wide       ? std::max(4 * cus, std::min(16 * cus, 96 * ndev))
+                     : std::max(8 * cus, std::min(24 * cus, 96 * ndev));
     const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
     if (p->seg_log) {
         // adjacency rows a segment keeps: the batch's largest graph, to 4
@@ -677,14 +701,16 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         o = align256(o + bytes);
         return at;
     };
-    p->off_inst = take(sizeof(mcs::DevInst) * count);
+    p->off_inst = take(sizeof(mcs::DevInst) * ndev);
     p->off_adj = take(p->adj.size());
     p->off_cls = take(p->rootcls.size());
-    p->off_inc = take(sizeof(int) * count);
-    p->off_open = take(sizeof(int) * count);
-    p->off_nodes = take(sizeof(unsigned long long) * count);
-    p->off_tbest = take(sizeof(unsigned long long) * count);
-    p->off_tproof = take(sizeof(unsigned long long) * count);
+    p->off_inc = take(sizeof(int) * ndev);
+    p->off_open = take(sizeof(int) * ndev);
+    p->off_nodes = take(sizeof(unsigned long long) * ndev);
+    p->off_tbest = take(sizeof(unsigned long long) * ndev);
+    p->off_tproof = take(sizeof(unsigned long long) * ndev);
+    p->off_bestn = take(sizeof(unsigned long long) * ndev);
+    p->off_dead = take(sizeof(int) * ndev);
     p->off_maps = take(sizeof(uint16_t) * p->map_pairs);
     p->off_glob = take(sizeof(mcs::DevGlobals));
     p->off_seq = take(sizeof(unsigned long long) * mcs::kRings * p->ring_slots);
@@ -731,6 +757,8 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.nodes = (unsigned long long *)(p->ws + p->off_nodes);
     sp.t_best = (unsigned long long *)(p->ws + p->off_tbest);
     sp.t_proof = (unsigned long long *)(p->ws + p->off_tproof);
+    sp.best_nodes = (unsigned long long *)(p->ws + p->off_bestn);
+    sp.dead = (int *)(p->ws + p->off_dead);
     sp.maps = (uint16_t *)(p->ws + p->off_maps);
     sp.g = (mcs::DevGlobals *)(p->ws + p->off_glob);
     sp.seq = (unsigned long long *)(p->ws + p->off_seq);
@@ -759,6 +787,8 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     double ticks = p->time_limit_s * p->tick_hz;
     sp.limit_ticks = ticks > 9e18 ? (unsigned long long)9e18 : (unsigned long long)ticks;
     sp.node_limit = p->node_limit;
+    sp.dead_abs = p->dead_abs;
+    sp.dead_rel = p->dead_rel;
     sp.hstack = p->hstack_stride ? p->ws + p->off_hstack : nullptr;
     sp.hstack_stride = p->hstack_stride;
     sp.seg_log = p->seg_log;
@@ -772,6 +802,8 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     rp.nodes = sp.nodes;
     rp.t_best = sp.t_best;
     rp.t_proof = sp.t_proof;
+    rp.best_nodes = sp.best_nodes;
+    rp.dead = sp.dead;
     rp.g = sp.g;
     rp.seq = sp.seq;
     rp.count = p->count;
@@ -941,6 +973,8 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
     p->h_inc.assign((const int *)(o + (p->off_inc - ob)), (const int *)(o + (p->off_inc - ob)) + n);
     p->h_open.assign((const int *)(o + (p->off_open - ob)),
                      (const int *)(o + (p->off_open - ob)) + n);
+    p->h_dead.assign((const int *)(o + (p->off_dead - ob)),
+                     (const int *)(o + (p->off_dead - ob)) + n);
     auto u64s = [&](size_t off) {
         const unsigned long long *q = (const unsigned long long *)(o + (off - ob));
         return std::vector<unsigned long long>(q, q + n);
@@ -962,20 +996,35 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
     const unsigned long long mask48 = 0xFFFFFFFFFFFFull;
     const unsigned long long t0 = p->h_glob.t0;
     bool all_proven = true;
-    for (int i = 0; i < n; i++) {
-        mcs_result &r = res[i];
-        int size = p->h_inc[p->inst[i].inc_slot];
-        bool proven = p->h_tproof[i] != 0 && p->h_open[i] == 0;
+    for (int k = 0; k < p->pairs; k++) {
+        mcs_result &r = res[k];
+        const int i0 = p->dev(k), i1 = p->portfolio ? i0 + 1 : i0;
+        const int size = p->h_inc[p->inst[i0].inc_slot];
+        // a pair is proven once either of its searches finished (a portfolio
+        // twin that saw its partner finish ends at once, proving nothing new)
+        bool proven = false;
+        unsigned long long tp = ~0ull;
+        int64_t nodes = 0;
+        for (int i = i0; i <= i1; i++) {
+            if (p->h_tproof[i] != 0 && p->h_open[i] == 0 && !p->h_dead[i]) {
+                proven = true;
+                tp = std::min(tp, p->h_tproof[i]);
+            }
+            nodes += (int64_t)p->h_nodes[i];
+        }
         all_proven = all_proven && proven;
         r.size = size;
         r.optimal = proven ? 1 : 0;
-        r.nodes = (int64_t)p->h_nodes[i];
-        unsigned long long kb = p->h_tbest[i];
-        r.t_best_s = kb ? (double)(((kb & mask48) - (t0 & mask48)) & mask48) / p->tick_hz : 0.0;
-        r.t_proof_s = proven ? (double)(p->h_tproof[i] - t0) / p->tick_hz : 0.0;
-        // the mapping of the final size sits in the slots of the instance
-        // that raised the incumbent to it (a portfolio twin may not have)
-        if (size > p->inst[i].lb && size > 0 && (int)(kb >> 48) == size) {
+        r.nodes = nodes;
+        r.t_proof_s = proven ? (double)(tp - t0) / p->tick_hz : 0.0;
+        r.t_best_s = 0.0;
+        // the mapping of the final size sits in the slots of the search that
+        // raised the incumbent to it (exactly one twin of a portfolio pair)
+        for (int i = i0; i <= i1; i++) {
+            const unsigned long long kb = p->h_tbest[i];
+            if (!(size > p->inst[i].lb && size > 0 && (int)(kb >> 48) == size))
+                continue;
+            r.t_best_s = (double)(((kb & mask48) - (t0 & mask48)) & mask48) / p->tick_hz;
             size_t off = p->inst[i].map_off + (size_t)size * (size - 1) / 2;
             for (int j = 0; j < size; j++) {
                 uint16_t e = p->h_maps[off + j];
@@ -985,6 +1034,7 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
                 if (r.map_h)
                     r.map_h[j] = p->ordH[i][ph];
             }
+            break;
         }
     }
     return all_proven ? MCS_OK : MCS_LIMIT;
@@ -1029,19 +1079,18 @@ mcs_status mcs_plan_stats(const mcs_plan *p, mcs_stats *st) {
     return MCS_OK;
 }
 
-mcs_status mcs_plan_set_goals(mcs_plan *p, const int32_t *goal, void *stream) {
-    g_err.clear();
-    if (!p || !goal)
-        return fail(MCS_E_INVALID, "NULL argument");
-    if (!p->uploaded)
-        return fail(MCS_E_WORKSPACE, "mcs_plan_upload has not been called");
+// Per pair: the incumbent the next run starts from (lb), the size at which
+// it stops (target, 0: none), whether the dead-end forecast may give it up,
+// and whether it is skipped; copied into the device descriptors.
+static mcs_status apply_bounds(mcs_plan *p, const int32_t *lb, const int32_t *target,
+                               const int32_t *dead_on, const int32_t *skip, void *stream) {
     for (int i = 0; i < p->count; i++) {
+        const int k = p->portfolio ? i >> 1 : i;
         mcs::DevInst &di = p->inst[i];
-        if (goal[i] > p->m[i])
-            return fail(MCS_E_INVALID, "a goal exceeds min(nG, nH)");
-        di.K0 = (uint8_t)(goal[i] < 0 ? 0 : p->K0[i]);
-        di.lb = goal[i] > 0 ? goal[i] - 1 : 0;
-        di.target = goal[i] > 0 ? goal[i] : 0;
+        di.K0 = (uint8_t)(skip[k] ? 0 : p->K0[i]);
+        di.lb = lb[k];
+        di.target = target[k];
+        di.dead_on = dead_on[k];
     }
     if (p->pin)
         stage_inputs(p);  // a graph replay copies the descriptors in from here
@@ -1051,27 +1100,59 @@ mcs_status mcs_plan_set_goals(mcs_plan *p, const int32_t *goal, void *stream) {
     return MCS_OK;
 }
 
+mcs_status mcs_plan_set_goals(mcs_plan *p, const int32_t *goal, void *stream) {
+    g_err.clear();
+    if (!p || !goal)
+        return fail(MCS_E_INVALID, "NULL argument");
+    if (!p->uploaded)
+        return fail(MCS_E_WORKSPACE, "mcs_plan_upload has not been called");
+    const int n = p->pairs;
+    std::vector<int32_t> lb(n), target(n), don(n), skip(n);
+    for (int k = 0; k < n; k++) {
+        if (goal[k] > p->m[p->dev(k)])
+            return fail(MCS_E_INVALID, "a goal exceeds min(nG, nH)");
+        lb[k] = goal[k] > 0 ? goal[k] - 1 : 0;
+        target[k] = goal[k] > 0 ? goal[k] : 0;
+        don[k] = goal[k] == 0 && p->dead_abs > 0 ? 1 : 0;
+        skip[k] = goal[k] < 0 ? 1 : 0;
+    }
+    return apply_bounds(p, lb.data(), target.data(), don.data(), skip.data(), stream);
+}
+
 mcs_status mcs_plan_root_bounds(const mcs_plan *p, int32_t *bounds) {
     if (!p || !bounds)
         return fail(MCS_E_INVALID, "NULL argument");
-    for (int i = 0; i < p->count; i++)
-        bounds[i] = p->root_bound[i];
+    for (int k = 0; k < p->pairs; k++)
+        bounds[k] = p->root_bound[p->dev(k)];
     return MCS_OK;
 }
 
 void mcs_plan_destroy(mcs_plan *p) { delete p; }
 
-// Goal-directed search over a batch (paper Sec. IV.A): each launch asks, per
-// open instance, "is there a common induced subgraph of at least `goal`
-// vertices?" (incumbent goal - 1, stop at the first mapping found).
-//   strategy 0 (top-down): goals root bound, root bound - 1, ... until one is
-//     reached; the first goal reached is the optimum.
-//   strategy 1 (bound correction): a plain run bounded by opts->node_limit
-//     gives a lower bound lo (and may already finish); then binary search on
-//     the goal in (lo, root bound], each refuted goal lowering the upper bound.
+// Goal-directed search over a batch (paper Sec. IV.A).  Every pair keeps a
+// lower bound lo (the best mapping found, kept) and an upper bound hi (Eq. 1
+// at the root, lowered by every refuted goal); it is settled once lo == hi.
+// Each launch runs every unsettled pair in one of two kinds of run:
+//   goal run g: incumbent g - 1, stop at the first mapping of size >= g;
+//     a mapping raises lo, a finished search without one sets hi = g - 1;
+//   plain run from s: incumbent s, no stop, the dead-end forecast on (for
+//     the dead-end strategies); a finished search settles the pair (its best
+//     mapping if it found one above s, else hi = s).
+// strategy 0 (top-down): goal runs at hi, hi - 1, ...: the first goal
+//   reached is the optimum.
+// strategy 1 (bound correction by bisection): a plain run bounded by
+//   opts->node_limit gives lo (and may finish); then goal runs at the middle
+//   of (lo, hi].
+// strategies 2 and 3 (dead-end bound correction): plain runs with the
+//   dead-end forecast; a pair forecast to be in a dead end (too many nodes
+//   since its incumbent last rose) restarts from s = lo + step -- the bound
+//   raised by 1 (strategy 2) or by a step that doubles at each forecast,
+//   1, 2, 4, ... (strategy 3) -- so only mappings above s are looked for; a
+//   raised bound found unreachable (a finished run with nothing above s)
+//   sets hi = s and the rest is goal runs at the middle of (lo, hi].  Goal
+//   runs never use the forecast, so every pair settles.
 // Every launch gets the full opts time limit; the node limit applies to the
-// first run of strategy 1 only.  Instances whose answer is settled are
-// skipped by later launches.
+// first run of strategy 1 only.
 mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H,
                            const mcs_opts *opts, int32_t strategy, void *workspace,
                            size_t bytes, void *stream, mcs_result *results,
@@ -1080,13 +1161,20 @@ mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H
         return fail(MCS_E_INVALID, "results is NULL");
     for (int i = 0; i < count; i++)
         results[i].size = -1;
-    if (strategy != 0 && strategy != 1)
-        return fail(MCS_E_INVALID, "strategy must be 0 (top-down) or 1 (bound correction)");
+    if (strategy < 0 || strategy > 3)
+        return fail(MCS_E_INVALID, "strategy must be 0 (top-down), 1 (bisection), 2 (dead-end, "
+                                   "+1) or 3 (dead-end, doubling step)");
+    const bool dead_strat = strategy >= 2;
     mcs_opts o1 = opts ? *opts : mcs_opts{};
+    if (dead_strat && o1.deadend_nodes <= 0)
+        return fail(MCS_E_INVALID, "strategies 2 and 3 need opts->deadend_nodes > 0");
     mcs_opts og = o1;
-    og.node_limit = 0;
+    if (strategy != 1)
+        og.node_limit = 0;
+    if (!dead_strat)
+        og.deadend_nodes = 0, og.deadend_ratio = 0;
     mcs_plan *p = nullptr;
-    mcs_status st = mcs_plan_create(count, G, H, strategy == 1 ? &o1 : &og, &p);
+    mcs_status st = mcs_plan_create(count, G, H, &og, &p);
     if (st != MCS_OK)
         return st;
     struct PlanGuard {
@@ -1097,76 +1185,58 @@ mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H
     if (st != MCS_OK)
         return st;
     const int n = count;
-    std::vector<int> lo(n, 0), hi(p->root_bound), goal(n, 0), done(n, 0);
+    // kind: 0 settled, 1 plain run from start[i], 2 goal run at goal[i]
+    std::vector<int> lo(n, 0), hi(n, 0), kind(n, 1), start(n, 0), goal(n, 0), step(n, 1);
+    (void)mcs_plan_root_bounds(p, hi.data());
     std::vector<std::vector<int32_t>> mg(n), mh(n);
     std::vector<int64_t> nodes(n, 0);
     std::vector<double> tbest(n, 0.0), tproof(n, 0.0);
     std::vector<mcs_result> r(n);
     std::vector<std::vector<int32_t>> bg(n), bh(n);
     for (int i = 0; i < n; i++) {
-        bg[i].assign(std::max(1, p->m[i]), 0);
-        bh[i].assign(std::max(1, p->m[i]), 0);
+        bg[i].assign(std::max(1, p->m[p->dev(i)]), 0);
+        bh[i].assign(std::max(1, p->m[p->dev(i)]), 0);
         r[i] = mcs_result{};
         r[i].map_g = bg[i].data();
         r[i].map_h = bh[i].data();
+        if (strategy == 0)
+            kind[i] = 2;
     }
     double elapsed = 0.0;
     int runs = 0;
     bool limited = false;
-    for (int i = 0; i < n; i++)
-        done[i] = lo[i] >= hi[i];  // e.g. an empty graph: root bound 0
     auto keep_map = [&](int i) {
         mg[i].assign(bg[i].begin(), bg[i].begin() + r[i].size);
         mh[i].assign(bh[i].begin(), bh[i].begin() + r[i].size);
     };
-    auto launch = [&](void) -> mcs_status {
-        mcs_status s1 = mcs_plan_set_goals(p, goal.data(), stream);
-        if (s1 == MCS_OK)
-            s1 = mcs_plan_run(p, stream);
-        if (s1 == MCS_OK)
-            s1 = mcs_plan_results(p, r.data(), stream);
-        if (s1 < 0)
-            return s1;
-        runs++;
-        elapsed += p->last_ms / 1000.0;
-        for (int i = 0; i < n; i++)
-            if (goal[i] >= 0) {
-                nodes[i] += r[i].nodes;
-                if (r[i].size > p->inst[i].lb)
-                    tbest[i] = elapsed - p->last_ms / 1000.0 + r[i].t_best_s;
-            }
-        return MCS_OK;
+    auto settle = [&](int i) {
+        kind[i] = 0;
+        tproof[i] = elapsed;
     };
-    if (strategy == 1) {
-        // first run: plain search under the node limit
-        for (int i = 0; i < n; i++)
-            goal[i] = 0;
-        st = launch();
-        if (st < 0)
-            return st;
-        for (int i = 0; i < n; i++) {
-            lo[i] = r[i].size;
-            keep_map(i);
-            if (r[i].optimal)
-                hi[i] = lo[i];  // the plain run finished: lo is the optimum
-            if (lo[i] >= hi[i]) {
-                done[i] = 1;
-                tproof[i] = elapsed;
-            }
+    auto bisect_next = [&](int i) {
+        if (lo[i] >= hi[i]) {
+            settle(i);
+            return;
         }
-        p->sp.node_limit = 0;
-    }
+        kind[i] = 2;
+        goal[i] = strategy == 0 ? hi[i] : (lo[i] + 1 + hi[i] + 1) / 2;
+        if (goal[i] <= lo[i])
+            goal[i] = lo[i] + 1;
+    };
+    for (int i = 0; i < n; i++)
+        if (lo[i] >= hi[i])
+            settle(i);  // e.g. an empty graph: root bound 0
+        else if (kind[i] == 2)
+            bisect_next(i);
+    std::vector<int32_t> lb(n), target(n), don(n), skip(n);
     for (;;) {
         bool any = false;
         for (int i = 0; i < n; i++) {
-            if (done[i]) {
-                goal[i] = -1;
-                continue;
-            }
-            any = true;
-            goal[i] = strategy == 0 ? hi[i] : (lo[i] + 1 + hi[i] + 1) / 2;
-            if (goal[i] <= lo[i])
-                goal[i] = lo[i] + 1;
+            skip[i] = kind[i] == 0;
+            lb[i] = kind[i] == 1 ? start[i] : kind[i] == 2 ? goal[i] - 1 : 0;
+            target[i] = kind[i] == 2 ? goal[i] : 0;
+            don[i] = kind[i] == 1 && dead_strat ? 1 : 0;
+            any = any || kind[i] != 0;
         }
         if (!any)
             break;
@@ -1174,29 +1244,69 @@ mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H
             limited = true;
             break;
         }
-        st = launch();
+        st = apply_bounds(p, lb.data(), target.data(), don.data(), skip.data(), stream);
+        if (st == MCS_OK)
+            st = mcs_plan_run(p, stream);
+        if (st == MCS_OK)
+            st = mcs_plan_results(p, r.data(), stream);
         if (st < 0)
             return st;
+        runs++;
+        elapsed += p->last_ms / 1000.0;
+        const bool stopped = p->h_glob.stop != 0;  // a time or node limit hit
         for (int i = 0; i < n; i++) {
-            if (goal[i] < 0)
+            if (kind[i] == 0)
                 continue;
-            if (r[i].size >= goal[i]) {  // reached: a mapping of at least goal
-                lo[i] = r[i].size;
-                keep_map(i);
-            } else if (r[i].optimal) {  // refuted: nothing of size >= goal
-                hi[i] = goal[i] - 1;
-            } else {
-                limited = true;  // this launch hit the time limit
-                done[i] = 1;
-                continue;
+            nodes[i] += r[i].nodes;
+            const bool found = r[i].size > lb[i];
+            if (found) {
+                tbest[i] = elapsed - p->last_ms / 1000.0 + r[i].t_best_s;
+                if (r[i].size > lo[i]) {
+                    lo[i] = r[i].size;
+                    keep_map(i);
+                }
             }
-            if (strategy == 0 && lo[i] == goal[i])
-                hi[i] = lo[i];
-            if (lo[i] >= hi[i]) {
-                done[i] = 1;
-                tproof[i] = elapsed;
+            if (kind[i] == 2) {
+                if (found) {
+                    // reached: a mapping of at least the goal
+                    if (strategy == 0)
+                        hi[i] = lo[i];
+                } else if (r[i].optimal) {
+                    hi[i] = goal[i] - 1;  // refuted: nothing of size >= goal
+                } else {
+                    limited = true;  // this launch hit the time limit
+                    kind[i] = 0;
+                    continue;
+                }
+                bisect_next(i);
+            } else if (r[i].optimal) {
+                // a plain run finished: its best above start is the optimum,
+                // and nothing above start means the raised bound is unreachable
+                if (found)
+                    hi[i] = lo[i];
+                else
+                    hi[i] = std::min(hi[i], start[i]);
+                bisect_next(i);
+            } else if (dead_strat && !stopped) {
+                // forecast as a dead end: raise the bound above the best so far
+                const int s = lo[i] + step[i];
+                if (strategy == 3)
+                    step[i] *= 2;
+                if (std::min(s, hi[i] - 1) <= lo[i]) {
+                    bisect_next(i);  // no room left to raise it: settle by goals
+                } else {
+                    start[i] = std::min(s, hi[i] - 1);
+                }
+            } else if (strategy == 1 && runs == 1 && stopped) {
+                // the node-limited first run of strategy 1: bisect from lo
+                bisect_next(i);
+            } else {
+                limited = true;
+                kind[i] = 0;
             }
         }
+        if (strategy == 1 && runs == 1)
+            p->sp.node_limit = 0;
     }
     for (int i = 0; i < n; i++) {
         mcs_result &o = results[i];

@@ -17,7 +17,7 @@ struct DevInst {
                        // index, or its portfolio twin's: twins share one)
     int32_t twin;      // the same pair entered under another vertex order, or -1;
                        // once either twin's search is finished the other stops
-    int32_t pad2;
+    int32_t dead_on;   // 1: this run may give the instance up as a dead end
 };
 
 // The node queue is sharded into one ring per XCD (workgroup i runs on XCD
@@ -83,6 +83,9 @@ struct SearchParams {
     unsigned long long *nodes;    // [count]
     unsigned long long *t_best;   // [count] (size << 48) | (realtime & 2^48-1)
     unsigned long long *t_proof;  // [count] realtime ticks when open reached 0
+    unsigned long long *best_nodes;  // [count] the instance's node count when its
+                                     // incumbent was last raised
+    int *dead;                    // [count] 1: given up as a dead end
     uint16_t *maps;               // per instance, per size s: s pairs (g | h << 8)
     DevGlobals *g;
     unsigned long long *seq;      // [kRings][ring_slots] queue slot sequence numbers
@@ -106,6 +109,11 @@ struct SearchParams {
     int policy_levels;       // LDS partner-order lists per wavefront (0 without policy)
     unsigned long long limit_ticks;  // time limit in realtime ticks
     long long node_limit;            // 0: none
+    long long dead_abs;              // dead-end forecast (instances with dead_on): more
+                                     // than this many nodes since the last improvement
+                                     // (0: never)
+    long long dead_rel;              // ... and more than this many times the nodes that
+                                     // led to the last improvement (0: absolute only)
     uint8_t *hstack;                 // (128-bit rows) [waves][hstack_stride] class stacks
     long long hstack_stride;         // bytes per wavefront: (cap_classes + 1) (L, R) pairs
     int seg_log;                     // segmented kernel: 2^seg_log lanes per search (0: one
@@ -122,6 +130,8 @@ struct ResetParams {
     unsigned long long *nodes;
     unsigned long long *t_best;
     unsigned long long *t_proof;
+    unsigned long long *best_nodes;
+    int *dead;
     DevGlobals *g;
     unsigned long long *seq;
     int count;

@@ -69,6 +69,7 @@ struct Searcher {
     uint8_t *sord;  // [policy levels][64]: partner order of policy-ordered frames
     int inst, map_off, nG, nH, target;
     int inc_slot, twin;  // shared incumbent word; portfolio twin (or -1)
+    int dead_on;         // the instance may be given up as a dead end
     // top frame, wave-uniform
     int t, base, K, d, v, sel, bound, flags, lsel, rsel;
     W rrem;
@@ -119,6 +120,7 @@ struct Searcher {
         target = 0;
         inc_slot = 0;
         twin = -1;
+        dead_on = 0;
         stop = false;
         roots_left = true;
         my_ring = (int)(blockIdx.x & (kRings - 1));
@@ -466,12 +468,16 @@ struct Searcher {
             target = (int)P.inst[i].target;
             inc_slot = (int)P.inst[i].inc_slot;
             twin = (int)P.inst[i].twin;
+            dead_on = (int)P.inst[i].dead_on;
         }
         int g = 0;
         if (lane == 0) {
             g = ld_rlx(&P.inc[inc_slot]);
             // the twin's search already finished: nothing is left to prove
-            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0)
+            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0 && !ld_rlx(&P.dead[twin]))
+                g = 255;
+            // given up as a dead end
+            if (dead_on && ld_rlx(&P.dead[i]))
                 g = 255;
         }
         inc = cap_inc(rl(g, 0));
@@ -541,9 +547,13 @@ struct Searcher {
                 for (int j = lane; j < size; j += 64)
                     dst[j] = smap[j];
             }
-            if (lane == 0)
+            if (lane == 0) {
                 a_max64(&P.t_best[inst], ((unsigned long long)size << 48) |
                                              (now_ticks() & 0xFFFFFFFFFFFFull));
+                // the nodes that led to this improvement (dead-end forecast)
+                a_max64(&P.best_nodes[inst],
+                        ld_rlx(&P.nodes[inst]) + pend_nodes + c_nodes);
+            }
         }
         set_inc(old > size ? old : size);
     }
@@ -1273,7 +1283,9 @@ struct Searcher {
         unsigned fl = 0;
         if (lane == 0) {
             gi = ld_rlx(&P.inc[inc_slot]);
-            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0)
+            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0 && !ld_rlx(&P.dead[twin]))
+                gi = 255;
+            if (dead_on && ld_rlx(&P.dead[inst]))
                 gi = 255;
             fl = ld_rlx(&P.g->xcd[my_ring].flag);
             if (may_donate) {
@@ -1295,8 +1307,28 @@ struct Searcher {
             stop = true;
             return;
         }
-        if (P.node_limit > 0)
+        if (P.node_limit > 0 || P.dead_abs > 0)
             flush_nodes();
+        if (P.dead_abs > 0 && dead_on) {
+            // dead-end forecast (paper Sec. IV.A): more than dead_abs nodes
+            // -- and, with dead_rel, more than dead_rel times the nodes that
+            // led to the last improvement -- without raising the incumbent
+            int gave_up = 0;
+            if (lane == 0) {
+                const unsigned long long n = ld_rlx(&P.nodes[inst]);
+                const unsigned long long b = ld_rlx(&P.best_nodes[inst]);
+                const unsigned long long since = n > b ? n - b : 0ull;
+                unsigned long long thr = (unsigned long long)P.dead_abs;
+                if (P.dead_rel > 0 && (unsigned long long)P.dead_rel * b > thr)
+                    thr = (unsigned long long)P.dead_rel * b;
+                if (since > thr) {
+                    st_rlx(&P.dead[inst], 1);
+                    gave_up = 1;
+                }
+            }
+            if (rl(gave_up, 0))
+                set_inc(255);
+        }
         if (may_donate) {
             // keep at least donate_low records waiting in this XCD's ring
             long long waiting = (long long)(rl_ull(tl, 0) - rl_ull(hd, 0));
@@ -1443,6 +1475,8 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
         R.nodes[i] = 0;
         R.t_best[i] = 0;
         R.t_proof[i] = 0;
+        R.best_nodes[i] = 0;
+        R.dead[i] = 0;
     }
     for (int i = tid; i < kRings * R.ring_slots; i += stride)
         R.seq[i] = (unsigned long long)(i % R.ring_slots);

@@ -81,6 +81,7 @@ struct SegSearch {
     int inst;         // instance of the segment's unit, -1: no unit
     int adj_inst;     // instance whose rows are in the segment's LDS
     int inc_slot, twin, map_off, target;
+    int dead_on;      // the instance may be given up as a dead end
     int t, base, K, d, v, sel, bound, flags, lsel, rsel, inc, d0;
     W rrem;
     W cL, cR;         // this lane's class of the top frame (class lk)
@@ -125,6 +126,7 @@ struct SegSearch {
         twin = -1;
         map_off = 0;
         target = 0;
+        dead_on = 0;
         t = -1;
         base = K = d = v = sel = bound = flags = lsel = rsel = inc = d0 = 0;
         rrem = cL = cR = 0;
@@ -315,9 +317,13 @@ struct SegSearch {
             uint16_t *dst = P.maps + map_off + size * (size - 1) / 2;
             for (int j = lk; j < size; j += S)
                 dst[j] = smap[j];
-            if (lk == 0)
+            if (lk == 0) {
                 a_max64(&P.t_best[inst], ((unsigned long long)size << 48) |
                                              (now_ticks() & 0xFFFFFFFFFFFFull));
+                // the nodes that led to this improvement (for the dead-end
+                // forecast)
+                a_max64(&P.best_nodes[inst], ld_rlx(&P.nodes[inst]) + nodes_pend);
+            }
         }
         set_inc(old > size ? old : size);
     }
@@ -717,11 +723,14 @@ struct SegSearch {
         const DevInst di = P.inst[i];
         const int slot = sc((int)di.inc_slot);
         const int tw = sc((int)di.twin);
+        const int don = sc((int)di.dead_on);
         int g = 0;
         if (lane == 0) {
             g = ld_rlx(&P.inc[slot]);
-            if (tw >= 0 && ld_rlx(&P.open[tw]) == 0)
+            if (tw >= 0 && ld_rlx(&P.open[tw]) == 0 && !ld_rlx(&P.dead[tw]))
                 g = 255;  // the twin's search already finished
+            if (don && ld_rlx(&P.dead[i]))
+                g = 255;  // given up as a dead end
         }
         g = rl(g, 0);
         if (seg == j) {
@@ -729,6 +738,7 @@ struct SegSearch {
             inst = i;
             inc_slot = slot;
             twin = tw;
+            dead_on = don;
             map_off = sc((int)di.map_off);
             target = sc((int)di.target);
             inc = 0;
@@ -944,6 +954,27 @@ struct SegSearch {
         }
     }
 
+    // Dead-end forecast (paper Sec. IV.A): an instance whose search has gone
+    // more than dead_abs nodes -- and, if dead_rel is set, more than dead_rel
+    // times the nodes that led to its last improvement -- without raising
+    // its incumbent is given up: every search on it prunes from then on, and
+    // the host steps the bound.
+    __device__ void forecast_dead_ends() {
+        if (inst >= 0 && dead_on && lk == 0) {
+            const unsigned long long n = ld_rlx(&P.nodes[inst]);
+            const unsigned long long b = ld_rlx(&P.best_nodes[inst]);
+            const unsigned long long since = n > b ? n - b : 0ull;
+            unsigned long long thr = (unsigned long long)P.dead_abs;
+            if (P.dead_rel > 0 && (unsigned long long)P.dead_rel * b > thr)
+                thr = (unsigned long long)P.dead_rel * b;
+            if (since > thr) {
+                st_rlx(&P.dead[inst], 1);
+                inc = 255;
+            }
+        }
+        inc = sfirst(inc);
+    }
+
     // Periodic: refresh incumbents, honour limits, keep the queue stocked.
     __device__ void check() {
         since_check = 0;
@@ -959,7 +990,9 @@ struct SegSearch {
         }
         if (inst >= 0) {
             int g = ld_rlx(&P.inc[inc_slot]);
-            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0)
+            if (twin >= 0 && ld_rlx(&P.open[twin]) == 0 && !ld_rlx(&P.dead[twin]))
+                g = 255;
+            if (dead_on && ld_rlx(&P.dead[inst]))
                 g = 255;
             set_inc(g);
         }
@@ -973,8 +1006,10 @@ struct SegSearch {
             return;
         }
         // (counts are also flushed before a 32-bit per-unit count could wrap)
-        if (P.node_limit > 0 || ballot(nodes_pend > (1u << 30)))
+        if (P.node_limit > 0 || P.dead_abs > 0 || ballot(nodes_pend > (1u << 30)))
             flush_nodes();
+        if (P.dead_abs > 0)
+            forecast_dead_ends();
         if (may_donate) {
             const long long waiting = (long long)(rl_ull(tl, 0) - rl_ull(hd, 0));
             if (waiting < P.donate_low) {

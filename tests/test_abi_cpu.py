@@ -227,19 +227,47 @@ def test_root_bounds_host(mcs_lib):
 
 
 def test_ordering_option_validated(mcs_lib):
-    """mcs_opts.ordering takes 0 (degree) or 1 (block-triangular); anything
-    else is rejected before any device work."""
+    """mcs_opts.ordering takes 0 (degree), 1 (block-triangular) or 2 (both,
+    as a portfolio: two search instances per pair, so a larger workspace);
+    anything else is rejected before any device work."""
+    from paper_1908_06418_amd import _Marshal, _abi, _opts
+    m = _Marshal([(mi.er_graph(10, 0.3, 1), mi.er_graph(10, 0.3, 2))] * 3)
+    h = ctypes.c_void_p()
+    sizes = {}
+    for ordering, status in ((0, _abi.MCS_OK), (1, _abi.MCS_OK), (2, _abi.MCS_OK),
+                             (3, _abi.MCS_E_INVALID), (-1, _abi.MCS_E_INVALID)):
+        o, _t = _opts(0, 0.0, None)
+        o.ordering = ordering
+        st = mcs_lib.mcs_plan_create(3, m.G, m.H, ctypes.byref(o), ctypes.byref(h))
+        assert st == status, (ordering, st)
+        if st == _abi.MCS_OK:
+            sizes[ordering] = mcs_lib.mcs_plan_workspace_size(h)
+            mcs_lib.mcs_plan_destroy(h)
+    assert sizes[0] == sizes[1] < sizes[2]
+
+
+def test_deadend_and_goal_options_validated(mcs_lib):
+    """Negative dead-end thresholds are rejected; goal strategies 2 and 3
+    need deadend_nodes > 0; strategies outside 0..3 are rejected (all before
+    any device work, with every result size set to -1)."""
     from paper_1908_06418_amd import _Marshal, _abi, _opts
     m = _Marshal([(mi.er_graph(10, 0.3, 1), mi.er_graph(10, 0.3, 2))])
     h = ctypes.c_void_p()
-    for ordering, status in ((0, _abi.MCS_OK), (1, _abi.MCS_OK), (2, _abi.MCS_E_INVALID),
-                             (-1, _abi.MCS_E_INVALID)):
-        o, _t = _opts(0, 0.0, None)
-        o.ordering = ordering
+    for nodes, ratio, status in ((0, 0, _abi.MCS_OK), (100, 2, _abi.MCS_OK),
+                                 (-1, 0, _abi.MCS_E_INVALID), (100, -2, _abi.MCS_E_INVALID)):
+        o, _t = _opts(0, 0.0, None, deadend_nodes=nodes, deadend_ratio=ratio)
         st = mcs_lib.mcs_plan_create(1, m.G, m.H, ctypes.byref(o), ctypes.byref(h))
-        assert st == status, (ordering, st)
+        assert st == status, (nodes, ratio, st)
         if st == _abi.MCS_OK:
             mcs_lib.mcs_plan_destroy(h)
+    res = (_abi.mcs_result * 1)()
+    for strategy, nodes in ((2, 0), (3, 0), (4, 100), (-1, 100)):
+        o, _t = _opts(0, 0.0, None, deadend_nodes=nodes)
+        res[0].size = 7
+        st = mcs_lib.mcs_solve_goals(1, m.G, m.H, ctypes.byref(o), strategy, None, 0, None, res,
+                                     None)
+        assert st == _abi.MCS_E_INVALID, (strategy, st)
+        assert res[0].size == -1
 
 
 def test_root_bounds_host_beyond_64(mcs_lib):

@@ -29,18 +29,50 @@ def _pairs():
     return pairs
 
 
-@pytest.mark.parametrize("strategy", ["top-down", "bisect"])
-def test_goal_search_matches_oracle(gpu, strategy):
+@pytest.mark.parametrize("strategy,ratio", [("top-down", 0), ("bisect", 0), ("dead-end+1", 0),
+                                            ("dead-end*2", 0), ("dead-end+1", 2),
+                                            ("dead-end*2", 4)])
+def test_goal_search_matches_oracle(gpu, strategy, ratio):
     from paper_1908_06418_amd import solve_goals
     pairs = _pairs()
     want = [oracle.mcs(G, H)["size"] for G, H in pairs]
-    _say(f"goal search {strategy}: {len(pairs)} pairs")
+    _say(f"goal search {strategy} ratio {ratio}: {len(pairs)} pairs")
     res, launches = solve_goals(pairs, strategy=strategy, node_limit=20000, time_limit_s=60,
-                                with_launches=True)
+                                with_launches=True, deadend_nodes=2000, deadend_ratio=ratio)
     for (G, H), r, w in zip(pairs, res, want):
         assert r.optimal and r.size == w
         assert len(r.mapping) == r.size and oracle.check.is_valid(G, H, r.mapping)
     assert launches >= 1
+
+
+def test_dead_end_forecast_gives_valid_partial_results(gpu):
+    """A plain batch with the dead-end forecast and a tiny threshold: pairs
+    given up are reported unproven (MCS_LIMIT) with a valid mapping no
+    larger than the optimum; pairs that finish first are exact."""
+    from paper_1908_06418_amd import solve_batch
+    pairs = _pairs()
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    for tun in ({}, {"seg_lanes": 64}):
+        res = solve_batch(pairs, time_limit_s=60, deadend_nodes=50, tuning=tun)
+        assert any(not r.optimal for r in res)
+        for (G, H), r, w in zip(pairs, res, want):
+            assert r.size <= w
+            assert r.size == len(r.mapping) and oracle.check.is_valid(G, H, r.mapping)
+            if r.optimal:
+                assert r.size == w
+
+
+def test_dead_end_portfolio_and_graph(gpu):
+    """The dead-end strategies with the two-order portfolio and with the
+    HIP graph: a twin given up must not stop its partner."""
+    from paper_1908_06418_amd import solve_goals
+    pairs = _pairs()
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    for kw in ({"ordering": "portfolio"}, {"tuning": {"use_graph": 1}}):
+        res = solve_goals(pairs, strategy="dead-end*2", time_limit_s=60, deadend_nodes=500,
+                          **kw)
+        assert [r.size for r in res] == want, kw
+        assert all(r.optimal for r in res)
 
 
 def test_bisect_through_graph_drops_node_limit(gpu):
@@ -102,11 +134,12 @@ def test_goal_search_report(gpu):
         plain = solve_batch(pairs, time_limit_s=60)
         row["plain_s"] = time.perf_counter() - t
         row["plain_proven"] = sum(r.optimal for r in plain)
-        for strat in ("top-down", "bisect"):
+        for strat in ("top-down", "bisect", "dead-end+1", "dead-end*2"):
             t = time.perf_counter()
             _say(f"report n={n}: {strat}")
             res, launches = solve_goals(pairs, strategy=strat, node_limit=200000,
-                                        time_limit_s=60, with_launches=True)
+                                        time_limit_s=60, with_launches=True,
+                                        deadend_nodes=200000, deadend_ratio=2)
             row[f"{strat}_s"] = time.perf_counter() - t
             row[f"{strat}_launches"] = launches
             row[f"{strat}_proven"] = sum(r.optimal for r in res)

@@ -1,0 +1,122 @@
+"""GPU tests of the two-order portfolio (paper Sec. IV: the portfolio of
+search variants, here with the shared incumbent the paper leaves for later):
+every pair is searched twice in one launch, under descending-degree order
+and under the block-triangular order, and the two searches share one
+incumbent word.  Sizes must equal the oracle's; the proof must come about
+as fast as the faster order's alone."""
+import json
+
+import numpy as np
+import pytest
+from _report import write_report
+
+import mcs_instances as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+# Pairs of the batched workload whose two orders differ most for the
+# oracle (nodes under degree order / nodes under block-triangular order,
+# sequential search): 408 8.2, 161 10.7, 209 17.1, 53 0.031, 64 0.048,
+# 129 0.075, 139 0.094.
+DIFFERING = (408, 161, 209, 53, 64, 129, 139)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _pairs(idx):
+    allp = mi.pairs_c4(max(idx) + 1)
+    return [allp[i] for i in idx]
+
+
+def test_portfolio_sizes_match_oracle(gpu):
+    """A batch of small pairs of every kind (labelled, directed) under the
+    portfolio: sizes equal the oracle's, mappings are valid, every pair is
+    proven, and nodes are the sum over both searches."""
+    from paper_1908_06418_amd import solve_batch
+    rng = np.random.default_rng(77)
+    pairs = []
+    for directed, nlab in [(False, 0), (True, 0), (False, 3), (True, 2)]:
+        for _ in range(6):
+            p = float(rng.uniform(0.1, 0.9))
+            pairs.append((mi.random_small(rng, int(rng.integers(0, 16)), p, directed, nlab),
+                          mi.random_small(rng, int(rng.integers(0, 16)), p, directed, nlab)))
+    pairs += _pairs(range(40))
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    res = solve_batch(pairs, time_limit_s=60, ordering="portfolio")
+    assert len(res) == len(pairs)
+    for (G, H), r, w in zip(pairs, res, want):
+        assert r.optimal and r.size == w, (r.size, w)
+        assert oracle.check.is_valid(G, H, r.mapping)
+        assert len(r.mapping) == r.size
+        assert r.nodes >= 1
+
+
+def test_portfolio_single_search_is_exact(gpu):
+    """One search at a time (the two twins still share the incumbent):
+    sizes exact."""
+    from paper_1908_06418_amd import solve_batch
+    pairs = _pairs(range(16))
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    res = solve_batch(pairs, time_limit_s=60, ordering="portfolio",
+                      tuning={"single_wave": 1})
+    assert [r.size for r in res] == want
+    assert all(r.optimal for r in res)
+
+
+def test_portfolio_goals_and_graph(gpu):
+    """The portfolio under goal-directed search and through the HIP graph."""
+    from paper_1908_06418_amd import Plan, solve_goals
+    pairs = _pairs(range(24))
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    for strategy in ("top-down", "bisect"):
+        res = solve_goals(pairs, strategy=strategy, time_limit_s=60, node_limit=20000,
+                          ordering="portfolio")
+        assert [r.size for r in res] == want, strategy
+        assert all(r.optimal for r in res)
+    plan = Plan(pairs, time_limit_s=60, tuning={"use_graph": 1}, ordering="portfolio").upload()
+    try:
+        for _ in range(3):
+            plan.run()
+            res = plan.results()
+            assert [r.size for r in res] == want
+    finally:
+        plan.close()
+
+
+def test_portfolio_proof_time_report(gpu):
+    """Each differing pair alone, under degree order, block-triangular
+    order and the portfolio: the portfolio's time to proof against the
+    faster single order's (median of 3 launches each).  The portfolio must
+    beat the slower order on every pair and stay within 1.5x of the faster
+    one (the twins split the GPU between them; the shared incumbent gives
+    part of that back)."""
+    from paper_1908_06418_amd import Plan
+    pairs = _pairs(DIFFERING)
+    want = [oracle.mcs(G, H)["size"] for G, H in pairs]
+    rows = []
+    for i, (pq, w) in enumerate(zip(pairs, want)):
+        row = {"pair": DIFFERING[i]}
+        for ordering in ("degree", "btf", "portfolio"):
+            plan = Plan([pq], time_limit_s=60, ordering=ordering).upload()
+            ts, nodes = [], 0
+            try:
+                for _ in range(3):
+                    plan.run()
+                    r = plan.results()[0]
+                    assert r.optimal and r.size == w
+                    ts.append(plan.stats().kernel_ms)
+                    nodes = r.nodes
+            finally:
+                plan.close()
+            row[ordering] = {"kernel_ms": sorted(ts)[1], "nodes": nodes}
+        fast = min(row["degree"]["kernel_ms"], row["btf"]["kernel_ms"])
+        slow = max(row["degree"]["kernel_ms"], row["btf"]["kernel_ms"])
+        row["portfolio_over_faster"] = row["portfolio"]["kernel_ms"] / fast
+        _say(json.dumps(row))
+        rows.append(row)
+        assert row["portfolio"]["kernel_ms"] < slow
+        assert row["portfolio"]["kernel_ms"] <= 1.5 * fast + 2.0
+    write_report("portfolio_proof_time.json", rows)
