@@ -167,12 +167,17 @@ def _scorer_pairs():
 
 def _python_nodes(pairs, k, sign, depth, mode):
     """Node counts of the plain Python recursion ordered by sign * feature k
-    of oracle.policy.features at nodes with |M| <= depth."""
+    of oracle.policy.features at nodes with |M| <= depth.  Every feature is a
+    count over n (or a 0/1 flag), so it is compared as the integer count:
+    a float64 sum of fractions can differ in the last place between equal
+    counts, which would break ties differently from the exact counts."""
     from _mcsplit_py import Counter, root
     out = []
     for G, H in pairs:
         def score(u, side, classes, sel, d, cand, G=G, H=H):
-            return sign * ref.features(G if side == 0 else H, u, side, classes, sel, d, cand)[k]
+            g = G if side == 0 else H
+            x = ref.features(g, u, side, classes, sel, d, cand)[k]
+            return sign * round(x * g["n"])
         c = Counter(G, H, 0, score=score, depth_max=depth, mode=mode)
         c.rec(root(G, H), 0)
         out.append(c.nodes)
