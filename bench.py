@@ -223,6 +223,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the kernels directly instead of replaying the HIP graph")
     ap.add_argument("--tuning", default="", help="JSON dict of mcs_tuning fields")
+    ap.add_argument("--ordering", default="degree", choices=("degree", "btf", "portfolio"),
+                    help="static vertex order (portfolio: both orders racing on one "
+                         "incumbent per pair)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (outside the timed region), "
                          "so HBM byte counters can be scaled against a known size")
@@ -259,7 +262,8 @@ def main():
     tuning = dict(tuning or {})
     if not args.no_graph:
         tuning["use_graph"] = 1
-    plan = Plan(pairs, time_limit_s=args.time_limit, tuning=tuning).upload()
+    plan = Plan(pairs, time_limit_s=args.time_limit, tuning=tuning,
+                ordering=args.ordering).upload()
     print(f"bench: {args.workload}, {len(pairs)} pairs, tuning {tuning} ({tuning_src})",
           file=sys.stderr, flush=True)
 
@@ -346,6 +350,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "pairs": len(pairs),
                    "word_bits": 8 * word, "directed": directed, "hip_graph": not args.no_graph,
+                   "ordering": args.ordering,
                    "tuning": tuning, "tuning_source": tuning_src},
         "instances_per_s": len(pairs) * K / elapsed,
         "exact": exact,

@@ -1,14 +1,17 @@
 """Autotuner for the search kernel's launch and scheduling knobs.
 
 The knobs (mcs_tuning in include/mcs.h) change only speed, never answers:
-resident wavefronts per CU, how many sibling children a wavefront evaluates at
-once, which nodes may be donated to the shared queue (the paper's PART_LEVEL
-idea), how often a busy wavefront looks at the queue, how many records each
-XCD's queue ring is kept stocked with, and the queue capacity.
+the search layout (searches of 8 or 16 lanes, or one per wavefront, and then
+how many sibling children a wavefront evaluates at once), resident
+wavefronts per CU, the LDS part of each search's class stack, the node
+queue's depth, how many records each XCD's queue ring is kept stocked with,
+and how often a busy search looks at the queue.
 The tuner times candidate settings on a sample of the workload through the C
 ABI, rejects any setting whose sizes differ from the others (they must agree:
 the search is exact), and caches the fastest per workload class in a JSON
-file ($MCS_TUNING_FILE, else ~/.cache/mcs_tuning.json).
+file ($MCS_TUNING_FILE, else ~/.cache/mcs_tuning.json).  tune() times a
+given list; tune_staged() walks the axes one at a time (coordinate descent:
+every value of one axis with the others at their best so far).
 """
 from __future__ import annotations
 
@@ -18,10 +21,23 @@ import os
 import time
 
 DEFAULT_CANDIDATES = [
-    {"waves_per_cu": w, "children_per_wave": 8, "check_interval": ci, "donate_low": lo}
-    for w in (8, 12, 16, 24)
-    for ci in (128, 256)
+    {"seg_lanes": sl, "waves_per_cu": w, "donate_low": lo}
+    for sl in (8, 16)
+    for w in (8, 12, 16)
     for lo in (1, 2)
+]
+
+# Axes of the staged search, in the order they are walked.  Zero is the
+# library's own choice.  children_per_wave applies to one search per
+# wavefront (seg_lanes 64) only.
+AXES = [
+    ("seg_lanes", (16, 8, 64)),
+    ("waves_per_cu", (0, 8, 12, 16, 20)),
+    ("children_per_wave", (8, 4, 2)),
+    ("stack_classes", (0, 1)),
+    ("ring_slots", (0, 4096, 32768)),
+    ("donate_low", (0, 1, 4)),
+    ("check_interval", (0, 64, 256)),
 ]
 
 
@@ -44,7 +60,7 @@ def workload_key(pairs) -> str:
                 e = sum(bin(r).count("1") for r in g["rows"])
                 dens.append(e / (n * (n - 1)))
     p = sum(dens) / len(dens) if dens else 0.0
-    bits = 32 if nmax <= 32 else 64
+    bits = 32 if nmax <= 32 else 64 if nmax <= 64 else 128
     nb = 8 * math.ceil(max(nmax, 1) / 8)
     batch = 1 << max(0, math.ceil(math.log2(len(pairs))))
     return (f"w{bits}-{'d' if directed else 'u'}{'l' if labelled else ''}-n{nb}"
@@ -82,26 +98,80 @@ def pick(measurements: list) -> dict:
     return min(ok, key=lambda m: m["kernel_ms"])
 
 
-def tune(pairs, candidates=None, time_limit_s: float = 30.0, reps: int = 1, log=None) -> dict:
-    """Time every candidate on pairs (GPU); returns the winning measurement
-    with the whole table under 'table'."""
+def measure(pairs, cand: dict, time_limit_s: float = 30.0, reps: int = 1) -> dict:
+    """Kernel time (best of reps launches) of one candidate on pairs."""
     from . import Plan
-    table = []
-    for cand in candidates or DEFAULT_CANDIDATES:
-        plan = Plan(pairs, time_limit_s=time_limit_s, tuning=cand).upload()
+    plan = Plan(pairs, time_limit_s=time_limit_s, tuning=cand).upload()
+    try:
         best_ms = None
         for _ in range(reps):
             plan.run()
             res = plan.results()
             st = plan.stats()
             best_ms = st.kernel_ms if best_ms is None else min(best_ms, st.kernel_ms)
-        m = {"tuning": cand, "kernel_ms": best_ms, "sizes": [r.size for r in res],
-             "proven": all(r.optimal for r in res), "nodes": st.nodes}
+    finally:
         plan.close()
+    return {"tuning": dict(cand), "kernel_ms": best_ms, "sizes": [r.size for r in res],
+            "proven": all(r.optimal for r in res), "nodes": st.nodes}
+
+
+def tune(pairs, candidates=None, time_limit_s: float = 30.0, reps: int = 1, log=None) -> dict:
+    """Time every candidate on pairs (GPU); returns the winning measurement
+    with the whole table under 'table'."""
+    table = []
+    for cand in candidates or DEFAULT_CANDIDATES:
+        m = measure(pairs, cand, time_limit_s, reps)
         table.append(m)
         if log:
             log(m)
     best = dict(pick(table))
+    best["table"] = table
+    return best
+
+
+def staged_candidates(best: dict, axis: str, values) -> list:
+    """The candidates of one stage: best with axis set to each value (values
+    that cannot apply to best's layout are left out)."""
+    out = []
+    for v in values:
+        if axis == "children_per_wave" and best.get("seg_lanes", 16) != 64:
+            continue
+        c = dict(best)
+        if v:
+            c[axis] = v
+        else:
+            c.pop(axis, None)
+        if c not in out:
+            out.append(c)
+    return out
+
+
+def tune_staged(pairs, axes=None, base=None, time_limit_s: float = 30.0, reps: int = 1,
+                log=None) -> dict:
+    """Coordinate descent over the axes: each stage times every value of one
+    axis with the others at the best found so far, and keeps the fastest
+    (sizes must agree across every candidate of every stage).  Returns the
+    winning measurement with every measurement under 'table'."""
+    best_t = dict(base or {})
+    table = []
+    seen = {}
+    best = None
+    for axis, values in axes or AXES:
+        stage = []
+        for cand in staged_candidates(best_t, axis, values):
+            key = json.dumps(cand, sort_keys=True)
+            if key not in seen:
+                seen[key] = measure(pairs, cand, time_limit_s, reps)
+                seen[key]["stage"] = axis
+                table.append(seen[key])
+                if log:
+                    log(seen[key])
+            stage.append(seen[key])
+        if stage:
+            best = pick(stage)
+            best_t = dict(best["tuning"])
+    pick(table)  # every candidate of every stage agrees on sizes
+    best = dict(best)
     best["table"] = table
     return best
 
@@ -120,10 +190,16 @@ def tuned(pairs, path: str | None = None) -> dict | None:
     return dict(entry["tuning"]) if entry else None
 
 
-def tune_and_store(pairs, sample=None, path: str | None = None, **kw) -> dict:
-    best = tune(sample or pairs, **kw)
+def tune_and_store(pairs, sample=None, path: str | None = None, staged: bool = False,
+                   note: str = "", **kw) -> dict:
+    """Tune on sample (default: pairs) and store the winner under pairs'
+    workload class."""
+    best = (tune_staged if staged else tune)(sample or pairs, **kw)
     data = load_cache(path)
-    data[workload_key(pairs)] = {"tuning": best["tuning"], "kernel_ms": best["kernel_ms"],
-                                 "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    entry = {"tuning": best["tuning"], "kernel_ms": best["kernel_ms"],
+             "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    if note:
+        entry["measured_on"] = note
+    data[workload_key(pairs)] = entry
     save_cache(data, path)
     return best

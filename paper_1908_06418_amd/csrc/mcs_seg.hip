@@ -98,6 +98,9 @@ struct SegSearch {
     unsigned long long t_start;
     unsigned long long n_steps, n_evals, n_nodes_wave, n_lanes, n_don, n_pops, n_busy, n_hbm,
         n_sleep, n_pushed, n_ncls;
+    // per-lane counts since the last check (at most check_interval steps, so
+    // 32 bits cannot wrap), folded into the totals above by fold_counts()
+    uint32_t c_evals, c_lanes, c_ncls;
     int max_used;
 
     __device__ SegSearch(const SearchParams &p, uint8_t *wave_lds, long long wave) : P(p) {
@@ -141,6 +144,7 @@ struct SegSearch {
         donor = 0;
         n_steps = n_evals = n_nodes_wave = n_lanes = n_don = n_pops = n_busy = n_hbm = 0;
         n_sleep = n_pushed = n_ncls = 0;
+        c_evals = c_lanes = c_ncls = 0;
         max_used = 0;
     }
 
@@ -525,23 +529,21 @@ struct SegSearch {
             if (need_unm)
                 unmatched();
         const bool need_eval = inst >= 0 && !fin && rrem != 0;
-        const uint64_t em = ballot(need_eval);
-        if (em) {
-            const int Kb = K;
+        if (ballot(need_eval)) {
+            // statistics, per lane (summed over the wavefront at the end):
+            // children evaluated, lanes holding one of their classes, and the
+            // classes they split
+            c_evals += need_eval && lk == 0 ? 1u : 0u;
+            c_lanes += need_eval && lk < K ? 1u : 0u;
+            c_ncls += need_eval && lk == 0 ? (unsigned)K : 0u;
             if (need_eval)
                 evaluate();
-            // statistics: children evaluated, and the classes they split
-            const int ne = __builtin_popcountll(em) >> LOGS;
-            n_evals += (unsigned)ne;
-            n_lanes += (unsigned)__builtin_popcountll(ballot(need_eval && lk < Kb));
-            n_ncls += (unsigned long long)wave_sum_u(need_eval && lk == 0 ? Kb : 0);
         }
         n_steps += 1;
         if (ballot(fin))
             finish_units();
     }
 
-    DEV unsigned wave_sum_u(int x) { return (unsigned)wave_sum(x); }
 
     // ---- work sharing ----
 
@@ -978,6 +980,7 @@ struct SegSearch {
     // Periodic: refresh incumbents, honour limits, keep the queue stocked.
     __device__ void check() {
         since_check = 0;
+        fold_counts();
         unsigned fl = 0;
         unsigned long long hd = 0, tl = 0;
         const bool may_donate = !P.single_wave && P.donate_low >= 0;
@@ -1107,9 +1110,11 @@ struct SegSearch {
         if (busy)
             n_busy += now_ticks() - t_busy0;
         // classes pushed and frames placed in HBM, summed over the segments
-        // (lane 0 of each)
+        // (lane 0 of each); children evaluated, their classes and the lanes
+        // holding them, summed over the lanes
         n_pushed = seg_total(pushed);
         n_hbm = seg_total(n_hbm);
+        fold_counts();
         if (lane == 0) {
             a_add64(&P.g->batches, n_steps);
             a_add64(&P.g->children, n_evals);
@@ -1133,6 +1138,14 @@ struct SegSearch {
         x = lk == 0 ? x : 0ull;
         return (unsigned long long)(unsigned)wave_sum((int)(unsigned)x) +
                ((unsigned long long)(unsigned)wave_sum((int)(unsigned)(x >> 32)) << 32);
+    }
+    // The per-lane counts into the wavefront's totals (each lane's count is
+    // at most 64 x check_interval, so the 32-bit sums cannot wrap).
+    __device__ void fold_counts() {
+        n_evals += (unsigned)wave_sum((int)c_evals);
+        n_lanes += (unsigned)wave_sum((int)c_lanes);
+        n_ncls += (unsigned)wave_sum((int)c_ncls);
+        c_evals = c_lanes = c_ncls = 0;
     }
 };
 

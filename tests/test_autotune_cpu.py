@@ -37,3 +37,40 @@ def test_pick_rejects_disagreeing_sizes():
           {"tuning": {"a": 2}, "kernel_ms": 2.0, "sizes": [3, 5], "proven": True}]
     with pytest.raises(RuntimeError):
         autotune.pick(ms)
+
+
+def test_workload_key_wide_rows():
+    k = autotune.workload_key(mi.pairs_w(ns=(80,), seeds=range(2)))
+    assert k.startswith("w128-dl-n80")
+
+
+def test_staged_candidates():
+    base = {"seg_lanes": 16}
+    c = autotune.staged_candidates(base, "waves_per_cu", (0, 8, 12))
+    assert c == [{"seg_lanes": 16}, {"seg_lanes": 16, "waves_per_cu": 8},
+                 {"seg_lanes": 16, "waves_per_cu": 12}]
+    # children_per_wave applies to one search per wavefront only
+    assert autotune.staged_candidates(base, "children_per_wave", (8, 4)) == []
+    c = autotune.staged_candidates({"seg_lanes": 64}, "children_per_wave", (8, 4))
+    assert c == [{"seg_lanes": 64, "children_per_wave": 8},
+                 {"seg_lanes": 64, "children_per_wave": 4}]
+
+
+def test_staged_search_walks_axes(monkeypatch):
+    """Coordinate descent with a fake timer: each stage keeps its fastest
+    value, and a candidate timed once is not timed again."""
+    calls = []
+
+    def fake_measure(pairs, cand, time_limit_s=30.0, reps=1):
+        calls.append(dict(cand))
+        ms = 10.0 - (cand.get("seg_lanes") == 8) * 3 - (cand.get("waves_per_cu") == 12) * 2
+        return {"tuning": dict(cand), "kernel_ms": ms, "sizes": [1, 2], "proven": True,
+                "nodes": 1}
+
+    monkeypatch.setattr(autotune, "measure", fake_measure)
+    best = autotune.tune_staged([None], axes=[("seg_lanes", (16, 8)),
+                                             ("waves_per_cu", (0, 12, 16))])
+    assert best["tuning"] == {"seg_lanes": 8, "waves_per_cu": 12}
+    assert best["kernel_ms"] == 5.0
+    keys = [tuple(sorted(c.items())) for c in calls]
+    assert len(keys) == len(set(keys)) == 4
