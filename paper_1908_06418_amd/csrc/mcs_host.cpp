@@ -1145,12 +1145,13 @@ void mcs_plan_destroy(mcs_plan *p) { delete p; }
 //   of (lo, hi].
 // strategies 2 and 3 (dead-end bound correction): plain runs with the
 //   dead-end forecast; a pair forecast to be in a dead end (too many nodes
-//   since its incumbent last rose) restarts from s = lo + step -- the bound
-//   raised by 1 (strategy 2) or by a step that doubles at each forecast,
-//   1, 2, 4, ... (strategy 3) -- so only mappings above s are looked for; a
-//   raised bound found unreachable (a finished run with nothing above s)
-//   sets hi = s and the rest is goal runs at the middle of (lo, hi].  Goal
-//   runs never use the forecast, so every pair settles.
+//   since its incumbent last rose) restarts from s = max(lo, s) + step -- the
+//   bound raised by 1 (strategy 2) or by a step that doubles at each
+//   forecast, 1, 2, 4, ... (strategy 3) -- so only mappings above s are
+//   looked for; a raised bound found unreachable (a finished run with
+//   nothing above s) sets hi = s and the rest is goal runs at the middle of
+//   (lo, hi].  s only grows and stays below hi, and goal runs never use the
+//   forecast, so every pair settles.
 // Every launch gets the full opts time limit; the node limit applies to the
 // first run of strategy 1 only.
 mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H,
@@ -1288,15 +1289,16 @@ mcs_status mcs_solve_goals(int32_t count, const mcs_graph *G, const mcs_graph *H
                     hi[i] = std::min(hi[i], start[i]);
                 bisect_next(i);
             } else if (dead_strat && !stopped) {
-                // forecast as a dead end: raise the bound above the best so far
-                const int s = lo[i] + step[i];
+                // forecast as a dead end: raise the bound (the best size so
+                // far, or the bound this run already started from) by the step
+                const int cur = std::max(lo[i], start[i]);
+                const int s = std::min(cur + step[i], hi[i] - 1);
                 if (strategy == 3)
                     step[i] *= 2;
-                if (std::min(s, hi[i] - 1) <= lo[i]) {
+                if (s <= cur)
                     bisect_next(i);  // no room left to raise it: settle by goals
-                } else {
-                    start[i] = std::min(s, hi[i] - 1);
-                }
+                else
+                    start[i] = s;
             } else if (strategy == 1 && runs == 1 && stopped) {
                 // the node-limited first run of strategy 1: bisect from lo
                 bisect_next(i);
