@@ -8,6 +8,7 @@ import json
 
 import numpy as np
 import pytest
+from _easy import easy_c4
 from _report import write_report
 
 import mcs_instances as mi
@@ -43,7 +44,7 @@ def test_portfolio_sizes_match_oracle(gpu):
             p = float(rng.uniform(0.1, 0.9))
             pairs.append((mi.random_small(rng, int(rng.integers(0, 16)), p, directed, nlab),
                           mi.random_small(rng, int(rng.integers(0, 16)), p, directed, nlab)))
-    pairs += _pairs(range(40))
+    pairs += easy_c4(40)[0]
     want = [oracle.mcs(G, H)["size"] for G, H in pairs]
     res = solve_batch(pairs, time_limit_s=60, ordering="portfolio")
     assert len(res) == len(pairs)
@@ -58,7 +59,7 @@ def test_portfolio_single_search_is_exact(gpu):
     """One search at a time (the two twins still share the incumbent):
     sizes exact."""
     from paper_1908_06418_amd import solve_batch
-    pairs = _pairs(range(16))
+    pairs = easy_c4(16, max_nodes=200_000)[0]
     want = [oracle.mcs(G, H)["size"] for G, H in pairs]
     res = solve_batch(pairs, time_limit_s=60, ordering="portfolio",
                       tuning={"single_wave": 1})
@@ -69,7 +70,7 @@ def test_portfolio_single_search_is_exact(gpu):
 def test_portfolio_goals_and_graph(gpu):
     """The portfolio under goal-directed search and through the HIP graph."""
     from paper_1908_06418_amd import Plan, solve_goals
-    pairs = _pairs(range(24))
+    pairs = easy_c4(24)[0]
     want = [oracle.mcs(G, H)["size"] for G, H in pairs]
     for strategy in ("top-down", "bisect"):
         res = solve_goals(pairs, strategy=strategy, time_limit_s=60, node_limit=20000,
