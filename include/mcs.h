@@ -282,6 +282,29 @@ mcs_status mcs_solve_batch(int32_t count, const mcs_graph *G, const mcs_graph *H
                            const mcs_opts *opts, void *workspace, size_t bytes,
                            void *stream, mcs_result *results);
 
+/* Bytes of the library's static device scratch (64 MiB). */
+#define MCS_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation:
+ * mcs_solve_batch with the library's own static device scratch (a
+ * file-scope array of MCS_STATIC_SCRATCH_BYTES per device, held by every
+ * device the library runs on until the process ends) as the workspace.  The
+ * caller still passes the inputs (host graphs, borrowed for the call) and
+ * the results (host, caller-owned).  No device memory, pinned host memory or
+ * event is allocated; the HIP graph mode (tuning->use_graph) is refused, as
+ * it stages through pinned memory.  Every call on one device reuses that
+ * device's scratch, whose contents the previous call left: the search state
+ * is cleared by the reset kernel at the start of each run.  Calls that
+ * overlap on one device (other host threads, other streams) race on the
+ * scratch: serialize them.  Synchronous on stream.  Errors: as
+ * mcs_solve_batch; MCS_E_WORKSPACE if the batch needs more than
+ * MCS_STATIC_SCRATCH_BYTES (mcs_workspace_size tells; fewer wavefronts per
+ * CU or one search per wavefront need less); MCS_E_INVALID for use_graph;
+ * MCS_E_DEVICE if the scratch's address cannot be looked up. */
+mcs_status mcs_solve_batch_static(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                                  const mcs_opts *opts, void *stream, mcs_result *results);
+
 /* Goal-directed search over a batch, as the paper's top-down and
  * bound-correction variants (Sec. IV.A).  strategy 0: goals root bound,
  * root bound - 1, ...; the first goal reached is the optimum.  strategy 1:

@@ -264,6 +264,36 @@ def solve_batch(pairs, node_limit=0, time_limit_s=0.0, tuning=None, with_stats=F
     return (res, st) if with_stats else res
 
 
+def solve_batch_static(pairs, node_limit=0, time_limit_s=0.0, tuning=None, ordering="degree",
+                       deadend_nodes=0, deadend_ratio=0):
+    """MCS of every pair in one launch on the library's static device scratch
+    (mcs_solve_batch_static): no device memory is allocated.  Returns a list
+    of Result."""
+    lib = _abi.load()
+    torch = _torch()
+    pairs = list(pairs)
+    m = _Marshal(pairs)
+    o, _t = _opts(node_limit, time_limit_s, tuning, ordering=ordering,
+                  deadend_nodes=deadend_nodes, deadend_ratio=deadend_ratio)
+    n = len(pairs)
+    res = (_abi.mcs_result * max(n, 1))()
+    bufs = []
+    for i, (g, h) in enumerate(pairs):
+        cap = max(1, min(int(g["n"]), int(h["n"])))
+        mg, mh = (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)()
+        bufs.append((mg, mh))
+        res[i].map_g, res[i].map_h = mg, mh
+    stream = torch.cuda.current_stream()
+    st = lib.mcs_solve_batch_static(n, m.G, m.H, ctypes.byref(o),
+                                    ctypes.c_void_p(stream.cuda_stream), res)
+    if st < 0:
+        raise McsError(st, _last_error())
+    return [Result(int(r.size), bool(r.optimal),
+                   [(int(bufs[i][0][j]), int(bufs[i][1][j])) for j in range(max(r.size, 0))],
+                   int(r.nodes), float(r.t_best_s), float(r.t_proof_s))
+            for i, r in enumerate(res[:n])]
+
+
 GOAL_STRATEGIES = {"top-down": 0, "bisect": 1, "dead-end+1": 2, "dead-end*2": 3}
 
 

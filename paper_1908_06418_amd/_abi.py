@@ -15,6 +15,7 @@ MCS_E_DEVICE = -3
 MCS_E_WORKSPACE = -4
 MCS_E_INTERNAL = -5
 MCS_MAX_N = 128
+MCS_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class mcs_graph(ctypes.Structure):
@@ -85,6 +86,10 @@ SIGNATURES = [
     ("mcs_solve_batch", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(mcs_graph),
                                        ctypes.POINTER(mcs_graph), ctypes.POINTER(mcs_opts), _P,
                                        ctypes.c_size_t, _P, ctypes.POINTER(mcs_result)]),
+    ("mcs_solve_batch_static", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(mcs_graph),
+                                              ctypes.POINTER(mcs_graph),
+                                              ctypes.POINTER(mcs_opts), _P,
+                                              ctypes.POINTER(mcs_result)]),
     ("mcs_solve", ctypes.c_int, [ctypes.POINTER(mcs_graph), ctypes.POINTER(mcs_graph),
                                  ctypes.POINTER(mcs_opts), _P, ctypes.c_size_t, _P,
                                  ctypes.POINTER(mcs_result)]),

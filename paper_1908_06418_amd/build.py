@@ -20,7 +20,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS
 
-SOURCES = ["mcs_search.hip", "mcs_seg.hip", "mcs_policy.hip", "mcs_host.cpp"]
+SOURCES = ["mcs_search.hip", "mcs_seg.hip", "mcs_policy.hip", "mcs_static.hip", "mcs_host.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -14,6 +14,7 @@
 
 extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed, int policy);
 extern "C" void *mcs_internal_seg_kernel(int word_bytes, int directed, int seg_log);
+extern "C" void *mcs_internal_static_scratch(size_t *bytes, int *err);
 extern "C" void *mcs_internal_reset_kernel(void);
 
 namespace {
@@ -293,6 +294,7 @@ struct mcs_plan {
     double tick_hz = 1e8;
 
     uint8_t *ws = nullptr;
+    bool no_events = false;  // (the static-scratch entry creates no events)
     bool uploaded = false;
     bool launched = false;
     mcs::SearchParams sp{};
@@ -923,7 +925,7 @@ mcs_status mcs_plan_run(mcs_plan *p, void *stream) {
     if (!p->uploaded)
         return fail(MCS_E_WORKSPACE, "mcs_plan_upload has not been called");
     hipStream_t s = as_stream(stream);
-    if (!p->ev0) {
+    if (!p->ev0 && !p->no_events) {
         HIP_TRY(hipEventCreate(&p->ev0));
         HIP_TRY(hipEventCreate(&p->ev1));
     }
@@ -1363,6 +1365,47 @@ mcs_status mcs_solve_batch(int32_t count, const mcs_graph *G, const mcs_graph *H
         for (int i = 0; i < count; i++)
             results[i].size = -1;
     mcs_plan_destroy(p);
+    return s;
+}
+
+mcs_status mcs_solve_batch_static(int32_t count, const mcs_graph *G, const mcs_graph *H,
+                                  const mcs_opts *opts, void *stream, mcs_result *results) {
+    if (!results)
+        return fail(MCS_E_INVALID, "results is NULL");
+    for (int i = 0; i < count; i++)
+        results[i].size = -1;
+    if (opts && opts->tuning && opts->tuning->use_graph)
+        return fail(MCS_E_INVALID, "the static-scratch entry does not run the HIP graph mode "
+                                   "(it stages through pinned host memory)");
+    size_t cap = 0;
+    int herr = 0;
+    uint8_t *scratch = (uint8_t *)mcs_internal_static_scratch(&cap, &herr);
+    if (!scratch)
+        return fail(MCS_E_DEVICE, "cannot look up the static scratch's device address (HIP "
+                                  "error " + std::to_string(herr) + ")");
+    mcs_plan *p = nullptr;
+    mcs_status s = mcs_plan_create(count, G, H, opts, &p);
+    if (s != MCS_OK)
+        return s;
+    struct PlanGuard {
+        mcs_plan *p;
+        ~PlanGuard() { mcs_plan_destroy(p); }
+    } guard{p};
+    if (p->ws_bytes > cap)
+        return fail(MCS_E_WORKSPACE, "the batch needs " + std::to_string(p->ws_bytes) +
+                                         " bytes of workspace, more than the " +
+                                         std::to_string(cap) +
+                                         "-byte static scratch: use mcs_solve_batch, or "
+                                         "fewer wavefronts per CU");
+    p->no_events = true;
+    s = mcs_plan_upload(p, scratch, cap, stream);
+    if (s == MCS_OK)
+        s = mcs_plan_run(p, stream);
+    if (s == MCS_OK)
+        s = mcs_plan_results(p, results, stream);
+    if (s < 0)
+        for (int i = 0; i < count; i++)
+            results[i].size = -1;
     return s;
 }
 
