@@ -14,6 +14,11 @@ static char g_dummy_kernel;
 extern "C" void *mcs_internal_search_kernel(int, int, int) { return &g_dummy_kernel; }
 extern "C" void *mcs_internal_reset_kernel(void) { return &g_dummy_kernel; }
 extern "C" void *mcs_internal_seg_kernel(int, int, int) { return &g_dummy_kernel; }
+extern "C" void *mcs_internal_static_scratch(size_t *bytes, int *err) {
+    *bytes = 0;
+    *err = -1;  // no device here
+    return nullptr;
+}
 
 static uint64_t g_state = 0x1234567ull;
 static uint64_t next_u64() {  // splitmix64
