@@ -13,7 +13,7 @@ pair proven optimal by the search itself; anything else marks the line
 "exact": false.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S]
-                    [--workload c4|c4_1024|c2|c2_n30|c3|c1|w]
+                    [--workload c4|c4_1024|c2|c2_n30|c3|c1|c5|w]
 
 The default workload is the batched one (4096 pairs).  Warmup and timed
 steps are cut to fit the wall-clock budget (default 420 s, the oracle leg
@@ -41,12 +41,6 @@ PEAK_HBM_BYTES = 8e12
 # kernel code (comments aside, code_hash) is the one those counters were
 # taken on.
 TRAFFIC = {
-    "c2": {"kernel_code_hash": "19d6bb92e9c532f0",
-           "bytes": int((31221114.3125 * 2 + 47464952.0) * 1024),
-           "profile": "profiles/mcs_search_kernel_c2.md"},
-    "w": {"kernel_code_hash": "19d6bb92e9c532f0",
-          "bytes": int((129434.9375 * 2 + 14574363.03125) * 1024),
-          "profile": "profiles/mcs_search_kernel_w.md"},
 }
 
 # Algorithmic 32-bit lane operations of one matched child (v, w), per class
@@ -81,6 +75,8 @@ def workloads():
         "c4": ("the batched workload: 4096 undirected pairs, n ~ U{10..35}, p ~ U[0.05,0.5), "
                "one persistent launch", lambda: mi.pairs_c4(4096), "expected_c4.json"),
         "c1": ("one undirected unlabelled pair G(16,0.3)", lambda: mi.pair_c1(), None),
+        "c5": ("the learned-ordering workload: 1024 undirected pairs, n ~ U{35..50}, "
+               "p 0.2 (first 512) / 0.4, one launch", lambda: mi.pairs_c5(1024), None),
         "w": ("40 directed vertex-labelled pairs n in {80,100}, p=0.1, ceil(0.33n) labels "
               "(128-bit rows), one batched launch", lambda: mi.pairs_w(), "expected_w.json"),
     }
@@ -100,15 +96,19 @@ def code_hash(text: str) -> str:
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
-def kernel_hash() -> str:
-    path = os.path.join(ROOT, "paper_1908_06418_amd", "csrc", "mcs_search.hip")
-    with open(path) as f:
-        return code_hash(f.read())
+def kernel_hash(source: str) -> str:
+    """code_hash of a kernel source file together with the device headers
+    it includes."""
+    text = ""
+    for name in (source, "mcs_device.h", "mcs_layout.h"):
+        with open(os.path.join(ROOT, "paper_1908_06418_amd", "csrc", name)) as f:
+            text += f.read() + "\n"
+    return code_hash(text)
 
 
-def traffic_for(workload: str, launches: int):
+def traffic_for(workload: str, source: str, launches: int):
     t = TRAFFIC.get(workload)
-    if not t or t["kernel_code_hash"] != kernel_hash():
+    if not t or t.get("source") != source or t["kernel_code_hash"] != kernel_hash(source):
         return None
     return t["bytes"] * launches
 
@@ -217,7 +217,8 @@ def main():
                     help="per-launch search time limit, seconds")
     ap.add_argument("--budget-s", type=float, default=420.0,
                     help="wall-clock budget of the whole run: warmup and timed steps are cut "
-                         "to fit it (at least 1 warmup and 3 timed steps are always run), "
+                         "to fit it (at least one warmup step, if any was asked for, and 3 "
+                         "timed steps, or all asked for if fewer, are always run), "
                          "leaving room for the cpu_baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
@@ -279,7 +280,7 @@ def main():
 
     warm_done = 0
     step_s = None
-    for _ in range(max(1, args.warmup)):
+    for _ in range(max(0, args.warmup)):
         if warm_done >= 1 and step_s is not None and left() < step_s * (3 + 1):
             break
         t1 = time.perf_counter()
@@ -327,7 +328,12 @@ def main():
     elapsed = time.perf_counter() - t0
     nmax = max(max(G["n"], H["n"]) for G, H in pairs)
     word = 4 if nmax <= 32 else 8 if nmax <= 64 else 16
-    directed = bool(pairs[0][0]["directed"])
+    directed = any(G["directed"] for G, _ in pairs)
+    seg_lanes = int(tuning.get("seg_lanes", 0) or 16)
+    segmented = word <= 8 and seg_lanes != 64
+    kernel_src = "mcs_seg.hip" if segmented else "mcs_search.hip"
+    kernel_name = (f"mcs_seg_kernel ({seg_lanes}-lane searches)" if segmented
+                   else "mcs_search_kernel")
     opc = ops_per_class(word, directed)
     ops = node_classes * opc + nodes * CHILD_OPS
     kern_s = kernel_ms / 1e3
@@ -367,8 +373,8 @@ def main():
         "lds_per_wave": st.lds_per_wave,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                      "frac": achieved / peak if peak else 0.0,
-                     "traffic": traffic_for(args.workload, 1),
-                     "kernel": "mcs_search_kernel",
+                     "traffic": traffic_for(args.workload, kernel_src, 1),
+                     "kernel": kernel_name,
                      "per_unit": f"{opc} int32 lane-ops per class of each matched child "
                                  f"counted as a node, plus {CHILD_OPS} per node; "
                                  "re-evaluated siblings are not counted"},

@@ -115,7 +115,7 @@ typedef struct {
     int32_t backoff_max;       /* an idle wavefront that finds no work sleeps
                                   1, 2, 4, ... up to this many times about
                                   3.4 us before polling again (0: 32) */
-    int32_t seg_lanes;         /* search layout: 16 or 8 -- each wavefront runs
+    int32_t seg_lanes;         /* search layout: 16, 8 or 4 -- each wavefront runs
                                   64 / seg_lanes independent searches, one per
                                   segment of that many lanes (a node's classes
                                   across the segment); 64 -- one search per

@@ -584,27 +584,28 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     // lane).
     {
         const int sl = p->tun.seg_lanes;
-        if (sl != 0 && sl != 8 && sl != 16 && sl != 64) {
+        if (sl != 0 && sl != 4 && sl != 8 && sl != 16 && sl != 64) {
             delete p;
-            return fail(MCS_E_INVALID, "seg_lanes must be 0, 8, 16 or 64");
+            return fail(MCS_E_INVALID, "seg_lanes must be 0, 4, 8, 16 or 64");
         }
         if (wide || p->policy || sl == 64)
             p->seg_log = 0;
         else
-            p->seg_log = sl == 8 ? 3 : 4;
+            p->seg_log = sl == 4 ? 2 : sl == 8 ? 3 : 4;
     }
     const int nseg = p->seg_log ? 64 >> p->seg_log : 1;
     // Default wavefronts: about 96 searches per instance, between 8 and 24
     // per CU for one search per wavefront (4 and 16 with 128-bit rows, whose
-    // larger state fits fewer), and about 48 searches per CU (12 wavefronts
-    // of 4) for the segmented kernel, so one hard instance alone still
-    // splits across thousands of searches.  One search is a long dependent
-    // chain of steps, so several wavefronts per SIMD fill the issue slots
-    // while there is work for them; past what the instances can keep busy,
-    // more searches only split the work into ever smaller donations.
+    // larger state fits fewer), and about 64 searches per CU (16 wavefronts
+    // of 4, as many as the segmented kernel's registers let a SIMD hold)
+    // for the segmented kernel, so one hard instance alone still splits
+    // across thousands of searches.  One search is a long dependent chain of
+    // steps, so several wavefronts per SIMD fill the issue slots while there
+    // is work for them; past what the instances can keep busy, more searches
+    // only split the work into ever smaller donations.
     const int want_waves =
         p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
-        : p->seg_log ? std::max(2 * cus, std::min((48 / nseg) * cus, (96 * ndev + nseg - 1) / nseg))
+        : p->seg_log ? std::max(2 * cus, std::min((64 / nseg) * cus, (96 * ndev + nseg - 1) / nseg))
         : wide       ? std::max(4 * cus, std::min(16 * cus, 96 * ndev))
                      : std::max(8 * cus, std::min(24 * cus, 96 * ndev));
     const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);

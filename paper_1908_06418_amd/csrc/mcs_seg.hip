@@ -154,7 +154,8 @@ struct SegSearch {
     __device__ int ssum(int x) const {
         x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
         x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
-        x += dpp<0x141>(x);  // row_half_mirror: the other quad of the 8-lane half
+        if (LOGS >= 3)
+            x += dpp<0x141>(x);  // row_half_mirror: the other quad of the 8-lane half
         if (LOGS >= 4)
             x += dpp<0x140>(x);  // row_mirror: the other half of the 16-lane row
         return x;
@@ -163,7 +164,8 @@ struct SegSearch {
     __device__ uint32_t smin(uint32_t x) const {
         x = dpp_min_step<0xB1>(x);
         x = dpp_min_step<0x4E>(x);
-        x = dpp_min_step<0x141>(x);
+        if (LOGS >= 3)
+            x = dpp_min_step<0x141>(x);
         if (LOGS >= 4)
             x = dpp_min_step<0x140>(x);
         return x;
@@ -1168,9 +1170,15 @@ __global__ void __launch_bounds__(256) mcs_seg_kernel(SearchParams Pk) {
 
 // Launch entry point used by the host driver: the kernel for rows of
 // word_bytes (4 or 8), directed or not, with segments of 2^seg_log lanes
-// (3 or 4); null for anything else.
+// (2, 3 or 4); null for anything else.
 extern "C" void *mcs_internal_seg_kernel(int word_bytes, int directed, int seg_log) {
     using namespace mcs;
+    if (seg_log == 2)
+        return word_bytes == 4 ? (directed ? (void *)mcs_seg_kernel<uint32_t, true, 2>
+                                           : (void *)mcs_seg_kernel<uint32_t, false, 2>)
+               : word_bytes == 8 ? (directed ? (void *)mcs_seg_kernel<uint64_t, true, 2>
+                                             : (void *)mcs_seg_kernel<uint64_t, false, 2>)
+                                 : nullptr;
     if (word_bytes == 4) {
         if (seg_log == 3)
             return directed ? (void *)mcs_seg_kernel<uint32_t, true, 3>

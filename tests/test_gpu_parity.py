@@ -47,9 +47,9 @@ def test_c1_single_pair(gpu):
         assert oracle.check.is_valid(G, H, r.mapping)
 
 
-# search layouts: one search per 16-lane segment (the default), per 8-lane
-# segment, and one per wavefront
-LAYOUTS = [16, 8, 64]
+# search layouts: one search per 16-lane segment (the default), per 8- or
+# 4-lane segment, and one per wavefront
+LAYOUTS = [16, 8, 4, 64]
 
 
 @pytest.mark.parametrize("lanes", LAYOUTS)
@@ -243,6 +243,7 @@ def test_tunings_do_not_change_sizes(gpu, tun):
     {"stack_classes": 1, "donate_low": -1},
     {"stack_classes": 1, "seg_lanes": 8, "ring_slots": 2, "waves_per_cu": 8},
     {"stack_classes": 1, "single_wave": 1},
+    {"stack_classes": 1, "seg_lanes": 4},
 ])
 def test_small_lds_stack_puts_frames_in_hbm_exactly(gpu, tun):
     """The smallest LDS part of each search's class stack (1 asks for the

@@ -3,7 +3,6 @@ against the float64 reference (oracle/policy.py), training, exactness of the
 search with the policy on, and what the trained policy gains."""
 import json
 import os
-from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 import pytest
@@ -77,24 +76,17 @@ def test_sgd_and_pack(gpu):
     assert np.array_equal(P.half_params.cpu().numpy(), after.astype(np.float16))
 
 
-def _rows_of(args):
-    G, H = args
-    from oracle import traces
-    Xb, yb = traces.branch_pair_rows(G, H)
-    Xv, yv = traces.value_pair_rows(G, H)
-    return Xb + Xv, yb + yv
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _training_set(count):
-    """Rows from the training workload's pairs of up to 24 vertices:
-    branching-vertex rows (proof-cost labels) and partner-order rows
-    (reachability labels), both from the oracle."""
-    pairs = [pq for pq in mi.pairs_c5(3 * count, train=True) if pq[0]["n"] <= 24][:count]
-    with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-        parts = list(ex.map(_rows_of, pairs))
-    X = np.array([r for Xa, _ in parts for r in Xa]).reshape(-1, ref.F)
-    y = np.array([v for _, ya in parts for v in ya])
-    return X, y
+def _training_set():
+    """Rows from the learned-ordering workload's training pairs (n ~ U{20..30},
+    p 0.2 / 0.4), stored by tests/golden/make_policy_rows.py from the oracle
+    alone: branching-vertex rows (proof-cost labels) and partner-order rows
+    (reachability labels)."""
+    d = np.load(os.path.join(GOLDEN, "policy_rows_c5_train.npz"))
+    return (d["X"].astype(np.float64), d["y"].astype(np.float64),
+            np.bincount(d["n"].astype(np.int64), minlength=31)[20:31].tolist())
 
 
 _TRAINED = {}
@@ -103,12 +95,12 @@ _TRAINED = {}
 def _trained_policy():
     if "p" not in _TRAINED:
         from paper_1908_06418_amd.policy import Policy
-        _say("policy: generating oracle traces")
-        X, y = _training_set(120)
-        _say(f"policy: {len(y)} rows, {y.mean():.2f} positive; training on the GPU")
+        X, y, by_n = _training_set()
+        _say(f"policy: {len(y)} rows (per n = 20..30: {by_n}), mean label {y.mean():.2f}; "
+             "training on the GPU")
         P = Policy(seed=0)
         curve = P.train(X, y, steps=600, lr=0.5)
-        _TRAINED.update(p=P, curve=curve, rows=len(y))
+        _TRAINED.update(p=P, curve=curve, rows=len(y), rows_by_n=by_n)
     return _TRAINED["p"], _TRAINED["curve"]
 
 
@@ -242,6 +234,7 @@ def test_policy_gain_report(gpu):
                        "nodes_ratio_median": float(np.median([l.nodes / b.nodes
                                                               for b, l in both]))}
     best = min(modes, key=lambda m: modes[m]["nodes_ratio_total"])
+    _TRAINED["best_mode"] = best
     c2 = mi.pairs_c2(ns=(30,))
     times = {}
     for name, kw in (("plain", {}), ("learned", {"policy": P, "policy_depth": 1,
@@ -263,6 +256,43 @@ def test_policy_gain_report(gpu):
               "c2_n30_nodes_plain": times["plain"][2],
               "c2_n30_nodes_learned": times["learned"][2],
               "train_rows": _TRAINED["rows"],
+              "train_rows_by_n_20_to_30": _TRAINED["rows_by_n"],
               "train_loss_first_last": [curve[0], curve[-1]]}
     _say("policy gain: " + json.dumps(report))
     write_report("policy_gain.json", report)
+
+
+def test_c5_learned_vs_degree_report(gpu):
+    """The learned-ordering workload (evaluation pairs n ~ U{35..50}, p 0.2
+    for the first half and 0.4 for the second; here the first 64 of each
+    half), one launch per way under the same 20 s limit: the plain degree
+    rule and the trained policy, both one search per wavefront (the layout
+    the scorer runs in), and the plain rule on the default segmented layout.
+    Proven count, nodes and median time to proof; sizes agree wherever two
+    ways both proved a pair, and every mapping is valid."""
+    from paper_1908_06418_amd import solve_batch
+    P, _ = _trained_policy()
+    mode = _TRAINED.get("best_mode", 3)
+    pairs = mi.pairs_c5(64) + mi.pairs_c5(64, start=512)
+    ways = {"degree_segmented": {},
+            "degree_one_per_wave": {"tuning": {"seg_lanes": 64}},
+            "learned_one_per_wave": {"policy": P, "policy_depth": 2, "policy_mode": mode}}
+    out, res_by = {}, {}
+    for name, kw in ways.items():
+        _say(f"c5: {name}")
+        res, st = solve_batch(pairs, time_limit_s=20, with_stats=True, **kw)
+        for (G, H), r in zip(pairs, res):
+            assert oracle.check.is_valid(G, H, r.mapping)
+        proven = [r for r in res if r.optimal]
+        out[name] = {"proven": len(proven), "pairs": len(pairs), "nodes": st.nodes,
+                     "kernel_ms": st.kernel_ms,
+                     "median_time_to_proof_s": float(np.median([r.t_proof_s for r in proven]))
+                     if proven else None}
+        res_by[name] = res
+    names = list(ways)
+    for i in range(len(pairs)):
+        sizes = {res_by[n][i].size for n in names if res_by[n][i].optimal}
+        assert len(sizes) <= 1, (i, sizes)
+    out["policy_mode"] = mode
+    _say("c5 report: " + json.dumps(out))
+    write_report("c5_learned_vs_degree.json", out)
