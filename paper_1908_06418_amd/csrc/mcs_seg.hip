@@ -6,7 +6,7 @@
 //     bound = |M| + sum over classes of min(|L|, |R|),
 // pruning it when the bound cannot beat the incumbent.
 //
-// Layout (ours): a wavefront is cut into 64 / S segments of S = 8 or 16
+// Layout (ours): a wavefront is cut into 64 / S segments of S = 4, 8 or 16
 // lanes, and each segment runs its own search.  Lane k of a segment holds
 // class k of the segment's top frame (classes k + S, k + 2S, ... of a frame
 // with more than S classes are read from LDS in further passes).  Every
@@ -15,7 +15,7 @@
 // is uniform within the segment, so the search's bookkeeping runs on the
 // vector unit for all segments at once instead of on the CU's single scalar
 // unit.  Segment reductions (the Eq. 1 sum, the class-choice minimum) are
-// DPP steps that stay inside 8- or 16-lane groups.
+// DPP steps that stay inside 4-, 8- or 16-lane groups.
 //
 // The segments advance in lock step.  One step is, for each segment, in this
 // order and only where it applies:
