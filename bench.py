@@ -300,7 +300,7 @@ def main():
     nodes = 0
     kernel_ms = 0.0
     lane_slots = batches = children = node_classes = 0
-    lds_bytes = 0
+    lds_bytes = pops = donations = hbm_frames = 0
     proven = 0
     busy = []
     t_best, t_proof = [], []
@@ -316,6 +316,9 @@ def main():
         lds_bytes += st.lds_bytes
         batches += st.batches
         children += st.children
+        pops += st.pops
+        donations += st.donations
+        hbm_frames += st.hbm_frames
         proven += sum(r.optimal for r in res)
         busy.append(st.busy_frac)
         t_best += [r.t_best_s for r in res]
@@ -373,6 +376,11 @@ def main():
         "busy_frac": sum(busy) / len(busy) if busy else 0.0,
         "active_lane_frac": lane_slots / (64.0 * batches) if batches else 0.0,
         "children_per_batch": children / batches if batches else 0.0,
+        "search_stats": {"steps_per_node": batches / nodes if nodes else 0.0,
+                         "children_per_node": children / nodes if nodes else 0.0,
+                         "queue_takes_per_node": pops / nodes if nodes else 0.0,
+                         "donations_per_node": donations / nodes if nodes else 0.0,
+                         "hbm_frames_per_node": hbm_frames / nodes if nodes else 0.0},
         "waves": st.waves,
         "lds_per_wave": st.lds_per_wave,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",

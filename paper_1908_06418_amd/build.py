@@ -15,8 +15,15 @@ LIB = os.path.join(PKG, "libmcs.so")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# Packed-FP32 instructions stay off in every HIP build of this project.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed-FP32 instructions stay off in every HIP build of this project, and
+# so does gfx950's three-input bitwise instruction (v_bitop3): this
+# compiler folded a chain of and/xor over three inputs (x ^ (x & y), then
+# its and with a third row, then the xor of the two) into one v_bitop3
+# with a wrong truth table (three minterms for what is a single one), which
+# made the directed split drop its parts.  Without the feature the same
+# code is plain v_and/v_xor/v_bfi.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-Xclang", "-target-feature", "-Xclang", "-bitop3-insts"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS
 

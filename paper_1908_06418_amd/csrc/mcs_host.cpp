@@ -994,7 +994,10 @@ mcs_status mcs_plan_results(mcs_plan *p, mcs_result *res, void *stream) {
     }
     p->have_results = true;
     if (p->h_glob.error)
-        return fail(MCS_E_INTERNAL, "a search wavefront hit an internal capacity check");
+        return fail(MCS_E_INTERNAL,
+                    p->h_glob.error == 2   ? "a search produced a mapping larger than the smaller graph"
+                    : p->h_glob.error == 3 ? "a search's class stack grew past its worst case"
+                                           : "a search wavefront hit an internal capacity check");
 
     const unsigned long long mask48 = 0xFFFFFFFFFFFFull;
     const unsigned long long t0 = p->h_glob.t0;

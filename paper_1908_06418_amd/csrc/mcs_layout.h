@@ -114,8 +114,10 @@ struct SearchParams {
                                      // (0: never)
     long long dead_rel;              // ... and more than this many times the nodes that
                                      // led to the last improvement (0: absolute only)
-    uint8_t *hstack;                 // (128-bit rows) [waves][hstack_stride] class stacks
-    long long hstack_stride;         // bytes per wavefront: (cap_classes + 1) (L, R) pairs
+    uint8_t *hstack;                 // HBM class stacks, or null: [waves][hstack_stride]
+                                     // (128-bit rows), [waves][searches][hstack_stride]
+                                     // (segments: the part above the LDS part)
+    long long hstack_stride;         // bytes per stack (0: no HBM part)
     int seg_log;                     // segmented kernel: 2^seg_log lanes per search (0: one
                                      // search per wavefront)
     int seg_bytes;                   // segmented kernel: LDS bytes per search (seg_layout)

@@ -22,11 +22,16 @@
 //   pop       -- the top frame has nothing left: return to the parent frame;
 //   unmatched -- the top frame's partners are done: take its "v unmatched"
 //                child in place (its bound follows from the parent's);
+//   reload    -- a frame the search has just entered, or returned to, gets
+//                its classes into registers and, if it is new, its class
+//                and v chosen;
 //   evaluate  -- split the classes for the next partner w of v, bound the
 //                child, and either prune it or push it as the new top frame
-//                and choose its class and v.
-// A phase no segment needs is skipped (a uniform branch on a ballot).
-// Children are evaluated one per step, in ascending w, each exactly once.
+//                (to be reloaded at the next step).
+// A phase no segment needs is skipped (a uniform branch on a ballot), and
+// each phase's code runs at most once per step for all the segments that
+// need it.  Children are evaluated one per step, in ascending w, each
+// exactly once.
 //
 // Work sharing, incumbents and termination are those of the one-search-per-
 // wavefront kernel (mcs_search.hip), applied per segment: node records in
@@ -44,12 +49,35 @@ namespace mcs {
 //   w:    v | sel << 8 | bound << 16 | flags << 24
 // |L_sel| and |R_sel| are not stored: the selected class itself is not
 // changed while its frame is open (only its partner copy is), so they are
-// counted again when the search returns to the frame.
+// counted from it when they are needed.
 
+// Codes of DevGlobals::error (the host reports MCS_E_INTERNAL).
+constexpr unsigned kErrMapping = 2;  // a mapping larger than the smaller graph
+constexpr unsigned kErrStack = 3;    // a frame past the class stack's worst case
+
+// Flags of a segment's top frame beside kFlagUnmatched, set between phases
+// of a step (never stored in a frame header or record):
+constexpr int kFlagSelect = 4;  // a new frame: load its classes, choose class and v
+constexpr int kFlagLoad = 8;    // a frame returned to: load its classes
+static_assert(kFlagSelect == kFlagFresh, "a fresh record takes the same path");
+
+// One step of a segment minimum.  The neighbour's value comes with the
+// minimum's identity as the fallback, so the DPP move folds into the
+// v_min_u32 itself (one instruction per step).
 template <int CTRL>
 DEV uint32_t dpp_min_step(uint32_t x) {
-    return umin(x, (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false));
+    return umin(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, CTRL, 0xF, 0xF,
+                                                         false));
 }
+
+// Pointers typed by address space.  The class stack's LDS part and HBM part
+// are reached through them, so the compiler emits LDS (ds_*) and global
+// accesses and cannot fold the branch between the two parts into a single
+// flat access with a selected address.
+template <typename T>
+using lds_p = __attribute__((address_space(3))) T *;
+template <typename T>
+using glb_p = __attribute__((address_space(1))) T *;
 
 template <typename W, bool DIR, int LOGS>
 struct SegSearch {
@@ -58,6 +86,10 @@ struct SegSearch {
     static constexpr int NB = bits_of<W>();
     static constexpr int NR = DIR ? 4 : 2;
     static constexpr uint32_t SEGMASK = S == 32 ? 0xFFFFFFFFu : ((1u << S) - 1);
+    // lane 0 of every segment
+    static constexpr uint64_t kLeadLanes = S == 16 ? 0x0001000100010001ull
+                                          : S == 8 ? 0x0101010101010101ull
+                                                   : 0x1111111111111111ull;
 
     const SearchParams &P;
     // knobs (wave-uniform)
@@ -65,11 +97,11 @@ struct SegSearch {
     // lane identity
     int lane, lk, seg;
     // this lane's segment's LDS
-    Cls<W> *scls;     // [cap + 1]: class stack entries 0 .. cap - 1; the last
-                      // entry is a trash slot
-    Cls<W> *hcls;     // class stack entries cap and above, in HBM (the worst
-                      // case fits: frames never straddle the two parts)
-    Cls<W> *hwave;    // the wavefront's HBM class stacks (segment j at j * hstride)
+    // class stack entry i is the pair of words (L, R) at 2i, 2i + 1
+    lds_p<W> scls;    // [cap + 1]: entries 0 .. cap - 1; the last is a trash slot
+    glb_p<W> hcls;    // entries cap and above, in HBM (the worst case fits:
+                      // frames never straddle the two parts)
+    glb_p<W> hwave;   // the wavefront's HBM class stacks (segment j at j * hstride)
     long long hstride;  // classes per segment's HBM part
     W *sadj;          // [NR][arows]
     uint16_t *smap;   // [NB] g | h << 8 per depth
@@ -82,7 +114,7 @@ struct SegSearch {
     int adj_inst;     // instance whose rows are in the segment's LDS
     int inc_slot, twin, map_off, target;
     int dead_on;      // the instance may be given up as a dead end
-    int t, base, K, d, v, sel, bound, flags, lsel, rsel, inc, d0;
+    int t, base, K, d, v, sel, bound, flags, inc, d0;
     W rrem;
     W cL, cR;         // this lane's class of the top frame (class lk)
     uint32_t nodes_pend;  // nodes of the unit not yet added to the instance's count
@@ -97,10 +129,9 @@ struct SegSearch {
     int donor;        // segment considered first for the next donation
     unsigned long long t_start;
     unsigned long long n_steps, n_evals, n_nodes_wave, n_lanes, n_don, n_pops, n_busy, n_hbm,
-        n_sleep, n_pushed, n_ncls;
-    // per-lane counts since the last check (at most check_interval steps, so
-    // 32 bits cannot wrap), folded into the totals above by fold_counts()
-    uint32_t c_evals, c_lanes, c_ncls;
+        n_sleep, n_pushed;
+    unsigned long long n_ncls;  // classes of this segment's evaluated children past the
+                                // first pass (summed over the segments at the end)
     int max_used;
 
     __device__ SegSearch(const SearchParams &p, uint8_t *wave_lds, long long wave) : P(p) {
@@ -116,10 +147,10 @@ struct SegSearch {
         const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, p.cap_classes, p.arows,
                                        p.frames);
         uint8_t *mine = wave_lds + (size_t)seg * (size_t)seg_bytes;
-        scls = (Cls<W> *)(mine + L.cls);
+        scls = (lds_p<W>)(mine + L.cls);
         hstride = p.hstack_stride / (long long)sizeof(Cls<W>);
-        hwave = (Cls<W> *)p.hstack + wave * NSEG * hstride;
-        hcls = hwave + seg * hstride;
+        hwave = (glb_p<W>)p.hstack + 2 * wave * NSEG * hstride;
+        hcls = hwave + 2 * seg * hstride;
         sadj = (W *)(mine + L.adj);
         smap = (uint16_t *)(mine + L.map);
         shdr = (uint4 *)(mine + L.hdr);
@@ -131,7 +162,7 @@ struct SegSearch {
         target = 0;
         dead_on = 0;
         t = -1;
-        base = K = d = v = sel = bound = flags = lsel = rsel = inc = d0 = 0;
+        base = K = d = v = sel = bound = flags = inc = d0 = 0;
         rrem = cL = cR = 0;
         nodes_pend = 0;
         fin = false;
@@ -144,7 +175,6 @@ struct SegSearch {
         donor = 0;
         n_steps = n_evals = n_nodes_wave = n_lanes = n_don = n_pops = n_busy = n_hbm = 0;
         n_sleep = n_pushed = n_ncls = 0;
-        c_evals = c_lanes = c_ncls = 0;
         max_used = 0;
     }
 
@@ -190,21 +220,34 @@ struct SegSearch {
     }
     // Class stack entry i of this lane's segment (LDS below cap, HBM above).
     __device__ Cls<W> cget(int i) const {
-        if (i < cap)
-            return scls[i];
-        return hcls[i - cap];
+        Cls<W> c;
+        if (i < cap) {
+            c.L = scls[2 * i];
+            c.R = scls[2 * i + 1];
+        } else {
+            c.L = hcls[2 * (i - cap)];
+            c.R = hcls[2 * (i - cap) + 1];
+        }
+        return c;
     }
     __device__ void cput(int i, const Cls<W> &c) const {
-        if (i < cap)
-            scls[i] = c;
-        else
-            hcls[i - cap] = c;
+        if (i < cap) {
+            scls[2 * i] = c.L;
+            scls[2 * i + 1] = c.R;
+        } else {
+            hcls[2 * (i - cap)] = c.L;
+            hcls[2 * (i - cap) + 1] = c.R;
+        }
     }
     // Entry i of segment j's class stack.
     __device__ Cls<W> cget_of(int j, int i) const {
         if (i < cap)
             return cls_of(j)[i];
-        return hwave[(long long)j * hstride + (i - cap)];
+        const glb_p<W> h = hwave + 2 * ((long long)j * hstride + (i - cap));
+        Cls<W> c;
+        c.L = h[0];
+        c.R = h[1];
+        return c;
     }
     // Orders a segment's class stores before other lanes of the wavefront
     // read them: an LDS frame needs only the wave's in-order LDS; a frame in
@@ -278,29 +321,22 @@ struct SegSearch {
             const int nl = popc(cL), nr = popc(cR);
             key = ((uint32_t)(nl > nr ? nl : nr) << 16) | ((uint32_t)ctz(cL) << 8) | (uint32_t)lk;
         }
-        for (int c = 1; ballot(c * S < K) != 0; ++c) {
-            const int k = c * S + lk;
-            if (k < K) {
-                const Cls<W> x = cget(base + k);
-                const int nl = popc(x.L), nr = popc(x.R);
-                key = umin(key, ((uint32_t)(nl > nr ? nl : nr) << 16) |
-                                    ((uint32_t)ctz(x.L) << 8) | (uint32_t)k);
+        if (ballot(K > S) != 0) {  // (rare) classes past the first S
+            for (int c = 1; ballot(c * S < K) != 0; ++c) {
+                const int k = c * S + lk;
+                if (k < K) {
+                    const Cls<W> x = cget(base + k);
+                    const int nl = popc(x.L), nr = popc(x.R);
+                    key = umin(key, ((uint32_t)(nl > nr ? nl : nr) << 16) |
+                                        ((uint32_t)ctz(x.L) << 8) | (uint32_t)k);
+                }
             }
         }
         const uint32_t mk = smin(key);
         v = (int)((mk >> 8) & 0xFFu);
         sel = (int)(mk & 0xFFu);
-        const Cls<W> cs = cget(base + sel);
-        rrem = cs.R;
-        lsel = popc(cs.L);
-        rsel = popc(cs.R);
-    }
-
-    // |L_sel| and |R_sel| of a frame the search returns to.
-    __device__ void recount_sel() {
-        const Cls<W> cs = cget(base + sel);
-        lsel = popc(cs.L);
-        rsel = popc(cs.R);
+        rrem = cget(base + sel).R;
+        flags = kFlagUnmatched;
     }
 
     // ---- incumbent ----
@@ -315,6 +351,15 @@ struct SegSearch {
     // vertices: raise the instance's incumbent; the segment that raised it
     // to `size` writes the mapping into that size's slot.
     __device__ void improve(int size) {
+        // a mapping larger than the smaller graph can only come from a broken
+        // class partition: stop with an internal error instead of writing
+        // past this instance's mapping slots
+        const DevInst di = P.inst[inst];
+        if (size > (di.nG < di.nH ? (int)di.nG : (int)di.nH)) {
+            if (lk == 0)
+                fail_lane(kErrMapping);
+            return;
+        }
         int old = 0;
         if (lk == 0)
             old = a_max(&P.inc[inc_slot], size);
@@ -350,15 +395,15 @@ struct SegSearch {
             flags = 0;  // nothing here can beat the incumbent: pop again
             return;
         }
-        if (rrem == 0 && !(flags & kFlagUnmatched))
-            return;
-        load_regs();
-        recount_sel();
+        if (rrem != 0)
+            flags |= kFlagLoad;  // its next partner is evaluated in this step
     }
 
     // The "v unmatched" child, in place: only the selected class loses v.
     __device__ void unmatched() {
         flags = 0;
+        const Cls<W> cs = cget(base + sel);
+        const int lsel = popc(cs.L), rsel = popc(cs.R);
         const int ub = bound - (lsel <= rsel ? 1 : 0);
         nodes_pend += 1;
         if (ub <= inc)
@@ -374,7 +419,7 @@ struct SegSearch {
             }
             K = last;
         } else {
-            Cls<W> c = cget(base + sel);
+            Cls<W> c = cs;
             c.L &= ~vb;
             if (lk == 0)
                 cput(base + sel, c);
@@ -383,44 +428,65 @@ struct SegSearch {
         bound = ub;
         if (K == 0)
             return;
-        flags = kFlagUnmatched;
-        load_regs();
-        select();
+        flags = kFlagSelect;  // a class and v of the smaller frame, in this step
+    }
+
+    // Registers (and, for a new frame, class and v) of the frames that need
+    // them.  cL then drops v: every child of the frame is split without it.
+    __device__ void reload() {
+        const bool ld = (flags & (kFlagSelect | kFlagLoad)) != 0;
+        if (ld)
+            load_regs();
+        const bool fresh = (flags & kFlagSelect) != 0;
+        if (ballot(fresh))
+            if (fresh)
+                select();
+        if (ld)
+            cL &= ~((W)1 << v);
+        flags &= ~kFlagLoad;
     }
 
     // Parts of class (L, R) for the child (v, w), by adjacency letter.
+    // Part a holds the vertices whose letter is a: bit 0 an edge from v (from
+    // w), bit 1 (directed) an edge into v (into w).  A part without a bit is
+    // the rest of the part with it (x & ~y == x ^ (x & y)), which saves the
+    // complement of each row.
     __device__ void split(W L, W R, W go, W ho, W gi, W hi, W *pl, W *pr) const {
         if constexpr (!DIR) {
-            pl[0] = L & ~go;
-            pr[0] = R & ~ho;
             pl[1] = L & go;
             pr[1] = R & ho;
+            pl[0] = L ^ pl[1];
+            pr[0] = R ^ pr[1];
         } else {
-            pl[0] = L & ~go & ~gi;
-            pr[0] = R & ~ho & ~hi;
-            pl[1] = L & go & ~gi;
-            pr[1] = R & ho & ~hi;
-            pl[2] = L & ~go & gi;
-            pr[2] = R & ~ho & hi;
-            pl[3] = L & go & gi;
-            pr[3] = R & ho & hi;
+            const W lo1 = L & go, ro1 = R & ho;
+            const W lo0 = L ^ lo1, ro0 = R ^ ro1;
+            pl[3] = lo1 & gi;
+            pr[3] = ro1 & hi;
+            pl[1] = lo1 ^ pl[3];
+            pr[1] = ro1 ^ pr[3];
+            pl[2] = lo0 & gi;
+            pr[2] = ro0 & hi;
+            pl[0] = lo0 ^ pl[2];
+            pr[0] = ro0 ^ pr[2];
         }
     }
-    DEV int part_min(const W *pl, const W *pr) {
+    // min(|L_a|, |R_a|) of each part, and their sum.
+    DEV int part_mins(const W *pl, const W *pr, int *mn) {
         int s = 0;
 #pragma unroll
         for (int a = 0; a < NR; ++a) {
             const int nl = popc(pl[a]), nr = popc(pr[a]);
-            s += nl < nr ? nl : nr;
+            mn[a] = nl < nr ? nl : nr;
+            s += mn[a];
         }
         return s;
     }
 
     // The next partner w of v: split, Eq. 1, then prune or descend.
+    // (cL no longer holds v: reload() took it out.)
     __device__ void evaluate() {
         const int w = ctz(rrem);
         rrem &= rrem - 1;
-        const W vb = (W)1 << v;
         const W wb = (W)1 << w;
         const W go = sadj[v], ho = sadj[arows + w];
         W gi = 0, hi = 0;
@@ -429,21 +495,26 @@ struct SegSearch {
             hi = sadj[3 * arows + w];
         }
         W pl[NR], pr[NR];
-        split(cL & ~vb, cR & ~wb, go, ho, gi, hi, pl, pr);
-        int contrib = part_min(pl, pr);
-        for (int c = 1; ballot(c * S < K) != 0; ++c) {
-            const int k = c * S + lk;
-            if (k < K) {
-                const Cls<W> x = cget(base + k);
-                W ql[NR], qr[NR];
-                split(x.L & ~vb, x.R & ~wb, go, ho, gi, hi, ql, qr);
-                contrib += part_min(ql, qr);
+        int mn[NR];
+        split(cL, cR & ~wb, go, ho, gi, hi, pl, pr);
+        int contrib = part_mins(pl, pr, mn);
+        if (ballot(K > S) != 0) {  // (rare) classes past the first S
+            for (int c = 1; ballot(c * S < K) != 0; ++c) {
+                const int k = c * S + lk;
+                n_ncls += (unsigned)__builtin_popcount(sbits(ballot(k < K)));
+                if (k < K) {
+                    const Cls<W> x = cget(base + k);
+                    W ql[NR], qr[NR];
+                    int qm[NR];
+                    split(x.L & ~((W)1 << v), x.R & ~wb, go, ho, gi, hi, ql, qr);
+                    contrib += part_mins(ql, qr, qm);
+                }
             }
         }
         const int b = d + 1 + ssum(contrib);
         nodes_pend += 1;
         if (b > inc)
-            descend(w, b, go, ho, gi, hi, pl, pr);
+            descend(w, b, go, ho, gi, hi, pl, pr, mn);
     }
 
     // The child (v, w) survived its bound: compact its non-empty classes
@@ -451,47 +522,64 @@ struct SegSearch {
     // kept class adds at least one to the Eq. 1 sum, so the child has at most
     // b - d - 1 classes: a frame that might not fit below cap starts at cap,
     // in the HBM part of the stack, so no frame straddles the two parts.
-    __device__ void descend(int w, int b, W go, W ho, W gi, W hi, const W *pl, const W *pr) {
+    __device__ void descend(int w, int b, W go, W ho, W gi, W hi, const W *pl, const W *pr,
+                            const int *mn) {
         int nb = base + K;
         if (nb < cap && nb + (b - d - 1) > cap)
             nb = cap;
         const bool hbm = nb >= cap;
+        if (ballot(hbm) != 0) {
+            // the HBM part holds hstride classes (none when the LDS part is
+            // the whole worst case): a frame past it means a broken invariant
+            const bool over = hbm && (long long)(nb - cap + (b - d - 1)) > hstride;
+            if (over) {
+                if (lk == 0)
+                    fail_lane(kErrStack);
+                return;
+            }
+        }
         int K2 = 0;
 #pragma unroll
         for (int a = 0; a < NR; ++a) {
-            const bool ne = pl[a] != 0 && pr[a] != 0;
+            const bool ne = mn[a] != 0;  // both sides non-empty
             const uint32_t m = sbits(ballot(ne));
             const int at = nb + K2 + below(m);
-            Cls<W> c;
-            c.L = pl[a];
-            c.R = pr[a];
-            if (!hbm)
-                scls[ne ? at : cap] = c;
-            else if (ne)
-                hcls[at - cap] = c;
+            if (ne) {
+                if (!hbm) {
+                    scls[2 * at] = pl[a];
+                    scls[2 * at + 1] = pr[a];
+                } else {
+                    hcls[2 * (at - cap)] = pl[a];
+                    hcls[2 * (at - cap) + 1] = pr[a];
+                }
+            }
             K2 += __builtin_popcount(m);
         }
-        const W vb = (W)1 << v;
-        const W wb = (W)1 << w;
-        for (int c = 1; ballot(c * S < K) != 0; ++c) {
-            const int k = c * S + lk;
-            W ql[NR], qr[NR];
-            const bool in = k < K;
-            const Cls<W> x = cget(base + (in ? k : 0));
-            split(in ? x.L & ~vb : (W)0, in ? x.R & ~wb : (W)0, go, ho, gi, hi, ql, qr);
+        if (ballot(K > S) != 0) {  // (rare) classes past the first S
+            const W vb = (W)1 << v;
+            const W wb = (W)1 << w;
+            for (int c = 1; ballot(c * S < K) != 0; ++c) {
+                const int k = c * S + lk;
+                W ql[NR], qr[NR];
+                const bool in = k < K;
+                const Cls<W> x = cget(base + (in ? k : 0));
+                split(in ? x.L & ~vb : (W)0, in ? x.R & ~wb : (W)0, go, ho, gi, hi, ql, qr);
 #pragma unroll
-            for (int a = 0; a < NR; ++a) {
-                const bool ne = ql[a] != 0 && qr[a] != 0;
-                const uint32_t m = sbits(ballot(ne));
-                const int at = nb + K2 + below(m);
-                Cls<W> y;
-                y.L = ql[a];
-                y.R = qr[a];
-                if (!hbm)
-                    scls[ne ? at : cap] = y;
-                else if (ne)
-                    hcls[at - cap] = y;
-                K2 += __builtin_popcount(m);
+                for (int a = 0; a < NR; ++a) {
+                    const bool ne = ql[a] != 0 && qr[a] != 0;
+                    const uint32_t m = sbits(ballot(ne));
+                    const int at = nb + K2 + below(m);
+                    if (ne) {
+                        if (!hbm) {
+                            scls[2 * at] = ql[a];
+                            scls[2 * at + 1] = qr[a];
+                        } else {
+                            hcls[2 * (at - cap)] = ql[a];
+                            hcls[2 * (at - cap) + 1] = qr[a];
+                        }
+                    }
+                    K2 += __builtin_popcount(m);
+                }
             }
         }
         // the parent frame, with w gone from its partners
@@ -513,32 +601,31 @@ struct SegSearch {
         K = K2;
         d += 1;
         bound = b;
-        flags = kFlagUnmatched;
-        load_regs();
-        select();
+        rrem = 0;
+        flags = kFlagSelect;  // class and v at the next step's reload
     }
 
     // One lock-step search step of every segment that holds a unit.
+    // A segment with no unit, or whose unit has finished, has t = -1,
+    // rrem = 0 and flags = 0, so the phase tests need not look at inst or fin.
     __device__ void step() {
-        const bool act = inst >= 0 && !fin;
-        const bool need_pop = act && rrem == 0 && !(flags & kFlagUnmatched);
+        const bool need_pop = t >= 0 && rrem == 0 && !(flags & (kFlagUnmatched | kFlagSelect));
         if (ballot(need_pop))
             if (need_pop)
                 pop();
-        const bool act2 = inst >= 0 && !fin;
-        const bool need_unm = act2 && rrem == 0 && (flags & kFlagUnmatched);
+        const bool need_unm = rrem == 0 && (flags & kFlagUnmatched);
         if (ballot(need_unm))
             if (need_unm)
                 unmatched();
-        const bool need_eval = inst >= 0 && !fin && rrem != 0;
-        if (ballot(need_eval)) {
-            // statistics, per lane (summed over the wavefront at the end):
-            // children evaluated, lanes holding one of their classes, and the
-            // classes they split
-            c_evals += need_eval && lk == 0 ? 1u : 0u;
-            c_lanes += need_eval && lk < K ? 1u : 0u;
-            c_ncls += need_eval && lk == 0 ? (unsigned)K : 0u;
-            if (need_eval)
+        if (ballot((flags & (kFlagSelect | kFlagLoad)) != 0))
+            reload();
+        const uint64_t ev = ballot(rrem != 0);
+        if (ev) {
+            // statistics (wave-uniform): children evaluated, and the lanes
+            // holding one of their classes in the first pass
+            n_evals += (unsigned)__builtin_popcountll(ev & kLeadLanes);
+            n_lanes += (unsigned)__builtin_popcountll(ev & ballot(lk < K));
+            if (rrem != 0)
                 evaluate();
         }
         n_steps += 1;
@@ -590,11 +677,15 @@ struct SegSearch {
         }
     }
 
-    __device__ void fail(unsigned code) {
-        if (lane == 0)
-            __hip_atomic_store(&P.g->error, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        raise_flag(kFlagStop);
-        stop = true;
+    // A check failed in the lanes that call this (any lanes, also inside a
+    // divergent branch): record the error and stop every search; the
+    // wavefronts leave at their next check().
+    __device__ void fail_lane(unsigned code) {
+        __hip_atomic_store(&P.g->error, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&P.g->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < kRings; ++k)
+            __hip_atomic_fetch_or(&P.g->xcd[k].flag, kFlagStop, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // Give segment j's shallowest open frame's remaining children to the
@@ -655,15 +746,14 @@ struct SegSearch {
         uint8_t *slot = P.slots + idx * (size_t)P.slot_bytes;
         int fK, fd, fbase;
         RecHdr<W> rh;
+        int fsel;
         if (b == jt) {
             fK = of(K, j);
             fd = of(d, j);
             fbase = of(base, j);
+            fsel = of(sel, j);
             rh.v = (uint8_t)of(v, j);
-            rh.sel = (uint8_t)of(sel, j);
             rh.bound = (uint8_t)of(bound, j);
-            rh.lsel = (uint8_t)of(lsel, j);
-            rh.rsel = (uint8_t)of(rsel, j);
         } else {
             const uint4 x = h[b];
             const uint32_t hz = sc(x.z), hw = sc(x.w);
@@ -671,9 +761,11 @@ struct SegSearch {
             fK = (int)((hz >> 16) & 0xFFu);
             fd = (int)(hz >> 24);
             rh.v = (uint8_t)(hw & 0xFFu);
-            const int fsel = (int)((hw >> 8) & 0xFFu);
-            rh.sel = (uint8_t)fsel;
+            fsel = (int)((hw >> 8) & 0xFFu);
             rh.bound = (uint8_t)((hw >> 16) & 0xFFu);
+        }
+        rh.sel = (uint8_t)fsel;
+        {
             const Cls<W> cs = cget_of(j, fbase + fsel);
             rh.lsel = (uint8_t)popc(sc(cs.L));
             rh.rsel = (uint8_t)popc(sc(cs.R));
@@ -795,7 +887,6 @@ struct SegSearch {
         const int ri = sc((int)rh.inst);
         const int rK = sc((int)rh.K), rd = sc((int)rh.d), rv = sc((int)rh.v);
         const int rsel_ = sc((int)rh.sel), rb = sc((int)rh.bound), rf = sc((int)rh.flags);
-        const int rls = sc((int)rh.lsel), rrs = sc((int)rh.rsel);
         const W rr_ = sc((W)rh.rrem);
         const uint16_t *rmap = (const uint16_t *)(slot + rec_map_off<W>());
         const Cls<W> *rcls = (const Cls<W> *)(slot + rec_cls_off<W>());
@@ -829,17 +920,15 @@ struct SegSearch {
             v = rv;
             sel = rsel_;
             bound = rb;
-            lsel = rls;
-            rsel = rrs;
             rrem = rr_;
-            flags = rf & kFlagUnmatched;
-            load_regs();
             if (bound <= inc) {
                 rrem = 0;
                 flags = 0;
             } else if (rf & kFlagFresh) {
-                flags = kFlagUnmatched;
-                select();
+                rrem = 0;
+                flags = kFlagSelect;
+            } else {
+                flags = (rf & kFlagUnmatched) | (rrem != 0 ? kFlagLoad : 0);
             }
         }
         n_pops += 1;
@@ -891,13 +980,8 @@ struct SegSearch {
             }
             bound = ssum(contrib);
             nodes_pend += 1;  // the root
-            if (K == 0 || bound <= inc) {
-                rrem = 0;
-                flags = 0;
-            } else {
-                flags = kFlagUnmatched;
-                select();
-            }
+            rrem = 0;
+            flags = (K == 0 || bound <= inc) ? 0 : kFlagSelect;
         }
         return true;
     }
@@ -982,7 +1066,6 @@ struct SegSearch {
     // Periodic: refresh incumbents, honour limits, keep the queue stocked.
     __device__ void check() {
         since_check = 0;
-        fold_counts();
         unsigned fl = 0;
         unsigned long long hd = 0, tl = 0;
         const bool may_donate = !P.single_wave && P.donate_low >= 0;
@@ -1112,11 +1195,10 @@ struct SegSearch {
         if (busy)
             n_busy += now_ticks() - t_busy0;
         // classes pushed and frames placed in HBM, summed over the segments
-        // (lane 0 of each); children evaluated, their classes and the lanes
-        // holding them, summed over the lanes
+        // (lane 0 of each)
         n_pushed = seg_total(pushed);
         n_hbm = seg_total(n_hbm);
-        fold_counts();
+        n_ncls = seg_total(n_ncls);
         if (lane == 0) {
             a_add64(&P.g->batches, n_steps);
             a_add64(&P.g->children, n_evals);
@@ -1127,7 +1209,7 @@ struct SegSearch {
             a_add64(&P.g->hbm_frames, n_hbm);
             a_add64(&P.g->pushed_classes, n_pushed);
             a_add64(&P.g->sleep_ticks, n_sleep);
-            a_add64(&P.g->node_classes, n_ncls);
+            a_add64(&P.g->node_classes, n_lanes + n_ncls);
         }
         const int mu = wave_max_i(max_used);
         if (lane == 0)
@@ -1140,14 +1222,6 @@ struct SegSearch {
         x = lk == 0 ? x : 0ull;
         return (unsigned long long)(unsigned)wave_sum((int)(unsigned)x) +
                ((unsigned long long)(unsigned)wave_sum((int)(unsigned)(x >> 32)) << 32);
-    }
-    // The per-lane counts into the wavefront's totals (each lane's count is
-    // at most 64 x check_interval, so the 32-bit sums cannot wrap).
-    __device__ void fold_counts() {
-        n_evals += (unsigned)wave_sum((int)c_evals);
-        n_lanes += (unsigned)wave_sum((int)c_lanes);
-        n_ncls += (unsigned)wave_sum((int)c_ncls);
-        c_evals = c_lanes = c_ncls = 0;
     }
 };
 
