@@ -104,7 +104,8 @@ typedef struct {
                                   stack kept in LDS (0: the worst case
                                   m(m+1)/2, m the largest min(nG, nH), or
                                   less if that keeps waves_per_cu from
-                                  fitting in LDS; never below 2m + 1).  The
+                                  fitting in LDS; never below m, so any one
+                                  frame fits at the stack's start).  The
                                   rest of the worst case is in HBM, so a
                                   child always has room: a frame that might
                                   not fit in the LDS part goes to the HBM

@@ -193,10 +193,11 @@ def path(G: dict, H: dict, steps) -> dict:
     return {"bounds": [int(b) for b in bounds], "classes": classes}
 
 
-def extend(G: dict, H: dict, steps, target: int, node_limit: int = 0):
+def extend(G: dict, H: dict, steps, target: int, node_limit: int = 0, with_nodes: bool = False):
     """True/False: does a common induced subgraph of size >= target contain
     the pairs in steps (original ids, a legal sequence of McSplit steps)?
-    None if node_limit stopped the search; raises on an illegal path."""
+    None if node_limit stopped the search; raises on an illegal path.  With
+    with_nodes, returns (answer, nodes the search entered)."""
     lib = _load()
     keep: list = []
     cg, ch = _cgraph(G, keep), _cgraph(H, keep)
@@ -208,7 +209,8 @@ def extend(G: dict, H: dict, steps, target: int, node_limit: int = 0):
                           int(target), int(node_limit), ctypes.byref(nodes))
     if r == -1:
         raise ValueError("illegal path")
-    return None if r == -2 else bool(r)
+    ans = None if r == -2 else bool(r)
+    return (ans, int(nodes.value)) if with_nodes else ans
 
 
 def branch_cost(G: dict, H: dict, steps, v_first: int, incumbent: int,

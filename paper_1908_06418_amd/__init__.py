@@ -202,6 +202,17 @@ class Plan:
         if st < 0:
             raise McsError(st, _last_error())
 
+    def set_goals(self, goals):
+        """mcs_plan_set_goals: goal[i] > 0 asks the next runs only whether
+        instance i has a common induced subgraph of at least goal[i]
+        vertices; 0 is a plain search, < 0 skips the instance."""
+        if len(goals) != len(self.pairs):
+            raise ValueError("one goal per instance")
+        g = (ctypes.c_int32 * len(goals))(*[int(x) for x in goals])
+        st = self.lib.mcs_plan_set_goals(self.handle, g, ctypes.c_void_p(self.stream.cuda_stream))
+        if st < 0:
+            raise McsError(st, _last_error())
+
     def results(self):
         n = len(self.pairs)
         res = (_abi.mcs_result * n)()

@@ -63,6 +63,8 @@ DEV int popc(uint32_t x) { return __builtin_popcount(x); }
 DEV int popc(uint64_t x) { return __builtin_popcountll(x); }
 DEV int ctz(uint32_t x) { return __builtin_ctz(x); }
 DEV int ctz(uint64_t x) { return __builtin_ctzll(x); }
+DEV int clz(uint32_t x) { return __builtin_clz(x); }
+DEV int clz(uint64_t x) { return __builtin_clzll(x); }
 
 DEV int popc(u128 x) { return popc((uint64_t)x) + popc((uint64_t)(x >> 64)); }
 DEV int ctz(u128 x) {

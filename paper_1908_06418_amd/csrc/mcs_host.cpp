@@ -17,6 +17,10 @@ extern "C" void *mcs_internal_seg_kernel(int word_bytes, int directed, int seg_l
 extern "C" void *mcs_internal_static_scratch(size_t *bytes, int *err);
 extern "C" void *mcs_internal_reset_kernel(void);
 
+// LDS allocation granule assumed for gfx950 workgroups (bytes): a multiple
+// of the hardware's unit, so that counting in it never over-commits a CU.
+static constexpr int kLdsGranule = 2048;
+
 namespace {
 
 thread_local std::string g_err;
@@ -559,7 +563,9 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     // The worst case of the depth-first class stack: frame t holds at most
     // m - t classes.
     const int full_cap = std::max(1, p->mmax * (p->mmax + 1) / 2);
-    const int min_cap = std::min(full_cap, 2 * p->mmax + 1);
+    // The LDS part must hold any one frame at its start (a root's classes, a
+    // taken record's), so never fewer than m classes.
+    const int min_cap = std::min(full_cap, std::max(1, p->mmax));
     p->frames = p->mmax + 1;
 
     // launch shape
@@ -635,7 +641,10 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         // still fit in a CU, else the largest LDS part that lets them; the
         // rest of each search's worst case is in HBM.
         p->cap_classes = full_cap;
-        const int share = lds_cu / target_wpc - 64;  // 64: a wave's part of the static LDS
+        // Workgroups of 4 wavefronts; a workgroup's LDS is its wavefronts'
+        // parts plus the kernel's static 256 bytes, allocated in granules.
+        const int blocks_cu = std::max(1, (target_wpc + 3) / 4);
+        const int share = ((lds_cu / blocks_cu) / kLdsGranule * kLdsGranule - 256) / 4;
         if (per_wave(full_cap) > share) {
             const int room = share / nseg - per_wave(0) / nseg - 16;
             p->cap_classes = std::max(min_cap, std::min(full_cap, room / (2 * p->word_bytes)));
@@ -672,6 +681,14 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         (void)hipGetLastError();
         per_cu = 1;
     }
+    {
+        // Never more workgroups than stay resident together: a persistent
+        // grid's extra workgroups would only start once the first ones end.
+        // LDS is counted in whole granules here (measured: three workgroups
+        // of 53,760 + 256 bytes did not stay resident in 160 KB together).
+        const int blk = (p->lds_per_block + 256 + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+        per_cu = std::max(1, std::min(per_cu, lds_cu / blk));
+    }
     p->blocks = per_cu * cus;
     if (p->tun.single_wave)
         p->blocks = 1;
@@ -695,6 +712,12 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     } else if (p->seg_log && p->cap_classes < full_cap) {
         p->hstack_stride = (long long)align256((size_t)full_cap * 2 * p->word_bytes);
         hstacks = (size_t)p->waves * (size_t)nseg;
+    }
+    if (p->seg_log &&
+        (long long)p->cap_classes + p->hstack_stride / (2 * p->word_bytes) > 4095) {
+        // a segment's frame header keeps a frame's first class in 12 bits
+        delete p;
+        return fail(MCS_E_INTERNAL, "class stack indices exceed the frame header's 12 bits");
     }
 
     // workspace layout

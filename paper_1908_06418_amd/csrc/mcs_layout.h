@@ -191,25 +191,24 @@ inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_clas
 
 // LDS of one search of the segmented kernel (one per lane segment), each
 // part 16-byte aligned:
-//   classes   [cap_classes + 1] (L, R) word pairs; the last is a trash slot
+//   classes   [cap_classes] (L, R) word pairs
 //   adjacency [R][arows] words (rows past arows are never read: arows is at
 //             least the largest vertex count of the batch)
-//   mapping   [NB] byte pairs
-//   headers   [frames] frame headers of four 32-bit words
+//   mapping   [frames] byte pairs, one per depth
+//   headers   [frames] frame headers of two 32-bit words
 struct SegLayout {
     int cls, adj, map, hdr, total;
 };
 
 inline constexpr SegLayout seg_layout(int word_bytes, int directed, int cap_classes, int arows,
                                       int frames) {
-    int nb = 8 * word_bytes;
     int rows = directed ? 4 : 2;
     SegLayout L{0, 0, 0, 0, 0};
     L.cls = 0;
-    L.adj = align16((cap_classes + 1) * 2 * word_bytes);
+    L.adj = align16(cap_classes * 2 * word_bytes);
     L.map = align16(L.adj + rows * arows * word_bytes);
-    L.hdr = align16(L.map + 2 * nb);
-    L.total = align16(L.hdr + frames * 16);
+    L.hdr = align16(L.map + 2 * frames);
+    L.total = align16(L.hdr + frames * 8);
     return L;
 }
 

@@ -43,13 +43,20 @@
 
 namespace mcs {
 
-// Frame header of a segment: four 32-bit words (one 16-byte LDS access).
-//   x, y: the remaining partners of v (low and high word)
-//   z:    base (first class, 16 bits) | K << 16 | d << 24
-//   w:    v | sel << 8 | bound << 16 | flags << 24
-// |L_sel| and |R_sel| are not stored: the selected class itself is not
-// changed while its frame is open (only its partner copy is), so they are
-// counted from it when they are needed.
+// Frame header of a segment: two 32-bit words (one 8-byte LDS access).
+//   x: base (first class, 12 bits) | K << 12 | d << 19 | v << 26
+//   y: sel | bound << 6 | unmatched << 13 | lo << 14
+// The remaining partners of v are not stored as a mask: partners are taken
+// in ascending order and a donation from the top frame hands out the lower
+// part of the rest, so they are always the selected class's R_sel above one
+// vertex -- lo, the partner taken last, plus one (kNoPartners: none left) --
+// and, in a unit's bottom frame only, at most hi0 (a register: the unit may
+// have come from a record holding a lower part).  The mask is rebuilt from
+// R_sel when the search returns to the frame.  |L_sel| and |R_sel| are not
+// stored either: the selected class itself is not changed while its frame
+// is open (only its partner copy is), so they are counted from it when they
+// are needed.
+constexpr uint32_t kNoPartners = 127;
 
 // Codes of DevGlobals::error (the host reports MCS_E_INTERNAL).
 constexpr unsigned kErrMapping = 2;  // a mapping larger than the smaller graph
@@ -98,14 +105,14 @@ struct SegSearch {
     int lane, lk, seg;
     // this lane's segment's LDS
     // class stack entry i is the pair of words (L, R) at 2i, 2i + 1
-    lds_p<W> scls;    // [cap + 1]: entries 0 .. cap - 1; the last is a trash slot
+    lds_p<W> scls;    // [cap]: entries 0 .. cap - 1
     glb_p<W> hcls;    // entries cap and above, in HBM (the worst case fits:
                       // frames never straddle the two parts)
     glb_p<W> hwave;   // the wavefront's HBM class stacks (segment j at j * hstride)
     long long hstride;  // classes per segment's HBM part
     W *sadj;          // [NR][arows]
-    uint16_t *smap;   // [NB] g | h << 8 per depth
-    uint4 *shdr;      // [frames]
+    uint16_t *smap;   // [frames] g | h << 8 per depth
+    uint2 *shdr;      // [frames]
     uint8_t *wlds;    // the wavefront's LDS (segment j at j * seg_bytes)
     int seg_bytes;
 
@@ -115,6 +122,7 @@ struct SegSearch {
     int inc_slot, twin, map_off, target;
     int dead_on;      // the instance may be given up as a dead end
     int t, base, K, d, v, sel, bound, flags, inc, d0;
+    int hi0;          // partners of the unit's bottom frame are below this vertex
     W rrem;
     W cL, cR;         // this lane's class of the top frame (class lk)
     uint32_t nodes_pend;  // nodes of the unit not yet added to the instance's count
@@ -153,7 +161,7 @@ struct SegSearch {
         hcls = hwave + 2 * seg * hstride;
         sadj = (W *)(mine + L.adj);
         smap = (uint16_t *)(mine + L.map);
-        shdr = (uint4 *)(mine + L.hdr);
+        shdr = (uint2 *)(mine + L.hdr);
         inst = -1;
         adj_inst = -1;
         inc_slot = 0;
@@ -163,6 +171,7 @@ struct SegSearch {
         dead_on = 0;
         t = -1;
         base = K = d = v = sel = bound = flags = inc = d0 = 0;
+        hi0 = NB;
         rrem = cL = cR = 0;
         nodes_pend = 0;
         fin = false;
@@ -267,40 +276,46 @@ struct SegSearch {
         const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
         return (uint16_t *)(wlds + (size_t)j * seg_bytes + L.map);
     }
-    __device__ uint4 *hdr_of(int j) const {
+    __device__ uint2 *hdr_of(int j) const {
         const SegLayout L = seg_layout((int)sizeof(W), DIR ? 1 : 0, P.cap_classes, arows, P.frames);
-        return (uint4 *)(wlds + (size_t)j * seg_bytes + L.hdr);
+        return (uint2 *)(wlds + (size_t)j * seg_bytes + L.hdr);
     }
 
     // ---- frames ----
 
-    __device__ uint4 pack_hdr() const {
-        uint4 h;
-        h.x = (uint32_t)rrem;
-        h.y = sizeof(W) >= 8 ? (uint32_t)((uint64_t)rrem >> 32) : 0u;
-        h.z = (uint32_t)base | ((uint32_t)K << 16) | ((uint32_t)d << 24);
-        h.w = (uint32_t)v | ((uint32_t)sel << 8) | ((uint32_t)bound << 16) |
-              ((uint32_t)flags << 24);
-        return h;
-    }
-    __device__ void save_hdr() {
-        const uint4 h = pack_hdr();
+    // The header of the top frame, whose partner w has just been taken.
+    __device__ void save_hdr(int w) {
+        uint2 h;
+        h.x = (uint32_t)base | ((uint32_t)K << 12) | ((uint32_t)d << 19) | ((uint32_t)v << 26);
+        h.y = (uint32_t)sel | ((uint32_t)bound << 6) |
+              ((uint32_t)(flags & kFlagUnmatched) << 13) | ((uint32_t)(w + 1) << 14);
         if (lk == 0)
             shdr[t] = h;
     }
+    // The partners of R above lo (the last partner taken, plus one) and
+    // below hi.
+    DEV W partner_range(W R, uint32_t lo1, int hi) {
+        if (lo1 >= (uint32_t)NB)
+            return (W)0;
+        W r = R & ~(((W)1 << lo1) - 1);
+        if (hi < NB)
+            r &= ((W)1 << hi) - 1;
+        return r;
+    }
+    // Header fields of frame i; the remaining partners are rebuilt from
+    // R_sel, which stays in the class stack while the frame is open.
     __device__ void read_hdr(int i) {
-        const uint4 h = shdr[i];
-        W r = (W)h.x;
-        if constexpr (sizeof(W) >= 8)
-            r |= (W)h.y << 32;
-        rrem = r;
-        base = (int)(h.z & 0xFFFFu);
-        K = (int)((h.z >> 16) & 0xFFu);
-        d = (int)(h.z >> 24);
-        v = (int)(h.w & 0xFFu);
-        sel = (int)((h.w >> 8) & 0xFFu);
-        bound = (int)((h.w >> 16) & 0xFFu);
-        flags = (int)(h.w >> 24);
+        const uint2 h = shdr[i];
+        base = (int)(h.x & 0xFFFu);
+        K = (int)((h.x >> 12) & 0x7Fu);
+        d = (int)((h.x >> 19) & 0x7Fu);
+        v = (int)(h.x >> 26);
+        sel = (int)(h.y & 0x3Fu);
+        bound = (int)((h.y >> 6) & 0x7Fu);
+        flags = (int)((h.y >> 13) & 1u);
+        const uint32_t lo1 = (h.y >> 14) & 0x7Fu;
+        rrem = lo1 < (uint32_t)NB ? partner_range(cget(base + sel).R, lo1, i == 0 ? hi0 : NB)
+                                  : (W)0;
     }
 
     // Class lk of the top frame into registers.
@@ -337,6 +352,8 @@ struct SegSearch {
         sel = (int)(mk & 0xFFu);
         rrem = cget(base + sel).R;
         flags = kFlagUnmatched;
+        if (t == 0)
+            hi0 = NB;  // a unit's bottom frame with a new class: all of its partners
     }
 
     // ---- incumbent ----
@@ -583,7 +600,7 @@ struct SegSearch {
             }
         }
         // the parent frame, with w gone from its partners
-        save_hdr();
+        save_hdr(w);
         if (lk == 0)
             smap[d] = (uint16_t)(v | (w << 8));
         sync_frame(hbm);
@@ -692,19 +709,22 @@ struct SegSearch {
     // queue (the frame keeps the rest; the top frame keeps half).
     __device__ void donate(int j) {
         const int jt = of(t, j);
-        const uint4 *h = hdr_of(j);
+        const uint2 *h = hdr_of(j);
         int b = -1;
         W grr = 0;
         int gfl = 0;
         for (int i = 0; i < jt; ++i) {
-            const uint4 x = h[i];
-            const uint32_t hz = sc(x.z), hw = sc(x.w);
-            W r = (W)sc(x.x);
-            if constexpr (sizeof(W) >= 8)
-                r |= (W)sc(x.y) << 32;
-            const int f = (int)(hw >> 24);
-            if ((int)(hz >> 24) > P.donate_depth)
+            const uint2 x = h[i];
+            const uint32_t hx = sc(x.x), hy = sc(x.y);
+            if ((int)((hx >> 19) & 0x7Fu) > P.donate_depth)
                 return;  // deeper frames hold too little work to hand out
+            const uint32_t lo1 = (hy >> 14) & 0x7Fu;
+            const int f = (int)((hy >> 13) & 1u);
+            W r = 0;
+            if (lo1 < (uint32_t)NB) {
+                const int fb = (int)(hx & 0xFFFu), fs = (int)(hy & 0x3Fu);
+                r = partner_range(sc(cget_of(j, fb + fs).R), lo1, i == 0 ? of(hi0, j) : NB);
+            }
             if (r != 0 || (f & kFlagUnmatched)) {
                 b = i;
                 grr = r;
@@ -720,14 +740,16 @@ struct SegSearch {
                 return;
             const int n = popc(jr);
             if (n >= 2) {
-                W r = jr, kept = 0;
-                for (int c = 0; c < n - n / 2; ++c) {
-                    kept |= r & (~r + 1);
+                // the record takes the lower n/2 partners, the frame keeps
+                // the upper ones (so its partners stay R_sel above a vertex)
+                W r = jr, low = 0;
+                for (int c = 0; c < n / 2; ++c) {
+                    low |= r & (~r + 1);
                     r &= r - 1;
                 }
-                grr = r;
+                grr = low;
                 gfl = jf & kFlagUnmatched;
-                keep_r = kept;
+                keep_r = r;
             } else if (n == 1 && (jf & kFlagUnmatched)) {
                 grr = 0;
                 gfl = kFlagUnmatched;
@@ -755,14 +777,14 @@ struct SegSearch {
             rh.v = (uint8_t)of(v, j);
             rh.bound = (uint8_t)of(bound, j);
         } else {
-            const uint4 x = h[b];
-            const uint32_t hz = sc(x.z), hw = sc(x.w);
-            fbase = (int)(hz & 0xFFFFu);
-            fK = (int)((hz >> 16) & 0xFFu);
-            fd = (int)(hz >> 24);
-            rh.v = (uint8_t)(hw & 0xFFu);
-            fsel = (int)((hw >> 8) & 0xFFu);
-            rh.bound = (uint8_t)((hw >> 16) & 0xFFu);
+            const uint2 x = h[b];
+            const uint32_t hx = sc(x.x), hy = sc(x.y);
+            fbase = (int)(hx & 0xFFFu);
+            fK = (int)((hx >> 12) & 0x7Fu);
+            fd = (int)((hx >> 19) & 0x7Fu);
+            rh.v = (uint8_t)(hx >> 26);
+            fsel = (int)(hy & 0x3Fu);
+            rh.bound = (uint8_t)((hy >> 6) & 0x7Fu);
         }
         rh.sel = (uint8_t)fsel;
         {
@@ -797,11 +819,10 @@ struct SegSearch {
                 flags = 0;
             }
         } else if (lane == 0) {
-            uint4 *hw = hdr_of(j);
-            uint4 x = hw[b];
-            x.x = 0;
-            x.y = 0;
-            x.w &= 0x00FFFFFFu;  // flags = 0
+            // the frame keeps nothing: no partners, no unmatched child
+            uint2 *hw = hdr_of(j);
+            uint2 x = hw[b];
+            x.y = (x.y & ~((0x7Fu << 14) | (1u << 13))) | (kNoPartners << 14);
             hw[b] = x;
         }
         wave_sync();
@@ -921,6 +942,7 @@ struct SegSearch {
             sel = rsel_;
             bound = rb;
             rrem = rr_;
+            hi0 = rr_ != 0 ? NB - clz(rr_) : 0;  // the record's partners end at its highest
             if (bound <= inc) {
                 rrem = 0;
                 flags = 0;
