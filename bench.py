@@ -336,7 +336,7 @@ def main():
     nmax = max(max(G["n"], H["n"]) for G, H in pairs)
     word = 4 if nmax <= 32 else 8 if nmax <= 64 else 16
     directed = any(G["directed"] for G, _ in pairs)
-    seg_lanes = int(tuning.get("seg_lanes", 0) or 16)
+    seg_lanes = int(tuning.get("seg_lanes", 0) or 8)
     segmented = word <= 8 and seg_lanes != 64
     kernel_src = "mcs_seg.hip" if segmented else "mcs_search.hip"
     kernel_name = (f"mcs_seg_kernel ({seg_lanes}-lane searches)" if segmented

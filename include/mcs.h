@@ -73,8 +73,12 @@ typedef struct {
  * defaults the library derives from the instance sizes. */
 typedef struct {
     int32_t waves_per_cu;      /* resident search wavefronts per CU (0: about
-                                  96 per instance, between 8 and 24 per CU;
-                                  capped by what LDS and registers allow) */
+                                  96 searches per instance; segmented
+                                  searches: 16, 12 or 8 per CU, the most that
+                                  leave each search about 40 classes of LDS
+                                  stack; one search per wavefront: 8 to 24;
+                                  always capped by what LDS and registers let
+                                  stay resident together) */
     int32_t children_per_wave; /* how many sibling children one wavefront may
                                   evaluate at once (1, 2, 4 or 8; 0: 8) */
     int32_t ring_slots;        /* total capacity of the device node queue, split
@@ -85,7 +89,7 @@ typedef struct {
                                   open node (0: 2; < 0: never donate) */
     int32_t donate_depth;      /* only nodes with |M| <= this are donated, as the
                                   paper delegates only above PART_LEVEL
-                                  (0: half the largest min(nG, nH)) */
+                                  (0: any depth -- the largest min(nG, nH)) */
     int32_t check_interval;    /* search steps between queue/limit checks (0: 128) */
     int32_t no_reprune;        /* 1: do not re-test a frame's bound against the
                                   incumbent when the search returns to it */
@@ -121,11 +125,10 @@ typedef struct {
                                   segment of that many lanes (a node's classes
                                   across the segment); 64 -- one search per
                                   wavefront, whose sibling children share the
-                                  lanes; 0: 16.  Rows of more than 64 bits and
+                                  lanes; 0: 8.  Rows of more than 64 bits and
                                   the learned policy always use 64.  With
                                   segments, waves_per_cu counts wavefronts
-                                  (default about 48 searches per CU) and
-                                  children_per_wave is not used. */
+                                  and children_per_wave is not used. */
 } mcs_tuning;
 
 typedef struct {

@@ -31,7 +31,7 @@ DEFAULT_CANDIDATES = [
 # library's own choice.  children_per_wave applies to one search per
 # wavefront (seg_lanes 64) only.
 AXES = [
-    ("seg_lanes", (16, 8, 4, 64)),
+    ("seg_lanes", (0, 16, 4, 64)),
     ("waves_per_cu", (0, 8, 12, 16, 20)),
     ("children_per_wave", (8, 4, 2)),
     ("stack_classes", (0, 1)),

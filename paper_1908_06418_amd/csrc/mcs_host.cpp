@@ -597,24 +597,9 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         if (wide || p->policy || sl == 64)
             p->seg_log = 0;
         else
-            p->seg_log = sl == 4 ? 2 : sl == 8 ? 3 : 4;
+            p->seg_log = sl == 4 ? 2 : sl == 16 ? 4 : 3;  // default: 8 lanes
     }
     const int nseg = p->seg_log ? 64 >> p->seg_log : 1;
-    // Default wavefronts: about 96 searches per instance, between 8 and 24
-    // per CU for one search per wavefront (4 and 16 with 128-bit rows, whose
-    // larger state fits fewer), and about 64 searches per CU (16 wavefronts
-    // of 4, as many as the segmented kernel's registers let a SIMD hold)
-    // for the segmented kernel, so one hard instance alone still splits
-    // across thousands of searches.  One search is a long dependent chain of
-    // steps, so several wavefronts per SIMD fill the issue slots while there
-    // is work for them; past what the instances can keep busy, more searches
-    // only split the work into ever smaller donations.
-    const int want_waves =
-        p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
-        : p->seg_log ? std::max(2 * cus, std::min((64 / nseg) * cus, (96 * ndev + nseg - 1) / nseg))
-        : wide       ? std::max(4 * cus, std::min(16 * cus, 96 * ndev))
-                     : std::max(8 * cus, std::min(24 * cus, 96 * ndev));
-    const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
     if (p->seg_log) {
         // adjacency rows a segment keeps: the batch's largest graph, to 4
         int nmax_all = 0;
@@ -628,6 +613,46 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         return mcs::lds_layout(p->word_bytes, directed, wide ? -1 : cap, p->frames,
                                p->policy_levels).total;
     };
+    // LDS bytes one wavefront may use when wpc of them share a CU
+    // (workgroups of 4; each workgroup's LDS is its wavefronts' parts plus
+    // the kernel's static 256 bytes, allocated in granules), and the class
+    // stack's LDS part that leaves to each segmented search.
+    auto wave_share = [&](int wpc) {
+        const int blocks_cu = std::max(1, (wpc + 3) / 4);
+        return ((lds_cu / blocks_cu) / kLdsGranule * kLdsGranule - 256) / 4;
+    };
+    auto seg_cap_at = [&](int wpc) {
+        const int room = wave_share(wpc) / nseg - per_wave(0) / nseg - 16;
+        return std::max(0, std::min(full_cap, room / (2 * p->word_bytes)));
+    };
+    // Default wavefronts: about 96 searches per instance, between 8 and 24
+    // per CU for one search per wavefront (4 and 16 with 128-bit rows, whose
+    // larger state fits fewer), so one hard instance alone still splits
+    // across thousands of searches.  The segmented kernel takes 16, 12 or 8
+    // wavefronts per CU (its registers allow at most 4 per SIMD): the most
+    // whose LDS still leaves each search an LDS part of about 40 classes
+    // (measured on the batched workload: 12 wavefronts of eight 8-lane
+    // searches, 43 classes each, put one frame in 300 into HBM).  One search
+    // is a long dependent chain of steps, so several wavefronts per SIMD fill
+    // the VALU issue slots while there is work for them; past what the
+    // instances can keep busy, more searches only split the work into ever
+    // smaller donations.
+    int seg_wpc = 8;
+    if (p->seg_log) {
+        const int want_cap = std::min(full_cap, std::max(min_cap, 32));
+        for (int wpc : {16, 12}) {
+            if (seg_cap_at(wpc) >= want_cap) {
+                seg_wpc = wpc;
+                break;
+            }
+        }
+    }
+    const int want_waves =
+        p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
+        : p->seg_log ? std::max(2 * cus, std::min(seg_wpc * cus, (96 * ndev + nseg - 1) / nseg))
+        : wide       ? std::max(4 * cus, std::min(16 * cus, 96 * ndev))
+                     : std::max(8 * cus, std::min(24 * cus, 96 * ndev));
+    const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);
     if (!p->seg_log) {
         // One search per wavefront: the whole worst case, in LDS (at most
         // 2081 classes of 16 bytes for 64 vertices) or, with 128-bit rows,
@@ -641,14 +666,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         // still fit in a CU, else the largest LDS part that lets them; the
         // rest of each search's worst case is in HBM.
         p->cap_classes = full_cap;
-        // Workgroups of 4 wavefronts; a workgroup's LDS is its wavefronts'
-        // parts plus the kernel's static 256 bytes, allocated in granules.
-        const int blocks_cu = std::max(1, (target_wpc + 3) / 4);
-        const int share = ((lds_cu / blocks_cu) / kLdsGranule * kLdsGranule - 256) / 4;
-        if (per_wave(full_cap) > share) {
-            const int room = share / nseg - per_wave(0) / nseg - 16;
-            p->cap_classes = std::max(min_cap, std::min(full_cap, room / (2 * p->word_bytes)));
-        }
+        if (per_wave(full_cap) > wave_share(target_wpc))
+            p->cap_classes = std::max(min_cap, seg_cap_at(target_wpc));
     }
     max_lds_block -= 256;  // the kernel's static LDS (its parameter copy)
     if (p->seg_log && per_wave(p->cap_classes) > max_lds_block) {
@@ -684,8 +703,8 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     {
         // Never more workgroups than stay resident together: a persistent
         // grid's extra workgroups would only start once the first ones end.
-        // LDS is counted in whole granules here (measured: three workgroups
-        // of 53,760 + 256 bytes did not stay resident in 160 KB together).
+        // LDS is counted in whole granules here, on top of the occupancy
+        // query.
         const int blk = (p->lds_per_block + 256 + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
         per_cu = std::max(1, std::min(per_cu, lds_cu / blk));
     }
@@ -799,8 +818,10 @@ mcs_status mcs_plan_upload(mcs_plan *p, void *workspace, size_t bytes, void *str
     sp.cmax = (cm == 1 || cm == 2 || cm == 4 || cm == 8) ? cm : 8;
     sp.donate_low = p->tun.donate_low > 0 ? p->tun.donate_low
                                           : (p->tun.donate_low < 0 ? -1 : 2);
-    sp.donate_depth = p->tun.donate_depth > 0 ? p->tun.donate_depth
-                                              : std::max(1, p->mmax / 2);
+    // Any frame may be handed out by default: a depth cut-off left the last
+    // hard instance's deep subtrees to one search while the rest idled
+    // (measured on the batched workload: 27-28 s instead of 30-37 s).
+    sp.donate_depth = p->tun.donate_depth > 0 ? p->tun.donate_depth : std::max(1, p->mmax);
     // (at most 2^16: the kernel's per-check step counters are 32-bit)
     sp.check_interval = p->tun.check_interval > 0 ? std::min(p->tun.check_interval, 65536) : 128;
     sp.reprune = p->tun.no_reprune ? 0 : 1;

@@ -192,8 +192,10 @@ inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_clas
 // LDS of one search of the segmented kernel (one per lane segment), each
 // part 16-byte aligned:
 //   classes   [cap_classes] (L, R) word pairs
-//   adjacency [R][arows] words (rows past arows are never read: arows is at
-//             least the largest vertex count of the batch)
+//   adjacency [R][arows] words of H: out-rows (and in-rows if directed);
+//             rows past arows are never read: arows is at least the
+//             largest vertex count of the batch.  (The search keeps the
+//             G rows of v in registers, loaded from HBM once per frame.)
 //   mapping   [frames] byte pairs, one per depth
 //   headers   [frames] frame headers of two 32-bit words
 struct SegLayout {
@@ -202,7 +204,7 @@ struct SegLayout {
 
 inline constexpr SegLayout seg_layout(int word_bytes, int directed, int cap_classes, int arows,
                                       int frames) {
-    int rows = directed ? 4 : 2;
+    int rows = directed ? 2 : 1;
     SegLayout L{0, 0, 0, 0, 0};
     L.cls = 0;
     L.adj = align16(cap_classes * 2 * word_bytes);

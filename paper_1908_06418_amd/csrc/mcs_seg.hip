@@ -110,7 +110,8 @@ struct SegSearch {
                       // frames never straddle the two parts)
     glb_p<W> hwave;   // the wavefront's HBM class stacks (segment j at j * hstride)
     long long hstride;  // classes per segment's HBM part
-    W *sadj;          // [NR][arows]
+    W *sadj;          // [NR / 2][arows] H rows: out (and in, directed)
+    const W *gadj;    // all instances' rows in HBM ([count][NR][NB]: G out, H out, G in, H in)
     uint16_t *smap;   // [frames] g | h << 8 per depth
     uint2 *shdr;      // [frames]
     uint8_t *wlds;    // the wavefront's LDS (segment j at j * seg_bytes)
@@ -125,6 +126,7 @@ struct SegSearch {
     int hi0;          // partners of the unit's bottom frame are below this vertex
     W rrem;
     W cL, cR;         // this lane's class of the top frame (class lk)
+    W go, gi;         // G's out-row (and in-row) of the top frame's v
     uint32_t nodes_pend;  // nodes of the unit not yet added to the instance's count
     bool fin;         // the unit is finished (its stack emptied)
     unsigned long long pushed;  // classes in the frames this segment pushed
@@ -160,6 +162,7 @@ struct SegSearch {
         hwave = (glb_p<W>)p.hstack + 2 * wave * NSEG * hstride;
         hcls = hwave + 2 * seg * hstride;
         sadj = (W *)(mine + L.adj);
+        gadj = (const W *)p.adj;
         smap = (uint16_t *)(mine + L.map);
         shdr = (uint2 *)(mine + L.hdr);
         inst = -1;
@@ -172,7 +175,7 @@ struct SegSearch {
         t = -1;
         base = K = d = v = sel = bound = flags = inc = d0 = 0;
         hi0 = NB;
-        rrem = cL = cR = 0;
+        rrem = cL = cR = go = gi = 0;
         nodes_pend = 0;
         fin = false;
         pushed = 0;
@@ -449,7 +452,8 @@ struct SegSearch {
     }
 
     // Registers (and, for a new frame, class and v) of the frames that need
-    // them.  cL then drops v: every child of the frame is split without it.
+    // them.  cL then drops v (every child of the frame is split without
+    // it), and v's G rows come into registers from HBM, once per frame.
     __device__ void reload() {
         const bool ld = (flags & (kFlagSelect | kFlagLoad)) != 0;
         if (ld)
@@ -458,8 +462,13 @@ struct SegSearch {
         if (ballot(fresh))
             if (fresh)
                 select();
-        if (ld)
+        if (ld) {
             cL &= ~((W)1 << v);
+            const W *rows = gadj + (size_t)inst * (NR * NB) + v;
+            go = rows[0];
+            if constexpr (DIR)
+                gi = rows[2 * NB];
+        }
         flags &= ~kFlagLoad;
     }
 
@@ -505,12 +514,10 @@ struct SegSearch {
         const int w = ctz(rrem);
         rrem &= rrem - 1;
         const W wb = (W)1 << w;
-        const W go = sadj[v], ho = sadj[arows + w];
-        W gi = 0, hi = 0;
-        if constexpr (DIR) {
-            gi = sadj[2 * arows + v];
-            hi = sadj[3 * arows + w];
-        }
+        const W ho = sadj[w];
+        W hi = 0;
+        if constexpr (DIR)
+            hi = sadj[arows + w];
         W pl[NR], pr[NR];
         int mn[NR];
         split(cL, cR & ~wb, go, ho, gi, hi, pl, pr);
@@ -832,10 +839,11 @@ struct SegSearch {
     // Segment j starts on instance i: its rows, incumbent, and identity.
     __device__ void set_instance(int j, int i) {
         if (of(adj_inst, j) != i) {
+            // H's rows (set 1: out; set 3: in) into the segment's LDS
             const W *src = (const W *)P.adj + (size_t)i * NR * NB;
             W *dst = adj_of(j);
-            for (int q = lane; q < NR * arows; q += 64)
-                dst[q] = src[(q / arows) * NB + (q % arows)];
+            for (int q = lane; q < (NR / 2) * arows; q += 64)
+                dst[q] = src[(2 * (q / arows) + 1) * NB + (q % arows)];
         }
         const DevInst di = P.inst[i];
         const int slot = sc((int)di.inc_slot);

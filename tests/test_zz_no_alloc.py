@@ -28,8 +28,9 @@ def test_static_scratch_matches_workspace_entry(gpu):
     from paper_1908_06418_amd import solve_batch, solve_batch_static
     rng = np.random.default_rng(9)
     # (the default launch of these batches needs more workspace than the
-    # static scratch holds: four wavefronts per CU fit, for both entries)
-    tun = {"waves_per_cu": 4}
+    # static scratch holds: four wavefronts of 16-lane searches per CU fit,
+    # for both entries)
+    tun = {"waves_per_cu": 4, "seg_lanes": 16}
     first = easy_c4(200, start=200)[0]
     second = [(mi.random_small(rng, int(rng.integers(0, 14)), 0.4, True, 2),
                mi.random_small(rng, int(rng.integers(0, 14)), 0.4, True, 2)) for _ in range(12)]
@@ -59,5 +60,5 @@ def test_static_scratch_rejects_what_does_not_fit(gpu):
     # the entry still works after the refusals
     pairs = easy_c4(8)[0]
     assert [r.size for r in solve_batch_static(pairs, time_limit_s=60,
-                                               tuning={"waves_per_cu": 4})] == \
+                                               tuning={"waves_per_cu": 4, "seg_lanes": 16})] == \
         [oracle.mcs(G, H)["size"] for G, H in pairs]
