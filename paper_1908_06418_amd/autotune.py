@@ -203,3 +203,46 @@ def tune_and_store(pairs, sample=None, path: str | None = None, staged: bool = F
     data[workload_key(pairs)] = entry
     save_cache(data, path)
     return best
+
+
+# Named synthetic workloads the command line below can tune (the generators
+# of mcs_instances, at the shapes bench.py measures).
+def _named_workload(name: str):
+    import mcs_instances as mi
+    return {
+        "c2_n30": (lambda: mi.pairs_c2(ns=(30,)),
+                   "60 undirected pairs G(30,p), p in {0.1,0.3,0.5}"),
+        "c3": (lambda: mi.pairs_c3(), "60 directed labelled pairs n in {40,50,60}, p=0.1"),
+        "c4": (lambda: mi.pairs_c4(4096),
+               "the 4096 batched pairs, n ~ U{10..35}, p ~ U[0.05,0.5)"),
+    }[name]
+
+
+def main(argv=None) -> int:
+    """python -m paper_1908_06418_amd.autotune WORKLOAD [--out PATH]:
+    staged tuning of a named workload on the GPU, stored under its workload
+    class (in the shipped table unless --out names another file)."""
+    import argparse
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("workload", choices=("c2_n30", "c3", "c4"))
+    ap.add_argument("--out", default=SHIPPED)
+    ap.add_argument("--time-limit", type=float, default=120.0)
+    args = ap.parse_args(argv)
+    factory, desc = _named_workload(args.workload)
+    pairs = factory()
+
+    def log(m):
+        print(json.dumps({"tuning": m["tuning"], "kernel_ms": round(m["kernel_ms"], 3),
+                          "proven": m["proven"]}), flush=True)
+
+    stages = sum(len(staged_candidates({}, a, v)) for a, v in AXES)
+    best = tune_and_store(pairs, path=args.out, staged=True, time_limit_s=args.time_limit,
+                          log=log, note=f"MI355X, {desc}; staged tuning, about {stages} "
+                                        "candidates, one launch each")
+    print(json.dumps({"workload": args.workload, "key": workload_key(pairs),
+                      "tuning": best["tuning"], "kernel_ms": best["kernel_ms"]}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

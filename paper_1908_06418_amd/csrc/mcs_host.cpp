@@ -626,17 +626,18 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         return std::max(0, std::min(full_cap, room / (2 * p->word_bytes)));
     };
     // Default wavefronts: about 96 searches per instance, between 8 and 24
-    // per CU for one search per wavefront (4 and 16 with 128-bit rows, whose
+    // per CU, for one search per wavefront (4 and 16 with 128-bit rows, whose
     // larger state fits fewer), so one hard instance alone still splits
-    // across thousands of searches.  The segmented kernel takes 16, 12 or 8
-    // wavefronts per CU (its registers allow at most 4 per SIMD): the most
-    // whose LDS still leaves each search an LDS part of about 40 classes
-    // (measured on the batched workload: 12 wavefronts of eight 8-lane
-    // searches, 43 classes each, put one frame in 300 into HBM).  One search
-    // is a long dependent chain of steps, so several wavefronts per SIMD fill
-    // the VALU issue slots while there is work for them; past what the
-    // instances can keep busy, more searches only split the work into ever
-    // smaller donations.
+    // across thousands of searches.  The segmented kernel takes about 256
+    // searches per instance, at least 8 wavefronts per CU and at most 16, 12
+    // or 8 (its registers allow 4 per SIMD): the most whose LDS still leaves
+    // each search an LDS part of about 32 classes.  One search is a long
+    // dependent chain of steps, so several wavefronts per SIMD fill the VALU
+    // issue slots while there is work for them; past what the instances can
+    // keep busy, more searches only split the work into ever smaller
+    // donations (measured: 60 pairs G(30, p) take 439 ms at 8 wavefronts per
+    // CU, 465 ms at 16 and 795 ms at 2.8; the 4,096 batched pairs 23.5 s at
+    // 16 and 27-28 s at 12).
     int seg_wpc = 8;
     if (p->seg_log) {
         const int want_cap = std::min(full_cap, std::max(min_cap, 32));
@@ -649,7 +650,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     }
     const int want_waves =
         p->tun.waves_per_cu > 0 ? p->tun.waves_per_cu * cus
-        : p->seg_log ? std::max(2 * cus, std::min(seg_wpc * cus, (96 * ndev + nseg - 1) / nseg))
+        : p->seg_log ? std::min(seg_wpc * cus, std::max(8 * cus, (256 * ndev + nseg - 1) / nseg))
         : wide       ? std::max(4 * cus, std::min(16 * cus, 96 * ndev))
                      : std::max(8 * cus, std::min(24 * cus, 96 * ndev));
     const int target_wpc = p->tun.single_wave ? 1 : std::max(1, (want_waves + cus - 1) / cus);

@@ -296,3 +296,61 @@ def test_c5_learned_vs_degree_report(gpu):
     out["policy_mode"] = mode
     _say("c5 report: " + json.dumps(out))
     write_report("c5_learned_vs_degree.json", out)
+
+
+# Arithmetic of the 16 -> 64 -> 64 -> 1 network per row, in FLOPs (a
+# multiply-add counts two): forward 2 (16*64 + 64*64 + 64); the gradient adds
+# the backward products (64*64 and 16*64 weight gradients, the 64*64 input
+# gradient of the middle layer, and the 64-wide output layer's).
+FWD_FLOP = 2 * (16 * 64 + 64 * 64 + 64)
+GRAD_FLOP = FWD_FLOP + 2 * (64 * 64 + 16 * 64 + 64 * 64 + 64 + 64)
+PEAK_FP16_MFMA = 2.5e15   # dense, MI355X
+PEAK_FP32_VECTOR = 157.3e12
+
+
+def test_policy_kernel_timing_report(gpu):
+    """The network's forward and gradient kernels timed on the stored
+    training rows and on a large synthetic batch, against the FP16 MFMA roof
+    (and the FP32 vector roof their FMAs actually run on).  Report only:
+    training is a few hundred such steps on tens of thousands of rows, far
+    below a second, so it is not what bounds the learned ordering."""
+    import torch
+    from paper_1908_06418_amd.policy import Policy
+    X, y, _ = _training_set()
+    rng = np.random.default_rng(3)
+    big = rng.random((1 << 20, 16)).astype(np.float16)
+    bigy = (rng.random(1 << 20) < 0.5).astype(np.float32)
+    P = Policy(seed=1)
+    out = {}
+    for name, xs, ys in (("training_rows", X.astype(np.float16), y.astype(np.float32)),
+                         ("synthetic_1M", big, bigy)):
+        xh = torch.from_numpy(np.ascontiguousarray(xs)).cuda()
+        yt = torch.from_numpy(np.ascontiguousarray(ys)).cuda()
+        rows = int(xh.shape[0])
+        for _ in range(3):
+            P.forward(xh)
+            P.grad(xh, yt)
+        torch.cuda.synchronize()
+        reps = 20
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            P.forward(xh)
+        e[1].record()
+        for _ in range(reps):
+            P.grad(xh, yt)
+        e[2].record()
+        torch.cuda.synchronize()
+        f_ms = e[0].elapsed_time(e[1]) / reps
+        g_ms = e[1].elapsed_time(e[2]) / reps
+        ftf = rows * FWD_FLOP / (f_ms * 1e-3) / 1e12
+        gtf = rows * GRAD_FLOP / (g_ms * 1e-3) / 1e12
+        out[name] = {"rows": rows, "forward_ms": f_ms, "grad_ms": g_ms,
+                     "forward_tflops": ftf, "grad_tflops": gtf,
+                     "forward_frac_fp16_mfma": ftf * 1e12 / PEAK_FP16_MFMA,
+                     "grad_frac_fp16_mfma": gtf * 1e12 / PEAK_FP16_MFMA,
+                     "forward_frac_fp32_vector": ftf * 1e12 / PEAK_FP32_VECTOR,
+                     "grad_frac_fp32_vector": gtf * 1e12 / PEAK_FP32_VECTOR}
+        assert f_ms > 0 and g_ms > 0
+    _say("policy kernel timing: " + json.dumps(out))
+    write_report("policy_kernel_timing.json", out)
