@@ -1,7 +1,7 @@
 """Autotuner for the search kernel's launch and scheduling knobs.
 
 The knobs (mcs_tuning in include/mcs.h) change only speed, never answers:
-the search layout (searches of 8 or 16 lanes, or one per wavefront, and then
+the search layout (searches of 4, 8 or 16 lanes, or one per wavefront, and then
 how many sibling children a wavefront evaluates at once), resident
 wavefronts per CU, the LDS part of each search's class stack, the node
 queue's depth, how many records each XCD's queue ring is kept stocked with,
