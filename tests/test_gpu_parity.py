@@ -146,10 +146,16 @@ def test_random_sweep_batched(gpu, directed, nlab, lanes):
     assert all(r.optimal for r in res)
 
 
-def test_edge_cases(gpu):
+@pytest.mark.parametrize("lanes", LAYOUTS)
+def test_edge_cases(gpu, lanes):
+    """Empty and complete graphs, an empty side, 31/33 and 64 vertices,
+    relabelled copies, an induced subgraph, and labelled pairs whose root
+    has more classes than a segment has lanes -- in every search layout."""
     rng = np.random.default_rng(5)
     g64 = mi.random_small(rng, 64, 0.5)
     g40 = mi.random_small(rng, 40, 0.2)
+    lab = mi.random_small(rng, 40, 0.3, False, 20)
+    lab2 = mi.random_small(rng, 36, 0.3, True, 24)
     cases = [
         (mi.empty_graph(0), mi.empty_graph(0), 0),
         (mi.empty_graph(0), mi.complete_graph(5), 0),
@@ -162,10 +168,12 @@ def test_edge_cases(gpu):
         (mi.empty_graph(33), mi.empty_graph(31), 31),
         (g64, mi.permute(g64, list(rng.permutation(64))), 64),
         (g40, mi.induced(g40, list(range(0, 40, 2))), 20),
+        (lab, mi.permute(lab, list(rng.permutation(40))), 40),
+        (lab2, mi.permute(lab2, list(rng.permutation(36))), 36),
     ]
     pairs = [(G, H) for G, H, _ in cases]
-    _say("edge cases")
-    res = _solve_batch(pairs, time_limit_s=60)
+    _say(f"edge cases, {lanes}-lane layout")
+    res = _solve_batch(pairs, time_limit_s=60, tuning={"seg_lanes": lanes})
     _check(pairs, res, [s for _, _, s in cases])
     assert all(r.optimal for r in res)
 
