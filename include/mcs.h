@@ -47,7 +47,10 @@ typedef enum {
     MCS_E_TOO_LARGE = -2, /* a graph has more than MCS_MAX_N vertices */
     MCS_E_DEVICE = -3,    /* a HIP call or the search kernel failed */
     MCS_E_WORKSPACE = -4, /* workspace missing, too small or misaligned */
-    MCS_E_INTERNAL = -5   /* an internal capacity check fired (a bug) */
+    MCS_E_INTERNAL = -5   /* an internal check fired (a bug): a capacity check, a
+                             mapping larger than the smaller graph, or a frame
+                             past the class stack's worst case; the search
+                             stops instead of writing out of bounds */
 } mcs_status;
 
 #define MCS_MAX_N 128
@@ -253,8 +256,8 @@ mcs_status mcs_plan_run(mcs_plan *plan, void *stream);
 
 /* Wait for the last run, copy results back and map them to original vertex
  * ids.  results has one entry per instance.  Returns MCS_OK, MCS_LIMIT, or
- * an error (MCS_E_DEVICE; MCS_E_INTERNAL if the kernel flagged a capacity
- * fault). */
+ * an error (MCS_E_DEVICE; MCS_E_INTERNAL if the kernel flagged a broken
+ * invariant). */
 mcs_status mcs_plan_results(mcs_plan *plan, mcs_result *results, void *stream);
 
 /* Statistics of the last run (valid after mcs_plan_results). */

@@ -484,29 +484,48 @@ def test_ordering_report(gpu):
 _FIXED_INC = {}
 
 
-def _fixed_incumbent_case():
-    """Batched-workload pairs the oracle proves quickly whose optimum is
-    below min(nG, nH), with the oracle's node count for the search that
-    starts at incumbent = optimum and asks for one vertex more."""
-    if not _FIXED_INC:
+def _fixed_incumbent_case(kind="batched"):
+    """Pairs the oracle proves quickly whose optimum is below min(nG, nH),
+    with the oracle's node count for the search that starts at incumbent =
+    optimum and asks for one vertex more: batched-workload pairs, or random
+    directed vertex-labelled pairs."""
+    if kind not in _FIXED_INC:
         from _easy import easy_c4
-        pairs, _ = easy_c4(120, start=64, max_nodes=400_000)
+        from _mcsplit_py import rank, root, select
+        if kind == "batched":
+            pairs, _ = easy_c4(120, start=64, max_nodes=400_000)
+        else:
+            rng = np.random.default_rng(31)
+            pairs = []
+            for _ in range(160):
+                n1, n2 = int(rng.integers(18, 27)), int(rng.integers(18, 27))
+                p = float(rng.uniform(0.15, 0.35))
+                nlab = int(rng.integers(2, 6))
+                pairs.append((mi.random_small(rng, n1, p, True, nlab),
+                              mi.random_small(rng, n2, p, True, nlab)))
         keep, goals, nodes = [], [], []
         for G, H in pairs:
-            opt = oracle.mcs(G, H)["size"]
-            if opt >= min(G["n"], H["n"]):
+            o = oracle.mcs(G, H, node_limit=2_000_000)
+            opt = o["size"]
+            if not o["complete"] or opt >= min(G["n"], H["n"]):
                 continue
-            # the root branches on G's first vertex in descending-degree order
-            deg = [bin(int(r)).count("1") for r in G["rows"]]
-            v0 = min(range(G["n"]), key=lambda u: (-deg[u], u))
+            # the root branches on the first vertex (descending-degree order)
+            # of the class it selects (Python reference of the rules)
+            classes = root(G, H)
+            if not classes:
+                continue
+            rg = rank(G)
+            v0 = min(classes[select(classes, rg)][0], key=lambda x: rg[x])
             n = oracle.branch_cost(G, H, [], v0, opt)
+            if n < 200:
+                continue  # too small a tree to split between searches
             keep.append((G, H))
             goals.append(opt + 1)
             nodes.append(n)
             if len(keep) == 48:
                 break
-        _FIXED_INC.update(pairs=keep, goals=goals, nodes=nodes)
-    return _FIXED_INC["pairs"], _FIXED_INC["goals"], _FIXED_INC["nodes"]
+        _FIXED_INC[kind] = (keep, goals, nodes)
+    return _FIXED_INC[kind]
 
 
 @pytest.mark.parametrize("tun", [
@@ -518,7 +537,8 @@ def _fixed_incumbent_case():
     {"seg_lanes": 8, "stack_classes": 1, "check_interval": 2, "donate_low": 64},
     {"seg_lanes": 64},
 ])
-def test_fixed_incumbent_node_counts_match_oracle(gpu, tun):
+@pytest.mark.parametrize("kind", ["batched", "directed_labelled"])
+def test_fixed_incumbent_node_counts_match_oracle(gpu, tun, kind):
     """With the incumbent held at the optimum (goal = optimum + 1, which no
     mapping reaches) the set of nodes the search evaluates does not depend on
     the order it visits them: each node whose ancestors' Eq. 1 bounds all
@@ -528,8 +548,8 @@ def test_fixed_incumbent_node_counts_match_oracle(gpu, tun):
     oracle's nodes on every pair: a lost or duplicated subtree anywhere in
     the work sharing changes the count."""
     from paper_1908_06418_amd import Plan
-    pairs, goals, want = _fixed_incumbent_case()
-    _say(f"fixed incumbent {tun}: {len(pairs)} pairs")
+    pairs, goals, want = _fixed_incumbent_case(kind)
+    _say(f"fixed incumbent, {kind}, {tun}: {len(pairs)} pairs")
     plan = Plan(pairs, time_limit_s=60, tuning=tun).upload()
     try:
         plan.set_goals(goals)
