@@ -53,18 +53,22 @@ typedef enum {
                              stops instead of writing out of bounds */
 } mcs_status;
 
-#define MCS_MAX_N 128
+/* The paper's limit (Sec. III.B): vertex indices and stack entries are
+ * bytes, with 255 reserved. */
+#define MCS_MAX_N 254
 
-/* One graph.  adj holds n rows of rw 64-bit words each, rw = 1 for n <= 64
- * and 2 for 65 <= n <= 128 (rw = ceil(n / 64), at least 1): the arc i -> j
+/* One graph.  adj holds n rows of rw 64-bit words each, rw = ceil(n / 64)
+ * (at least 1; 1 up to 64, 2 up to 128, 3 up to 192, 4 up to 254): the arc i -> j
  * exists iff bit j % 64 of adj[i * rw + j / 64] is set.  Undirected graphs
  * must be symmetric.  No self loops (diagonal bits) and no bits at or above
  * n.  label is NULL (unlabelled) or n vertex labels; G and H of a pair must
  * agree on directed and on labelled.  One batch may mix directed and
  * undirected pairs, and labelled and unlabelled ones.  A batch whose
- * largest graph has more than 64 vertices runs the slower 128-bit kernel
- * (two classes per lane in nodes of more than 64 classes) for all its
- * pairs. */
+ * largest graph has more than 64 vertices runs the slower one-search-per-
+ * wavefront kernel with 128-bit rows for all its pairs (two classes per
+ * lane in nodes of more than 64 classes), and one whose largest graph has
+ * more than 128 vertices the same kernel with 256-bit rows (up to four
+ * classes per lane). */
 typedef struct {
     int32_t n;
     int32_t directed;
@@ -118,7 +122,7 @@ typedef struct {
                                   not fit in the LDS part goes to the HBM
                                   part.  One search per wavefront always
                                   keeps the whole worst case (in LDS, or in
-                                  HBM with 128-bit rows); this field does not
+                                  HBM with 128- and 256-bit rows); this field does not
                                   apply to it. */
     int32_t backoff_max;       /* an idle wavefront that finds no work sleeps
                                   1, 2, 4, ... up to this many times about

@@ -14,7 +14,7 @@ MCS_E_TOO_LARGE = -2
 MCS_E_DEVICE = -3
 MCS_E_WORKSPACE = -4
 MCS_E_INTERNAL = -5
-MCS_MAX_N = 128
+MCS_MAX_N = 254
 MCS_STATIC_SCRATCH_BYTES = 64 << 20
 
 

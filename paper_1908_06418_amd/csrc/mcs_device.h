@@ -16,10 +16,132 @@ namespace mcs {
 // Rows of graphs with 65..128 vertices.
 using u128 = unsigned __int128;
 
+// Rows of graphs with 129..254 vertices: four 64-bit words, low word first.
+// The integer operators the search applies to a row word (bitwise logic,
+// shifts, and the x - 1 / ~x + 1 of lowest-bit tricks) are written out per
+// word; a shift count is at most 255.
+struct u256 {
+    uint64_t w[4];
+    u256() = default;
+    __host__ __device__ constexpr u256(uint64_t x) : w{x, 0, 0, 0} {}
+    __device__ explicit operator bool() const { return (w[0] | w[1] | w[2] | w[3]) != 0; }
+    __device__ explicit operator uint64_t() const { return w[0]; }
+    __device__ explicit operator uint32_t() const { return (uint32_t)w[0]; }
+    __device__ explicit operator int() const { return (int)w[0]; }
+};
+__device__ __forceinline__ u256 operator&(const u256 &a, const u256 &b) {
+    u256 r;
+    for (int i = 0; i < 4; ++i)
+        r.w[i] = a.w[i] & b.w[i];
+    return r;
+}
+__device__ __forceinline__ u256 operator|(const u256 &a, const u256 &b) {
+    u256 r;
+    for (int i = 0; i < 4; ++i)
+        r.w[i] = a.w[i] | b.w[i];
+    return r;
+}
+__device__ __forceinline__ u256 operator^(const u256 &a, const u256 &b) {
+    u256 r;
+    for (int i = 0; i < 4; ++i)
+        r.w[i] = a.w[i] ^ b.w[i];
+    return r;
+}
+__device__ __forceinline__ u256 operator~(const u256 &a) {
+    u256 r;
+    for (int i = 0; i < 4; ++i)
+        r.w[i] = ~a.w[i];
+    return r;
+}
+__device__ __forceinline__ u256 &operator&=(u256 &a, const u256 &b) { return a = a & b; }
+__device__ __forceinline__ u256 &operator|=(u256 &a, const u256 &b) { return a = a | b; }
+__device__ __forceinline__ u256 &operator^=(u256 &a, const u256 &b) { return a = a ^ b; }
+__device__ __forceinline__ bool operator==(const u256 &a, const u256 &b) {
+    return ((a.w[0] ^ b.w[0]) | (a.w[1] ^ b.w[1]) | (a.w[2] ^ b.w[2]) | (a.w[3] ^ b.w[3])) == 0;
+}
+__device__ __forceinline__ bool operator!=(const u256 &a, const u256 &b) { return !(a == b); }
+__device__ __forceinline__ u256 operator+(const u256 &a, const u256 &b) {
+    u256 r;
+    uint64_t c = 0;
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t s = a.w[i] + b.w[i];
+        const uint64_t t = s + c;
+        c = (uint64_t)(s < a.w[i]) | (uint64_t)(t < s);
+        r.w[i] = t;
+    }
+    return r;
+}
+__device__ __forceinline__ u256 operator-(const u256 &a, const u256 &b) { return a + (~b + u256(1)); }
+// Word j of the result takes words j - q and j - q - 1 of a (q = s / 64).
+__device__ __forceinline__ u256 operator<<(const u256 &a, int s) {
+    const int q = s >> 6, b = s & 63;
+    u256 r;
+    for (int j = 0; j < 4; ++j) {
+        uint64_t hi = 0, lo = 0;
+        for (int i = 0; i < 4; ++i) {
+            hi = (j - i == q) ? a.w[i] : hi;
+            lo = (j - i == q + 1) ? a.w[i] : lo;
+        }
+        r.w[j] = (hi << b) | (b ? lo >> (64 - b) : 0);
+    }
+    return r;
+}
+__device__ __forceinline__ u256 operator>>(const u256 &a, int s) {
+    const int q = s >> 6, b = s & 63;
+    u256 r;
+    for (int j = 0; j < 4; ++j) {
+        uint64_t lo = 0, hi = 0;
+        for (int i = 0; i < 4; ++i) {
+            lo = (i - j == q) ? a.w[i] : lo;
+            hi = (i - j == q + 1) ? a.w[i] : hi;
+        }
+        r.w[j] = (lo >> b) | (b ? hi << (64 - b) : 0);
+    }
+    return r;
+}
+
 template <typename W>
 struct Cls {
     W L, R;
 };
+
+// A row word or class in memory (LDS, HBM stack or queued record), read
+// and written word by word: an aggregate copy of a 256-bit value goes
+// through a temporary in scratch memory.
+template <typename W>
+DEV W ld_w(const W *p) {
+    if constexpr (sizeof(W) == 32) {
+        const uint64_t *q = (const uint64_t *)p;
+        W x;
+        for (int i = 0; i < 4; ++i)
+            x.w[i] = q[i];
+        return x;
+    } else {
+        return *p;
+    }
+}
+template <typename W>
+DEV void st_w(W *p, const W &x) {
+    if constexpr (sizeof(W) == 32) {
+        uint64_t *q = (uint64_t *)p;
+        for (int i = 0; i < 4; ++i)
+            q[i] = x.w[i];
+    } else {
+        *p = x;
+    }
+}
+template <typename W>
+DEV Cls<W> ld_cls(const Cls<W> *p) {
+    Cls<W> c;
+    c.L = ld_w(&p->L);
+    c.R = ld_w(&p->R);
+    return c;
+}
+template <typename W>
+DEV void st_cls(Cls<W> *p, const Cls<W> &c) {
+    st_w(&p->L, c.L);
+    st_w(&p->R, c.R);
+}
 
 // A frame header in LDS: one 32-bit word per field, written from lane f of
 // one register (v_writelane, then a single masked LDS store) and read back
@@ -38,7 +160,14 @@ enum HdrField {
     kHRsel,
     kHRrem2,  // (128-bit rows) bits 64..95 and 96..127 of the partner mask
     kHRrem3,
+    kHRrem4,  // (256-bit rows) bits 128..255 of the partner mask
+    kHRrem5,
+    kHRrem6,
+    kHRrem7,
 };
+
+// Header field of bits 32k..32k+31 of the partner mask.
+constexpr int rrem_field(int k) { return k < 2 ? k : kHRrem2 + (k - 2); }
 
 template <typename W>
 struct RecHdr {
@@ -48,9 +177,10 @@ struct RecHdr {
     W rrem;
 };
 
-static_assert(kHRsel < kHdrWords && kHRrem3 < kHdrWordsWide, "header layout");
-static_assert(sizeof(RecHdr<uint64_t>) <= kRecHeader && sizeof(RecHdr<uint32_t>) <= kRecHeader &&
-                  sizeof(RecHdr<u128>) <= kRecHeader,
+static_assert(kHRsel < kHdrWords && kHRrem3 < kHdrWordsWide && kHRrem7 < kHdrWords256,
+              "header layout");
+static_assert(sizeof(RecHdr<uint64_t>) <= rec_header(8) && sizeof(RecHdr<uint32_t>) <= rec_header(4) &&
+                  sizeof(RecHdr<u128>) <= rec_header(16) && sizeof(RecHdr<u256>) <= rec_header(32),
               "record header layout");
 
 constexpr int kFlagUnmatched = 1;  // the "v unmatched" child is still to do
@@ -70,6 +200,68 @@ DEV int popc(u128 x) { return popc((uint64_t)x) + popc((uint64_t)(x >> 64)); }
 DEV int ctz(u128 x) {
     const uint64_t lo = (uint64_t)x;
     return lo ? ctz(lo) : 64 + ctz((uint64_t)(x >> 64));
+}
+DEV int popc(const u256 &x) { return popc(x.w[0]) + popc(x.w[1]) + popc(x.w[2]) + popc(x.w[3]); }
+DEV int ctz(const u256 &x) {
+    return x.w[0] ? ctz(x.w[0])
+           : x.w[1] ? 64 + ctz(x.w[1])
+           : x.w[2] ? 128 + ctz(x.w[2])
+                    : 192 + ctz(x.w[3]);
+}
+
+// 64-bit word q of a row word (zero past its width), and a row word from
+// its 64-bit words.
+DEV uint64_t word64(uint32_t x, int q) { return q == 0 ? x : 0; }
+DEV uint64_t word64(uint64_t x, int q) { return q == 0 ? x : 0; }
+DEV uint64_t word64(u128 x, int q) { return q == 0 ? (uint64_t)x : q == 1 ? (uint64_t)(x >> 64) : 0; }
+DEV uint64_t word64(const u256 &x, int q) { return q < 4 ? x.w[q] : 0; }
+template <typename W>
+DEV W from_words(const uint64_t *x) {
+    if constexpr (sizeof(W) == 32) {
+        u256 r;
+        for (int i = 0; i < 4; ++i)
+            r.w[i] = x[i];
+        return r;
+    } else if constexpr (sizeof(W) == 16) {
+        return ((u128)x[1] << 64) | x[0];
+    } else {
+        return (W)x[0];
+    }
+}
+// c ? a : b on row words.  For u256 the choice is made per word: a
+// conditional on two struct lvalues selects between their addresses, which
+// would keep the registers of a search's row words in scratch memory.
+template <typename W>
+DEV W pick(bool c, const W &a, const W &b) {
+    if constexpr (sizeof(W) == 32) {
+        u256 r;
+        for (int i = 0; i < 4; ++i)
+            r.w[i] = c ? a.w[i] : b.w[i];
+        return r;
+    } else {
+        return c ? a : b;
+    }
+}
+// Bit i of a row word, as a row word.
+template <typename W>
+DEV W bit_at(int i) {
+    if constexpr (sizeof(W) == 32) {
+        u256 r;
+        for (int j = 0; j < 4; ++j)
+            r.w[j] = (i >> 6) == j ? 1ull << (i & 63) : 0;
+        return r;
+    } else {
+        return (W)1 << i;
+    }
+}
+template <typename W>
+DEV bool test_bit(const W &x, int i) {
+    if constexpr (sizeof(W) == 32) {
+        const uint64_t a = (i >> 6) == 0 ? x.w[0] : (i >> 6) == 1 ? x.w[1] : (i >> 6) == 2 ? x.w[2] : x.w[3];
+        return (a >> (i & 63)) & 1;
+    } else {
+        return (x >> i) & 1;
+    }
 }
 
 // ---- wave helpers ----------------------------------------------------------
@@ -91,6 +283,18 @@ DEV uint64_t rl(uint64_t x, int l) {
 DEV unsigned long long rl_ull(unsigned long long x, int l) { return (unsigned long long)rl((uint64_t)x, l); }
 DEV u128 sc(u128 x) { return ((u128)sc((uint64_t)(x >> 64)) << 64) | sc((uint64_t)x); }
 DEV u128 rl(u128 x, int l) { return ((u128)rl((uint64_t)(x >> 64), l) << 64) | rl((uint64_t)x, l); }
+DEV u256 sc(const u256 &x) {
+    u256 r;
+    for (int i = 0; i < 4; ++i)
+        r.w[i] = sc(x.w[i]);
+    return r;
+}
+DEV u256 rl(const u256 &x, int l) {
+    u256 r;
+    for (int i = 0; i < 4; ++i)
+        r.w[i] = rl(x.w[i], l);
+    return r;
+}
 
 DEV uint64_t ballot(bool p) { return __ballot(p); }
 DEV int mbcnt(uint64_t m) {

@@ -54,18 +54,18 @@ bool in_arc(const mcs_graph &g, int i, int j) {
     return (g.adj[(size_t)i * row_words(g.n) + (j >> 6)] >> (j & 63)) & 1;
 }
 
-// A vertex set (a row or one side of a class) of up to 128 vertices.
+// A vertex set (a row or one side of a class) of up to 256 vertices.
 struct Bits {
-    uint64_t w[2] = {0, 0};
+    uint64_t w[4] = {0, 0, 0, 0};
     void set(int j) { w[j >> 6] |= 1ull << (j & 63); }
     bool get(int j) const { return (w[j >> 6] >> (j & 63)) & 1; }
-    bool any() const { return (w[0] | w[1]) != 0; }
+    bool any() const { return (w[0] | w[1] | w[2] | w[3]) != 0; }
 };
 
 Bits first_n(int n) {
     Bits b;
-    b.w[0] = low_mask(n);
-    b.w[1] = low_mask(n - 64);
+    for (int k = 0; k < 4; k++)
+        b.w[k] = low_mask(n - 64 * k);
     return b;
 }
 
@@ -346,14 +346,14 @@ void put_word(std::vector<uint8_t> &buf, uint64_t x) {
     buf.insert(buf.end(), p, p + sizeof(W));
 }
 
-// One row word as the kernels read it: 32, 64 or 128 bits (low half first).
+// One row word as the kernels read it: 32, 64, 128 or 256 bits (low
+// 64-bit word first).
 void pack_word(std::vector<uint8_t> &buf, int word_bytes, const Bits &x) {
     if (word_bytes == 4) {
         put_word<uint32_t>(buf, x.w[0]);
     } else {
-        put_word<uint64_t>(buf, x.w[0]);
-        if (word_bytes == 16)
-            put_word<uint64_t>(buf, x.w[1]);
+        for (int k = 0; k < word_bytes / 8; k++)
+            put_word<uint64_t>(buf, x.w[k]);
     }
 }
 
@@ -455,7 +455,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
     int nmax = 0;
     for (int i = 0; i < count; i++)
         nmax = std::max(nmax, std::max(G[i].n, H[i].n));
-    p->word_bytes = nmax <= 32 ? 4 : nmax <= 64 ? 8 : 16;
+    p->word_bytes = nmax <= 32 ? 4 : nmax <= 64 ? 8 : nmax <= 128 ? 16 : 32;
     if (p->policy && p->word_bytes > 8) {
         delete p;
         return fail(MCS_E_INVALID, "the learned policy takes graphs of at most 64 vertices");
@@ -583,7 +583,7 @@ mcs_status mcs_plan_create(int32_t count, const mcs_graph *G, const mcs_graph *H
         clock_khz = 100000;
     (void)hipGetLastError();
     p->tick_hz = (double)clock_khz * 1000.0;
-    const bool wide = p->word_bytes == 16;
+    const bool wide = p->word_bytes >= 16;
     // Search layout: one search per lane segment of 16 (or 8) lanes
     // (mcs_seg.hip), or one per wavefront (mcs_search.hip: needed for
     // 128-bit rows and for the learned policy, which scores one vertex per

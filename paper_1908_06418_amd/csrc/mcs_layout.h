@@ -141,23 +141,28 @@ struct ResetParams {
 };
 
 // Words of one frame header in LDS (one 32-bit word per field, padded).
-// Rows of 128 bits need two more words for the remaining-partner mask.
+// Rows of 128 bits need two more words for the remaining-partner mask, rows
+// of 256 bits six.
 constexpr int kHdrWords = 12;
 constexpr int kHdrWordsWide = 14;
-inline constexpr int hdr_words(int word_bytes) { return word_bytes > 8 ? kHdrWordsWide : kHdrWords; }
+constexpr int kHdrWords256 = 18;
+inline constexpr int hdr_words(int word_bytes) {
+    return word_bytes > 16 ? kHdrWords256 : word_bytes > 8 ? kHdrWordsWide : kHdrWords;
+}
 
-// Record of a donated node in the queue: a 32-byte header, the mapping
-// (NB pairs of bytes) and the classes.
+// Record of a donated node in the queue: a header (32 bytes, 48 with
+// 256-bit rows), the mapping (NB pairs of bytes) and the classes.
 constexpr int kRecHeader = 32;
+inline constexpr int rec_header(int word_bytes) { return word_bytes > 16 ? 48 : kRecHeader; }
 
 template <typename W>
 constexpr int bits_of() { return 8 * (int)sizeof(W); }
 
 template <typename W>
-constexpr int rec_map_off() { return kRecHeader; }
+constexpr int rec_map_off() { return rec_header((int)sizeof(W)); }
 
 template <typename W>
-constexpr int rec_cls_off() { return kRecHeader + 2 * bits_of<W>(); }
+constexpr int rec_cls_off() { return rec_header((int)sizeof(W)) + 2 * bits_of<W>(); }
 
 // LDS of one wavefront, in this order, each part 16-byte aligned:
 //   classes   [cap_classes + 1] (L, R) word pairs; the last is a trash slot
@@ -215,7 +220,7 @@ inline constexpr SegLayout seg_layout(int word_bytes, int directed, int cap_clas
 }
 
 inline int slot_bytes_for(int word_bytes, int mmax) {
-    int b = kRecHeader + 2 * 8 * word_bytes + mmax * 2 * word_bytes;
+    int b = rec_header(word_bytes) + 2 * 8 * word_bytes + mmax * 2 * word_bytes;
     return (b + 63) & ~63;
 }
 

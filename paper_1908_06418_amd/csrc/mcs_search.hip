@@ -9,10 +9,10 @@
 // GPU mapping (ours, not the paper's CUDA design):
 //   * One wavefront runs one depth-first search at a time.  Classes are
 //     bitsets (L, R) of one word each (32-bit rows for graphs of at most 32
-//     vertices, 64-bit up to 64, 128-bit up to 128); lane k holds class k.
-//     A node has at most min(|V_G|, |V_H|) classes, so one wave64 holds all
-//     of them up to 64 vertices; with 128-bit rows a frame of more than 64
-//     classes puts class 64 + k in a second slot of lane k.
+//     vertices, 64-bit up to 64, 128-bit up to 128, 256-bit up to 254);
+//     lane k holds class k.  A node has at most min(|V_G|, |V_H|) classes,
+//     so one wave64 holds all of them up to 64 vertices; with wider rows a
+//     frame of more than 64 classes puts class 64q + k in slot q of lane k.
 //   * A batch evaluates up to 8 sibling children at once: lanes are split in
 //     segments of S = 8/16/32/64 lanes, each segment a copy of the classes and
 //     its own w.  Split, popcounts and the min() of Eq. 1 are per lane; the
@@ -54,7 +54,7 @@ template <typename W, bool DIR, bool POL>
 struct Searcher {
     static constexpr int NB = bits_of<W>();  // vertices per row word
     static constexpr int NR = DIR ? 4 : 2;   // adjacency row sets per instance
-    static constexpr int Q = NB > 64 ? 2 : 1;  // classes per lane
+    static constexpr int Q = NB > 64 ? NB / 64 : 1;  // class slots per lane
     static constexpr int HW = hdr_words((int)sizeof(W));  // header words per frame
     static_assert(!(POL && Q > 1), "the policy scorer takes one vertex per lane");
 
@@ -75,9 +75,10 @@ struct Searcher {
     W rrem;
     int logS;
     // this lane's copy of class (lane mod S) of the top frame, and in a
-    // frame of more than 64 classes (S = 64), of class lane + 64 in cL1, cR1
+    // frame of more than 64 classes (S = 64), of class lane + 64q in slot q
+    // (cLh[q - 1], cRh[q - 1])
     W cL, cR;
-    W cL1, cR1;
+    W cLh[Q > 1 ? Q - 1 : 1], cRh[Q > 1 ? Q - 1 : 1];
     int inc;
     bool stop;
     bool roots_left;  // false once every instance root has been claimed
@@ -165,6 +166,23 @@ struct Searcher {
             wave_sync_global();
     }
 
+    // Slot q of this lane's classes.  A constant q names a register; a
+    // wave-uniform q selects (register arrays are never indexed at run time).
+    __device__ W slotL(int q) const {
+        W x = cL;
+#pragma unroll
+        for (int j = 1; j < Q; ++j)
+            x = pick(q == j, cLh[j - 1], x);
+        return x;
+    }
+    __device__ W slotR(int q) const {
+        W x = cR;
+#pragma unroll
+        for (int j = 1; j < Q; ++j)
+            x = pick(q == j, cRh[j - 1], x);
+        return x;
+    }
+
     // -- frame registers -----------------------------------------------------
 
     __device__ void load_regs() {
@@ -177,21 +195,24 @@ struct Searcher {
             cR = in ? c.R : (W)0;
         } else {
             // segments as with one class per lane; only a frame of more
-            // than 64 classes (S = 64) puts classes 64.. in the second slot
+            // than 64 classes (S = 64) puts classes 64q.. in slot q
             logS = K <= 8 ? 3 : K <= 16 ? 4 : K <= 32 ? 5 : 6;
             const int S = 1 << logS;
             const int k = lane & (S - 1);
             const bool in0 = k < K;
-            const Cls<W> c0 = scls[base + (in0 ? k : 0)];
-            cL = in0 ? c0.L : (W)0;
-            cR = in0 ? c0.R : (W)0;
-            cL1 = 0;
-            cR1 = 0;
-            if (K > 64) {
-                const bool in1 = k + S < K;
-                const Cls<W> c1 = scls[base + (in1 ? k + S : 0)];
-                cL1 = in1 ? c1.L : (W)0;
-                cR1 = in1 ? c1.R : (W)0;
+            const Cls<W> c0 = ld_cls(scls + base + (in0 ? k : 0));
+            cL = pick(in0, c0.L, (W)0);
+            cR = pick(in0, c0.R, (W)0);
+#pragma unroll
+            for (int q = 1; q < Q; ++q) {
+                cLh[q - 1] = (W)0;
+                cRh[q - 1] = (W)0;
+                if (K > 64 * q) {
+                    const bool in = k + 64 * q < K;
+                    const Cls<W> c = ld_cls(scls + base + (in ? k + 64 * q : 0));
+                    cLh[q - 1] = pick(in, c.L, (W)0);
+                    cRh[q - 1] = pick(in, c.R, (W)0);
+                }
             }
         }
     }
@@ -199,8 +220,8 @@ struct Searcher {
     // selectLabelClass + selectVertex: the class with the smallest
     // max(|L|, |R|), ties to the smallest vertex of L; v = that vertex.
     __device__ void select() {
-        if constexpr (Q == 2) {
-            select2();
+        if constexpr (Q > 1) {
+            select_wide();
             return;
         }
         uint32_t key = 0xFFFFFFFFu;
@@ -230,28 +251,34 @@ struct Searcher {
         }
     }
 
-    // select() with a second class slot per lane (classes lane + S, used
-    // only when S = 64).  L sets are disjoint, so keys are distinct.
-    __device__ void select2() {
+    // select() with Q class slots per lane (class lane + qS in slot q; slots
+    // past the first are used only when S = 64).  L sets are disjoint, so
+    // keys are distinct.
+    __device__ void select_wide() {
         const int S = 1 << logS;
-        uint32_t key0 = 0xFFFFFFFFu, key1 = 0xFFFFFFFFu;
-        if (lane < S) {
-            if (lane < K) {
-                int nl = popc(cL), nr = popc(cR);
-                key0 = ((uint32_t)(nl > nr ? nl : nr) << 8) | (uint32_t)ctz(cL);
+        uint32_t key[Q];
+        uint32_t kmin = 0xFFFFFFFFu;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            key[q] = 0xFFFFFFFFu;
+            if (lane < S && lane + q * S < K) {
+                const W l = slotL(q), r = slotR(q);
+                int nl = popc(l), nr = popc(r);
+                key[q] = ((uint32_t)(nl > nr ? nl : nr) << 8) | (uint32_t)ctz(l);
             }
-            if (lane + S < K) {
-                int nl = popc(cL1), nr = popc(cR1);
-                key1 = ((uint32_t)(nl > nr ? nl : nr) << 8) | (uint32_t)ctz(cL1);
-            }
+            kmin = umin(kmin, key[q]);
         }
-        const uint32_t mk = seg0_min(umin(key0, key1), logS);
-        const int who = ctz((uint64_t)ballot(key0 == mk || key1 == mk));
-        const bool hi = rl(key1 == mk ? 1 : 0, who) != 0;
-        sel = who + (hi ? S : 0);
+        const uint32_t mk = seg0_min(kmin, logS);
+        int hq = 0;
+#pragma unroll
+        for (int q = 1; q < Q; ++q)
+            hq = key[q] == mk ? q : hq;
+        const int who = ctz((uint64_t)ballot(kmin == mk));
+        hq = rl(hq, who);
+        sel = who + hq * S;
         v = (int)(mk & 0xFF);
-        rrem = rl(hi ? cR1 : cR, who);
-        lsel = popc(rl(hi ? cL1 : cL, who));
+        rrem = rl(slotR(hq), who);
+        lsel = popc(rl(slotL(hq), who));
         rsel = popc(rrem);
         flags &= ~kFlagOrdered;
     }
@@ -415,6 +442,20 @@ struct Searcher {
                 "v_writelane_b32 %0, %2, 12"
                 : "+v"(x)
                 : "s"(w2), "s"(w3));
+        } else if constexpr (sizeof(W) == 32) {
+            static_assert(kHRrem2 == 11 && kHRrem7 == 16, "header field order");
+            const int w2 = (int)(uint32_t)rrem.w[1], w3 = (int)(uint32_t)(rrem.w[1] >> 32);
+            const int w4 = (int)(uint32_t)rrem.w[2], w5 = (int)(uint32_t)(rrem.w[2] >> 32);
+            const int w6 = (int)(uint32_t)rrem.w[3], w7 = (int)(uint32_t)(rrem.w[3] >> 32);
+            asm volatile(
+                "v_writelane_b32 %0, %1, 11\n\t"
+                "v_writelane_b32 %0, %2, 12\n\t"
+                "v_writelane_b32 %0, %3, 13\n\t"
+                "v_writelane_b32 %0, %4, 14\n\t"
+                "v_writelane_b32 %0, %5, 15\n\t"
+                "v_writelane_b32 %0, %6, 16"
+                : "+v"(x)
+                : "s"(w2), "s"(w3), "s"(w4), "s"(w5), "s"(w6), "s"(w7));
         }
         // lanes past the last field all store into the header's padding word
         shdr[t * HW + (lane < HW ? lane : HW - 1)] = x;
@@ -423,6 +464,14 @@ struct Searcher {
     // One field of frame i's header, as a scalar.
     __device__ int hdr(int i, int f) const { return sc(shdr[i * HW + f]); }
     __device__ W hdr_rrem(int i) const {
+        if constexpr (sizeof(W) == 32) {
+            uint64_t ws[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                ws[k] = (uint64_t)(uint32_t)hdr(i, rrem_field(2 * k)) |
+                        ((uint64_t)(uint32_t)hdr(i, rrem_field(2 * k + 1)) << 32);
+            return from_words<W>(ws);
+        }
         W r = (W)(uint32_t)hdr(i, kHRremLo);
         if constexpr (sizeof(W) >= 8)
             r |= (W)(uint32_t)hdr(i, kHRremHi) << 32;
@@ -436,7 +485,15 @@ struct Searcher {
     __device__ void read_hdr(int i) {
         const int x = shdr[i * HW + (lane < HW ? lane : 0)];
         W r = (W)(uint32_t)rl(x, kHRremLo);
-        if constexpr (sizeof(W) >= 8)
+        if constexpr (sizeof(W) == 32) {
+            uint64_t ws[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                ws[k] = (uint64_t)(uint32_t)rl(x, rrem_field(2 * k)) |
+                        ((uint64_t)(uint32_t)rl(x, rrem_field(2 * k + 1)) << 32);
+            r = from_words<W>(ws);
+        }
+        if constexpr (sizeof(W) >= 8 && sizeof(W) <= 16)
             r |= (W)(uint32_t)rl(x, kHRremHi) << 32;
         if constexpr (sizeof(W) == 16) {
             r |= (W)(uint32_t)rl(x, kHRrem2) << 64;
@@ -460,7 +517,7 @@ struct Searcher {
         if (i != inst) {
             const W *src = (const W *)P.adj + (size_t)i * NR * NB;
             for (int j = lane; j < NR * NB; j += 64)
-                sadj[j] = src[j];
+                st_w(sadj + j, ld_w(src + j));
             inst = i;
             map_off = (int)P.inst[i].map_off;
             nG = (int)P.inst[i].nG;
@@ -496,7 +553,7 @@ struct Searcher {
         } else {
             const Cls<W> *rc = (const Cls<W> *)P.rootcls + sc((int)di.cls_off);
             for (int j = lane; j < K; j += 64)
-                scls[j] = rc[j];
+                st_cls(scls + j, ld_cls(rc + j));
         }
         sync();
         t = 0;
@@ -513,11 +570,11 @@ struct Searcher {
         } else {
             // (slots past K hold empty classes)
             if (lane < (1 << logS)) {
-                int nl = popc(cL), nr = popc(cR);
-                contrib = nl < nr ? nl : nr;
-                nl = popc(cL1);
-                nr = popc(cR1);
-                contrib += nl < nr ? nl : nr;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int nl = popc(slotL(q)), nr = popc(slotR(q));
+                    contrib += nl < nr ? nl : nr;
+                }
             }
         }
         bound = wave_sum(contrib);
@@ -571,8 +628,8 @@ struct Searcher {
     // -- one batch of sibling children -----------------------------------------
 
     __device__ void batch() {
-        if constexpr (Q == 2) {
-            batch2();
+        if constexpr (Q > 1) {
+            batch_wide();
             return;
         }
         const int S = 1 << logS;
@@ -740,11 +797,36 @@ struct Searcher {
         (void)S;
     }
 
-    // batch() for 128-bit rows: the same steps, on the second class slot
-    // too when the frame has more than 64 classes.  Lane j stands for
-    // vertices j and 64 + j when the children taken are struck from the
-    // partner mask.
-    __device__ void batch2() {
+    // filterDomain on slot q of this lane: the parts of class (slot q) by
+    // adjacency letter, with v and w already struck from it.
+    __device__ void parts_of(int q, const W &vb, const W &wb, const W &go, const W &ho,
+                             const W &gi, const W &hi, W *l, W *r) const {
+        const W Lx = slotL(q) & ~vb;
+        const W Rx = slotR(q) & ~wb;
+        if constexpr (!DIR) {
+            l[0] = Lx & ~go;
+            r[0] = Rx & ~ho;
+            l[1] = Lx & go;
+            r[1] = Rx & ho;
+        } else {
+            l[0] = Lx & ~go & ~gi;
+            r[0] = Rx & ~ho & ~hi;
+            l[1] = Lx & go & ~gi;
+            r[1] = Rx & ho & ~hi;
+            l[2] = Lx & ~go & gi;
+            r[2] = Rx & ~ho & hi;
+            l[3] = Lx & go & gi;
+            r[3] = Rx & ho & hi;
+        }
+    }
+
+    // batch() for rows wider than 64 bits: the same steps, on slot q too
+    // when the frame has more than 64q classes (then S = 64 and the batch
+    // is one child).  Lane j stands for vertices j, 64 + j, ... when the
+    // children taken are struck from the partner mask.  The surviving
+    // child's parts are split again when it is pushed, rather than kept
+    // from the bound pass: Q slots of parts would not fit in registers.
+    __device__ void batch_wide() {
         const int S = 1 << logS;
         int C = popc(rrem);
         if (C > cmax)
@@ -755,49 +837,25 @@ struct Searcher {
         const bool act = seg < C;
         W x = rrem;
         for (int i = 1; i < C; ++i) {
-            W y = x & (x - 1);
-            x = seg >= i ? y : x;
+            W y = x & (x - (W)1);
+            x = pick(seg >= i, y, x);
         }
         const int myw = act ? ctz(x) : 0;
-        const W vb = (W)1 << v;
-        const W wb = (W)1 << myw;
-        const W go = sadj[v], ho = sadj[NB + myw];
-        W gi = 0, hi = 0;
+        const W vb = bit_at<W>(v);
+        const W wb = bit_at<W>(myw);
+        const W go = ld_w(sadj + v), ho = ld_w(sadj + NB + myw);
+        W gi = (W)0, hi = (W)0;
         if constexpr (DIR) {
-            gi = sadj[2 * NB + v];
-            hi = sadj[3 * NB + myw];
+            gi = ld_w(sadj + 2 * NB + v);
+            hi = ld_w(sadj + 3 * NB + myw);
         }
-        // parts of slot q at index q * NR + a; the second slot only holds
-        // classes in frames of more than 64
-        const bool two = K > 64;
-        W pl[2 * NR], pr[2 * NR];
         int contrib = 0;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            if (q == 1 && !two) {
-#pragma unroll
-                for (int a = 0; a < NR; ++a)
-                    pl[NR + a] = pr[NR + a] = 0;
+        for (int q = 0; q < Q; ++q) {
+            if (q > 0 && K <= 64 * q)
                 break;
-            }
-            const W Lx = (q ? cL1 : cL) & ~vb;
-            const W Rx = (q ? cR1 : cR) & ~wb;
-            W *l = pl + q * NR, *r = pr + q * NR;
-            if constexpr (!DIR) {
-                l[0] = Lx & ~go;
-                r[0] = Rx & ~ho;
-                l[1] = Lx & go;
-                r[1] = Rx & ho;
-            } else {
-                l[0] = Lx & ~go & ~gi;
-                r[0] = Rx & ~ho & ~hi;
-                l[1] = Lx & go & ~gi;
-                r[1] = Rx & ho & ~hi;
-                l[2] = Lx & ~go & gi;
-                r[2] = Rx & ~ho & hi;
-                l[3] = Lx & go & gi;
-                r[3] = Rx & ho & hi;
-            }
+            W l[NR], r[NR];
+            parts_of(q, vb, wb, go, ho, gi, hi, l, r);
 #pragma unroll
             for (int a = 0; a < NR; ++a) {
                 int nl = popc(l[a]), nr = popc(r[a]);
@@ -820,55 +878,55 @@ struct Searcher {
         c_ncls += (uint32_t)((C - nsurv + (nsurv ? 1 : 0)) * K);
 
         // the child of rank r took the r-th lowest vertex of rrem
-        const uint64_t mlo = (uint64_t)rrem, mhi = (uint64_t)(rrem >> 64);
-        const int r0 = mbcnt(mlo), r1 = __builtin_popcountll(mlo) + mbcnt(mhi);
-        const bool t0 = ((mlo >> lane) & 1) && r0 < C;
-        const bool t1 = ((mhi >> lane) & 1) && r1 < C;
-        const bool s0 = t0 && ((sb >> (((r0 << logS) + S - 1) & 63)) & 1);
-        const bool s1 = t1 && ((sb >> (((r1 << logS) + S - 1) & 63)) & 1);
-        const uint64_t x0 = ballot(t0 && (!s0 || r0 == first));
-        const uint64_t x1 = ballot(t1 && (!s1 || r1 == first));
-        rrem &= ~((W)x0 | ((W)x1 << 64));
+        uint64_t xq[Q];
+        int below = 0, wF = -1;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint64_t m = word64(rrem, q);
+            const int r = below + mbcnt(m);
+            below += __builtin_popcountll(m);
+            const bool tq = ((m >> lane) & 1) && r < C;
+            const bool sq = tq && ((sb >> (((r << logS) + S - 1) & 63)) & 1);
+            xq[q] = ballot(tq && (!sq || r == first));
+            const uint64_t f = ballot(tq && r == first);
+            if (wF < 0 && f)
+                wF = 64 * q + ctz(f);
+        }
+        rrem &= ~from_words<W>(xq);
         if (first < 0)
             return;
-        const uint64_t f0 = ballot(t0 && r0 == first), f1 = ballot(t1 && r1 == first);
-        const int wF = f0 ? ctz(f0) : 64 + ctz(f1);
 
+        // push the surviving child: its non-empty classes, compacted in
+        // slot and part order (a class past the capacity goes to the trash
+        // slot, and the check below then fails the search)
         const bool inF = seg == first;
-        int pos[2 * NR];
-        bool ne[2 * NR];
+        const int nb = base + K;
         int K2 = 0;
 #pragma unroll
-        for (int j = 0; j < 2 * NR; ++j) {
-            ne[j] = false;
-            pos[j] = 0;
-        }
-#pragma unroll
-        for (int j = 0; j < 2 * NR; ++j) {
-            if (j == NR && !two)
+        for (int q = 0; q < Q; ++q) {
+            if (q > 0 && K <= 64 * q)
                 break;
-            ne[j] = inF && pl[j] != 0 && pr[j] != 0;
-            uint64_t m = ballot(ne[j]);
-            pos[j] = K2 + mbcnt(m);
-            K2 += __builtin_popcountll(m);
+            W l[NR], r[NR];
+            parts_of(q, vb, wb, go, ho, gi, hi, l, r);
+#pragma unroll
+            for (int a = 0; a < NR; ++a) {
+                const bool ne = inF && l[a] != (W)0 && r[a] != (W)0;
+                const uint64_t m = ballot(ne);
+                const int pos = nb + K2 + mbcnt(m);
+                K2 += __builtin_popcountll(m);
+                Cls<W> c;
+                c.L = l[a];
+                c.R = r[a];
+                st_cls(scls + (ne && pos < cap_classes ? pos : cap_classes), c);
+            }
         }
         // (the stack holds the worst case: this capacity check cannot fire)
-        const int nb = base + K;
         if (nb + K2 > cap_classes) {
             fail(1);
             return;
         }
         if (nb + K2 > max_used)
             max_used = nb + K2;
-#pragma unroll
-        for (int j = 0; j < 2 * NR; ++j) {
-            if (j == NR && !two)
-                break;
-            Cls<W> c;
-            c.L = pl[j];
-            c.R = pr[j];
-            scls[ne[j] ? nb + pos[j] : cap_classes] = c;
-        }
         smap[d] = (uint16_t)(v | (wF << 8));
         save_top();
         sync();
@@ -895,18 +953,17 @@ struct Searcher {
         c_nodes += 1;
         if (ub <= inc)
             return false;
-        const W vb = (W)1 << v;
-        if constexpr (Q == 2) {
+        const W vb = bit_at<W>(v);
+        if constexpr (Q > 1) {
             // class j sits in lane j mod S, slot j / S
             const int S = 1 << logS;
             if (lsel == 1) {
                 // the last class moves into the selected one's place
                 const int last = K - 1;
-                const bool lhi = last >= S;
                 Cls<W> c;
-                c.L = lhi ? cL1 : cL;
-                c.R = lhi ? cR1 : cR;
-                scls[(sel != last && lane == (last & (S - 1))) ? base + sel : cap_classes] = c;
+                c.L = slotL(last >> logS);
+                c.R = slotR(last >> logS);
+                st_cls(scls + ((sel != last && lane == (last & (S - 1))) ? base + sel : cap_classes), c);
                 K = last;
                 sync();
                 bound = ub;
@@ -915,14 +972,13 @@ struct Searcher {
                 load_regs();
             } else {
                 const int sl = sel & (S - 1);
-                const bool shi = sel >= S;
-                if ((lane & (S - 1)) == sl) {
-                    if (shi)
-                        cL1 &= ~vb;
-                    else
-                        cL &= ~vb;
-                }
-                scls[lane == sl ? base + sel : cap_classes].L = shi ? cL1 : cL;
+                const int sq = sel >> logS;
+                const bool mine = (lane & (S - 1)) == sl;
+                cL = pick(mine && sq == 0, cL & ~vb, cL);
+#pragma unroll
+                for (int q = 1; q < Q; ++q)
+                    cLh[q - 1] = pick(mine && sq == q, cLh[q - 1] & ~vb, cLh[q - 1]);
+                st_w(&scls[lane == sl ? base + sel : cap_classes].L, slotL(sq));
                 sync();
                 bound = ub;
             }
@@ -1094,7 +1150,7 @@ struct Searcher {
             for (int j = lane; j < fd; j += 64)
                 rmap[j] = smap[j];
             for (int j = lane; j < fK; j += 64)
-                rcls[j] = scls[fbase + j];
+                st_cls(rcls + j, ld_cls(scls + fbase + j));
         }
         if (lane == 0) {
             a_add_rlx(&P.open[inst], 1);
@@ -1108,10 +1164,9 @@ struct Searcher {
             shdr[b * HW + kHRremLo] = 0;
             shdr[b * HW + kHRremHi] = 0;
             shdr[b * HW + kHFlags] = 0;
-            if constexpr (sizeof(W) == 16) {
-                shdr[b * HW + kHRrem2] = 0;
-                shdr[b * HW + kHRrem3] = 0;
-            }
+#pragma unroll
+            for (int k = 2; k < (int)sizeof(W) / 4; ++k)
+                shdr[b * HW + rrem_field(k)] = 0;
         }
         sync();
         n_don += 1;
@@ -1168,21 +1223,18 @@ struct Searcher {
         rrem = sc((W)rh.rrem);
         const uint16_t *rmap = (const uint16_t *)(slot + rec_map_off<W>());
         const Cls<W> *rcls = (const Cls<W> *)(slot + rec_cls_off<W>());
-        uint16_t mp = 0, mp1 = 0;
-        Cls<W> cc, cc1;
-        cc.L = 0;
-        cc.R = 0;
-        cc1.L = 0;
-        cc1.R = 0;
-        if (lane < d)
-            mp = rmap[lane];
-        if (lane < K)
-            cc = rcls[lane];
-        if constexpr (Q == 2) {
-            if (lane + 64 < d)
-                mp1 = rmap[lane + 64];
-            if (lane + 64 < K)
-                cc1 = rcls[lane + 64];
+        // entry lane + 64q of the mapping and of the classes in slot q
+        uint16_t mp[Q];
+        Cls<W> cc[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            mp[q] = 0;
+            cc[q].L = (W)0;
+            cc[q].R = (W)0;
+            if (lane + 64 * q < d)
+                mp[q] = rmap[lane + 64 * q];
+            if (lane + 64 * q < K)
+                cc[q] = ld_cls(rcls + lane + 64 * q);
         }
         // every lane's loads of the slot have returned before the slot is
         // handed back, so a relaxed store suffices: the producer's later
@@ -1193,15 +1245,12 @@ struct Searcher {
         if (lane == 0)
             st_rlx(&P.seq[idx], hd + (unsigned long long)P.ring_slots);
         set_instance(ri);
-        if (lane < d)
-            smap[lane] = mp;
-        if (lane < K)
-            scls[lane] = cc;
-        if constexpr (Q == 2) {
-            if (lane + 64 < d)
-                smap[lane + 64] = mp1;
-            if (lane + 64 < K)
-                scls[lane + 64] = cc1;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (lane + 64 * q < d)
+                smap[lane + 64 * q] = mp[q];
+            if (lane + 64 * q < K)
+                st_cls(scls + lane + 64 * q, cc[q]);
         }
         sync();
         t = 0;
@@ -1497,10 +1546,13 @@ __global__ void __launch_bounds__(256) mcs_reset_kernel(ResetParams R) {
 
 extern "C" void *mcs_internal_search_kernel(int word_bytes, int directed, int policy) {
     using namespace mcs;
-    if (word_bytes == 16) {
+    if (word_bytes == 16 || word_bytes == 32) {
         // (the learned policy takes graphs of at most 64 vertices)
         if (policy)
             return nullptr;
+        if (word_bytes == 32)
+            return directed ? (void *)mcs_search_kernel<u256, true, false>
+                            : (void *)mcs_search_kernel<u256, false, false>;
         return directed ? (void *)mcs_search_kernel<u128, true, false>
                         : (void *)mcs_search_kernel<u128, false, false>;
     }

@@ -77,7 +77,7 @@ static void expect(bool ok, const char *what) {
 }
 
 int main() {
-    const int sizes[] = {1, 16, 33, 64, 65, 100, 128};
+    const int sizes[] = {1, 16, 33, 64, 65, 100, 128, 129, 193, 254};
     for (int ordering = 0; ordering < 2; ordering++)
         for (int directed = 0; directed < 2; directed++)
             for (int labels : {0, 3, 70})
@@ -104,7 +104,7 @@ int main() {
                         std::vector<int32_t> rb(G.size());
                         expect(mcs_plan_root_bounds(p, rb.data()) == MCS_OK, "root bounds");
                         for (size_t i = 0; i < G.size(); i++)
-                            expect(rb[i] >= 0 && rb[i] <= 128, "root bound range");
+                            expect(rb[i] >= 0 && rb[i] <= MCS_MAX_N, "root bound range");
                         mcs_plan_destroy(p);
                     }
                     expect(mcs_workspace_size((int32_t)G.size(), G.data(), H.data(), &o) > 0,
@@ -112,6 +112,7 @@ int main() {
                 }
     // rejected inputs: a bit at or above n in the second word, a self loop in
     // the second word, an asymmetric undirected graph, too many vertices
+    // (255: the limit is 254)
     {
         Graph g = random_graph(100, 0.2, 0, 0), h = random_graph(100, 0.2, 0, 0);
         mcs_graph G = g.view(), H = h.view();
@@ -127,7 +128,7 @@ int main() {
         g.adj[2 * 3 + 1] ^= 1ull << (80 - 64);
         G = g.view();
         expect(mcs_plan_create(1, &G, &H, nullptr, &p) == MCS_E_INVALID, "asymmetric");
-        Graph big = random_graph(129, 0.1, 1, 0);
+        Graph big = random_graph(MCS_MAX_N + 1, 0.1, 1, 0);
         G = big.view();
         expect(mcs_plan_create(1, &G, &H, nullptr, &p) == MCS_E_TOO_LARGE, "too large");
     }

@@ -72,7 +72,7 @@ def test_status_strings(mcs_lib):
 
 
 @pytest.mark.parametrize("mutate,status", [
-    (lambda G, H: (dict(G, n=129, rows=[0] * 129), H), -2),
+    (lambda G, H: (dict(G, n=255, rows=[0] * 255), H), -2),
     (lambda G, H: (dict(G, n=-1), H), -1),
     (lambda G, H: (dict(G, rows=[G["rows"][0] | 1] + G["rows"][1:]), H), -1),   # self loop
     (lambda G, H: (dict(G, rows=[G["rows"][0] | (1 << 20)] + G["rows"][1:]), H), -1),  # bit >= n
@@ -115,6 +115,36 @@ def test_validation_errors_two_word_rows(mcs_lib, mutate):
     assert mcs_lib.mcs_last_error()
 
 
+@pytest.mark.parametrize("mutate", [
+    lambda G: _flip(G, 0, 230),     # a bit at or above n, in the fourth word of a row
+    lambda G: _flip(G, 150, 150),   # a self loop in the third word
+    lambda G: _flip(G, 199, 199),   # a self loop in the fourth word
+    lambda G: _flip(G, 3, 190),     # asymmetric in the third word
+    lambda G: _flip(G, 195, 3),     # asymmetric in the first word of a four-word row
+])
+def test_validation_errors_four_word_rows(mcs_lib, mutate):
+    """Graphs of 193..254 vertices have four 64-bit words per row."""
+    from paper_1908_06418_amd import McsError
+    G = mi.er_graph(200, 0.05, 1)
+    H = mi.er_graph(200, 0.05, 2)
+    _create([(G, H)]).close()
+    with pytest.raises(McsError) as e:
+        _create([(mutate(G), H)])
+    assert _status(e) == -1
+    assert mcs_lib.mcs_last_error()
+
+
+def test_largest_graphs_accepted(mcs_lib):
+    """254 vertices, the paper's limit, make a plan (with 3- and 4-word rows
+    in one batch); 255 do not."""
+    from paper_1908_06418_amd import McsError
+    _create([(mi.er_graph(254, 0.05, 1), mi.er_graph(150, 0.05, 2)),
+             (mi.empty_graph(254), mi.complete_graph(254))]).close()
+    with pytest.raises(McsError) as e:
+        _create([(mi.empty_graph(255), mi.empty_graph(3))])
+    assert _status(e) == -2
+
+
 def test_two_word_rows_marshalled_low_word_first():
     from paper_1908_06418_amd import _Marshal
     g = mi.er_graph(100, 0.2, 3)
@@ -125,6 +155,12 @@ def test_two_word_rows_marshalled_low_word_first():
         assert int(words[2 * i]) | (int(words[2 * i + 1]) << 64) == r
     small = _Marshal([(mi.er_graph(64, 0.2, 3), mi.er_graph(64, 0.2, 4))])
     assert small.keep[0].size == 64
+    for n, rw in ((150, 3), (254, 4)):
+        g = mi.er_graph(n, 0.2, 3)
+        words = _Marshal([(g, g)]).keep[0]
+        assert words.size == rw * n
+        for i, r in enumerate(g["rows"]):
+            assert sum(int(words[rw * i + k]) << (64 * k) for k in range(rw)) == r
 
 
 def test_wide_plan_sizes(mcs_lib):
@@ -133,6 +169,8 @@ def test_wide_plan_sizes(mcs_lib):
     pairs = [(mi.er_graph(128, 0.3, 5), mi.er_graph(120, 0.3, 6))]
     narrow = [(mi.er_graph(64, 0.3, 5), mi.er_graph(60, 0.3, 6))]
     assert workspace_size(pairs) > workspace_size(narrow) > 0
+    widest = [(mi.er_graph(254, 0.3, 5), mi.er_graph(200, 0.3, 6))]
+    assert workspace_size(widest) > workspace_size(pairs)
     Plan(pairs).close()
 
 

@@ -1,0 +1,240 @@
+"""GPU parity for graphs of 129..254 vertices (the paper's limit, Sec. III.B):
+256-bit rows, and up to four class slots per lane (class 64q + k in slot q
+of lane k) for frames of more than 64, 128 or 192 classes.  A batch whose
+largest graph has more than 128 vertices runs every pair on this kernel, so
+small pairs mixed into such a batch run the 256-bit words on the one-slot
+path; labelled pairs with more than 128 (192) shared labels start with that
+many classes at the root and use the third (fourth) slot.
+
+Sizes must equal the oracle's; mappings are checked for validity.  With one
+wavefront the search walks the oracle's tree, so node counts agree too.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import mcs_instances as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _check(pairs, res, want):
+    for i, ((G, H), r) in enumerate(zip(pairs, res)):
+        errs = oracle.check.mapping_errors(G, H, r.mapping)
+        assert not errs, (i, errs[:3])
+        assert len(r.mapping) == r.size
+        assert r.size == want[i], (i, r.size, want[i])
+
+
+def _many_labels(seed, n, p, directed, nlab):
+    """G and H drawn independently; label i % nlab on G, the same multiset in
+    a random order on H, so every label is shared: nlab root classes."""
+    rng = np.random.default_rng(seed)
+    g = mi.random_small(rng, n, p, directed)
+    h = mi.random_small(rng, n, p, directed)
+    g["label"] = [i % nlab for i in range(n)]
+    h["label"] = [int(x) % nlab for x in rng.permutation(n)]
+    return g, h
+
+
+def _relabelled_copy(seed, n, p, directed=False):
+    """A random graph and a relabelled copy (MCS = n).  The draws used here
+    have degree sequences the degree order aligns at once (under a thousand
+    oracle nodes); many equal degrees can take the oracle millions."""
+    rng = np.random.default_rng(seed)
+    g = mi.random_small(rng, n, p, directed)
+    return g, mi.permute(g, list(rng.permutation(n)))
+
+
+def _small(seed, count, directed, nlab):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n1, n2 = int(rng.integers(4, 19)), int(rng.integers(4, 19))
+        p = float(rng.uniform(0.1, 0.7))
+        out.append((mi.random_small(rng, n1, p, directed, nlab),
+                    mi.random_small(rng, n2, p, directed, nlab)))
+    return out
+
+
+def _solve(pairs, **kw):
+    from paper_1908_06418_amd import solve_batch
+    return solve_batch(pairs, time_limit_s=kw.pop("time_limit_s", 120), **kw)
+
+
+@pytest.mark.parametrize("kind", ["undirected", "directed", "labelled", "directed_labelled"])
+def test_wide256_single_wave_reproduces_oracle_node_count(gpu, kind):
+    """One wavefront on the 256-bit kernel expands exactly the oracle's nodes:
+    class selection over four slots, the split of every slot, the unmatched
+    child and the partner bookkeeping over 254 vertices all follow the
+    sequential algorithm."""
+    directed = kind.startswith("directed")
+    labelled = "labelled" in kind
+    nlab = 6 if labelled else 0
+    seed = {"undirected": 71, "directed": 72, "labelled": 73, "directed_labelled": 74}[kind]
+    rng = np.random.default_rng(seed)
+    # small pairs, and a pair with a 130-vertex graph that puts the batch on
+    # the 256-bit kernel
+    pairs = _small(seed, 8, directed, nlab)
+    pairs += [(mi.random_small(rng, 130, 0.5, directed, nlab),
+               mi.random_small(rng, 12, 0.5, directed, nlab))]
+    if labelled:
+        # 140 and 250 (directed) or 140 and 195 shared labels: that many
+        # classes at the root, in the third and fourth slots
+        if directed:
+            pairs += [_many_labels(81, 180, 0.3, True, 130),
+                      _many_labels(82, 254, 0.3, True, 250)]
+        else:
+            pairs += [_many_labels(83, 160, 0.5, False, 140),
+                      _many_labels(84, 200, 0.4, False, 195)]
+    else:
+        # relabelled copies at 200 and 254 vertices (sizes 200 and 254); the
+        # single wavefront's worst-case stack (32,385 classes at 254) is in HBM
+        if directed:
+            pairs += [_relabelled_copy(100, 254, 0.3, True), _relabelled_copy(101, 200, 0.3, True)]
+        else:
+            pairs += [_relabelled_copy(100, 254, 0.5), _relabelled_copy(100, 200, 0.3)]
+    tun = {"single_wave": 1, "children_per_wave": 1, "no_reprune": 1}
+    _say(f"wide256 single-wave {kind}: {len(pairs)} pairs")
+    res = _solve(pairs, tuning=tun)
+    for i, ((G, H), r) in enumerate(zip(pairs, res)):
+        o = oracle.mcs(G, H)
+        assert o["complete"]
+        assert r.optimal and r.size == o["size"], (i, r.size, o["size"])
+        assert r.nodes == o["nodes"], (i, r.nodes, o["nodes"])
+        assert oracle.check.is_valid(G, H, r.mapping)
+
+
+def _wide256_batch():
+    pairs = [_many_labels(82, 254, 0.3, True, 250),
+             _many_labels(84, 200, 0.4, False, 195),
+             _many_labels(85, 200, 0.3, True, 150),
+             _many_labels(83, 160, 0.5, False, 140),
+             _many_labels(81, 180, 0.3, True, 130),
+             _relabelled_copy(100, 254, 0.5),
+             _relabelled_copy(100, 254, 0.3, True),
+             _relabelled_copy(100, 200, 0.3),
+             _relabelled_copy(100, 150, 0.5)]
+    # the directed labelled workload's recipe (p = 0.1, ceil(0.33 n) labels)
+    # at 70 vertices, and small pairs
+    pairs += [(mi.er_graph(70, 0.1, mi.stream_seed(6, s, 0), True, True),
+               mi.er_graph(70, 0.1, mi.stream_seed(6, s, 1), True, True)) for s in range(2)]
+    pairs += _small(86, 8, False, 0) + _small(87, 4, True, 3)
+    return pairs
+
+
+@functools.lru_cache(maxsize=1)
+def _wide256_sizes():
+    out = []
+    for G, H in _wide256_batch():
+        r = oracle.mcs(G, H)
+        assert r["complete"]
+        out.append(r["size"])
+    return tuple(out)
+
+
+def test_wide256_batched_matches_oracle(gpu):
+    """The default launch: thousands of wavefronts share the batch's work
+    through the node queue, so 256-bit records (a 48-byte header and up to
+    254 classes) are donated and taken."""
+    from paper_1908_06418_amd import Plan
+    pairs = _wide256_batch()
+    want = list(_wide256_sizes())
+    _say(f"wide256 batch: {len(pairs)} pairs")
+    plan = Plan(pairs, time_limit_s=120).upload()
+    try:
+        plan.run()
+        res = plan.results()
+        st = plan.stats()
+    finally:
+        plan.close()
+    assert all(r.optimal for r in res)
+    _check(pairs, res, want)
+    assert want[5] == 254 and want[6] == 254 and want[7] == 200 and want[8] == 150
+    assert st.donations > 0 and st.pops > 0
+
+
+def test_wide256_edge_cases(gpu):
+    rng = np.random.default_rng(88)
+    g200 = mi.random_small(rng, 200, 0.1)
+    cases = [
+        (mi.empty_graph(254), mi.empty_graph(254), 254),
+        (mi.complete_graph(254), mi.complete_graph(200), 200),
+        (mi.empty_graph(129), mi.complete_graph(254), 1),
+        (mi.empty_graph(0), mi.empty_graph(254), 0),
+        (mi.complete_graph(254), mi.empty_graph(1), 1),
+        (g200, mi.induced(g200, [0, 63, 64, 127, 128, 191, 192, 199]), 8),
+        (mi.empty_graph(193), mi.empty_graph(192), 192),
+        (mi.empty_graph(129), mi.empty_graph(128), 128),
+    ]
+    pairs = [(G, H) for G, H, _ in cases]
+    _say("wide256 edge cases")
+    res = _solve(pairs)
+    assert all(r.optimal for r in res)
+    _check(pairs, res, [s for _, _, s in cases])
+
+
+def test_wide256_and_narrow_kernels_agree(gpu):
+    """The same small pairs on the 64-bit kernel, and on the 256-bit kernel
+    (one 129-vertex pair in the batch): identical sizes."""
+    small = _small(89, 24, False, 3) + _small(90, 24, True, 0)
+    narrow = _solve(small)
+    wide = _solve(small + [(mi.empty_graph(129), mi.empty_graph(129))])
+    assert [r.size for r in wide[:-1]] == [r.size for r in narrow]
+    assert wide[-1].size == 129
+    assert all(r.optimal for r in narrow + wide)
+
+
+@pytest.mark.parametrize("tun", [
+    {"stack_classes": 1},
+    {"stack_classes": 1, "ring_slots": 2, "check_interval": 1, "waves_per_cu": 1},
+])
+def test_wide256_stack_is_always_the_worst_case(gpu, tun):
+    """With 256-bit rows each wavefront's class stack in HBM holds the whole
+    worst case (32,385 classes at 254 vertices) whatever stack_classes asks
+    for, so a child always has room, even with a node queue of two slots and
+    a donation check every step, and sizes stay exact."""
+    from paper_1908_06418_amd import Plan
+    pairs = _wide256_batch()
+    want = list(_wide256_sizes())
+    _say(f"wide256 stack {tun}: {len(pairs)} pairs")
+    plan = Plan(pairs, time_limit_s=120, tuning=tun).upload()
+    try:
+        plan.run()
+        res = plan.results()
+        st = plan.stats()
+    finally:
+        plan.close()
+    mmax = max(min(G["n"], H["n"]) for G, H in pairs)
+    assert st.stack_classes == mmax * (mmax + 1) // 2
+    assert st.max_stack_used <= st.stack_classes
+    assert all(r.optimal for r in res)
+    _check(pairs, res, want)
+
+
+def test_wide256_graph_replays_match_oracle(gpu):
+    """The HIP graph (reset kernel + 256-bit search kernel) replayed three
+    times, with eager work between replays: the oracle's sizes every time."""
+    import torch
+    from paper_1908_06418_amd import Plan
+    pairs = _wide256_batch()
+    want = list(_wide256_sizes())
+    plan = Plan(pairs, time_limit_s=120, tuning={"use_graph": 1}).upload()
+    try:
+        for rep in range(3):
+            _say(f"wide256 graph replay {rep}")
+            plan.run()
+            res = plan.results()
+            assert all(r.optimal for r in res)
+            _check(pairs, res, want)
+            x = torch.randn(1 << 20, device="cuda")
+            torch.cuda.synchronize()
+            assert torch.isfinite(x.sum()).item()
+    finally:
+        plan.close()
