@@ -359,7 +359,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {4: "u32", 8: "u64", 16: "u128"}[word],
+        "dtype": {4: "u32", 8: "u64", 16: "u128", 32: "u256"}[word],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "pairs": len(pairs),
                    "word_bits": 8 * word, "directed": directed, "hip_graph": not args.no_graph,

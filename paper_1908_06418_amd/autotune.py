@@ -60,7 +60,7 @@ def workload_key(pairs) -> str:
                 e = sum(bin(r).count("1") for r in g["rows"])
                 dens.append(e / (n * (n - 1)))
     p = sum(dens) / len(dens) if dens else 0.0
-    bits = 32 if nmax <= 32 else 64 if nmax <= 64 else 128
+    bits = 32 if nmax <= 32 else 64 if nmax <= 64 else 128 if nmax <= 128 else 256
     nb = 8 * math.ceil(max(nmax, 1) / 8)
     batch = 1 << max(0, math.ceil(math.log2(len(pairs))))
     return (f"w{bits}-{'d' if directed else 'u'}{'l' if labelled else ''}-n{nb}"
