@@ -238,3 +238,60 @@ def test_wide256_graph_replays_match_oracle(gpu):
             assert torch.isfinite(x.sum()).item()
     finally:
         plan.close()
+
+
+def _timed(pairs, time_limit_s=60, warm=True):
+    from paper_1908_06418_amd import Plan
+    plan = Plan(pairs, time_limit_s=time_limit_s).upload()
+    try:
+        if warm:
+            plan.run()
+        plan.run()
+        res = plan.results()
+        st = plan.stats()
+    finally:
+        plan.close()
+    return res, st
+
+
+def test_wide256_rate_report(gpu):
+    """Kernel time and node rate of the 256-bit kernel, printed (and kept as
+    wide256_report.json, see _report.py):
+
+    - the batch above (sizes checked against the oracle's);
+    - the 40 directed vertex-labelled pairs of 80 and 100 vertices (the
+      128-bit workload), once as they are and once with an empty 129-vertex
+      pair added, which puts them on the 256-bit kernel (sizes equal);
+    - the same recipe (p = 0.1, ceil(0.33 n) labels) at 150 and 200
+      vertices, 8 pairs each, under a 20 s limit: pairs proven, and every
+      size at least the oracle's within 2e6 nodes."""
+    import json
+    from _report import write_report
+    report = {}
+    pairs = _wide256_batch()
+    res, st = _timed(pairs)
+    _check(pairs, res, list(_wide256_sizes()))
+    report["batch"] = {"pairs": len(pairs), "kernel_ms": st.kernel_ms, "nodes": st.nodes,
+                       "waves": st.waves}
+    w = mi.pairs_w()
+    r128, s128 = _timed(w)
+    r256, s256 = _timed(w + [(mi.empty_graph(129), mi.empty_graph(129))])
+    assert [r.size for r in r256[:-1]] == [r.size for r in r128]
+    assert all(r.optimal for r in r128 + r256)
+    report["w_128bit"] = {"kernel_ms": s128.kernel_ms, "nodes": s128.nodes, "waves": s128.waves}
+    report["w_256bit"] = {"kernel_ms": s256.kernel_ms, "nodes": s256.nodes, "waves": s256.waves}
+    big = [(mi.er_graph(n, 0.1, mi.stream_seed(9, s, 0), True, True),
+            mi.er_graph(n, 0.1, mi.stream_seed(9, s, 1), True, True))
+           for n in (150, 200) for s in range(8)]
+    rb, sb = _timed(big, time_limit_s=20, warm=False)
+    for (G, H), r in zip(big, rb):
+        assert oracle.check.is_valid(G, H, r.mapping) and len(r.mapping) == r.size
+        assert r.size >= oracle.mcs(G, H, node_limit=2_000_000)["size"]
+    report["w_recipe_150_200"] = {"pairs": len(big), "proven": sum(r.optimal for r in rb),
+                                  "kernel_ms": sb.kernel_ms, "nodes": sb.nodes,
+                                  "sizes": [r.size for r in rb]}
+    for k, v in report.items():
+        if "kernel_ms" in v:
+            v["nodes_per_s"] = v["nodes"] / (v["kernel_ms"] / 1e3) if v["kernel_ms"] else None
+    _say("wide256 report: " + json.dumps(report))
+    write_report("wide256_report.json", report)
