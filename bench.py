@@ -41,10 +41,10 @@ PEAK_HBM_BYTES = 8e12
 # kernel code (comments aside, code_hash) is the one those counters were
 # taken on.
 TRAFFIC = {
-    # profiles/mcs_seg_kernel_c4.md: FETCH_SIZE 11,556,081.6 KiB x 1.9997 plus
-    # WRITE_SIZE 336,609,865.0 KiB x 1.000
-    "c4": {"source": "mcs_seg.hip", "kernel_code_hash": "850df5b7fbb3e720",
-           "bytes": 368_351_712_358},
+    # profiles/mcs_seg_kernel_c4.md: FETCH_SIZE 11,270,091.4 KiB x 1.9997 plus
+    # WRITE_SIZE 381,296,812.5 KiB x 1.000
+    "c4": {"source": "mcs_seg.hip", "kernel_code_hash": "11272294e2ea296e",
+           "bytes": 413_525_491_404},
 }
 
 # Algorithmic 32-bit lane operations of one matched child (v, w), per class
