@@ -169,7 +169,8 @@ constexpr int rec_cls_off() { return rec_header((int)sizeof(W)) + 2 * bits_of<W>
 //             that lanes with nothing to store write to, so the stores need
 //             no exec-mask branches (cap_classes = -1: the classes live
 //             elsewhere, as they do in HBM for 128-bit rows)
-//   adjacency [R][NB] words
+//   adjacency [R][NB] words (R = 4 directed, 2 undirected; with rows wider
+//             than 64 bits only H's rows, R = 2 or 1)
 //   mapping   [NB] byte pairs
 //   headers   [frames][hdr_words] frame headers, one 32-bit word per field
 //   orders    [policy levels][64] partner order of policy-ordered frames
@@ -182,7 +183,7 @@ inline constexpr int align16(int x) { return (x + 15) & ~15; }
 inline constexpr LdsLayout lds_layout(int word_bytes, int directed, int cap_classes,
                                       int frames, int policy_levels = 0) {
     int nb = 8 * word_bytes;
-    int rows = directed ? 4 : 2;
+    int rows = (directed ? 4 : 2) / (word_bytes > 8 ? 2 : 1);
     int hdr_bytes = 4 * hdr_words(word_bytes);
     LdsLayout L{0, 0, 0, 0, 0, 0};
     L.cls = 0;

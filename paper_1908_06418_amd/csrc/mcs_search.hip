@@ -61,7 +61,9 @@ struct Searcher {
     const SearchParams &P;  // a copy in LDS: cold fields are read when needed
     int cmax, cap_classes, check_interval, reprune;  // hot knobs, kept in registers
     int lane;
-    W *sadj;        // [NR][NB]: G rows, H rows (out), then G, H in-rows
+    W *sadj;        // [NR][NB]: G rows, H rows (out), then G, H in-rows; with
+                    // rows wider than 64 bits only H's: [NR / 2][NB] (out, in)
+    const W *gadj;  // (rows wider than 64 bits) the instance's rows in HBM, for v's G rows
     uint16_t *smap; // [NB] current path: g | h << 8
     int *shdr;      // [NB + 1][HW]
     Cls<W> *scls;   // [cap_classes + 1] (LDS; HBM with 128-bit rows)
@@ -112,6 +114,7 @@ struct Searcher {
         else
             scls = (Cls<W> *)(p.hstack + (size_t)wave * (size_t)p.hstack_stride);
         sadj = (W *)(lds + L.adj);
+        gadj = (const W *)p.adj;
         smap = (uint16_t *)(lds + L.map);
         shdr = (int *)(lds + L.hdr);
         sord = lds + L.ord;
@@ -516,8 +519,16 @@ struct Searcher {
     __device__ void set_instance(int i) {
         if (i != inst) {
             const W *src = (const W *)P.adj + (size_t)i * NR * NB;
-            for (int j = lane; j < NR * NB; j += 64)
-                st_w(sadj + j, ld_w(src + j));
+            if constexpr (Q == 1) {
+                for (int j = lane; j < NR * NB; j += 64)
+                    st_w(sadj + j, ld_w(src + j));
+            } else {
+                // H's rows only (sets 1 and 3 of the instance's rows); v's G
+                // rows are read from HBM, one row per batch
+                for (int j = lane; j < (NR / 2) * NB; j += 64)
+                    st_w(sadj + j, ld_w(src + (2 * (j / NB) + 1) * NB + j % NB));
+                gadj = src;
+            }
             inst = i;
             map_off = (int)P.inst[i].map_off;
             nG = (int)P.inst[i].nG;
@@ -843,11 +854,11 @@ struct Searcher {
         const int myw = act ? ctz(x) : 0;
         const W vb = bit_at<W>(v);
         const W wb = bit_at<W>(myw);
-        const W go = ld_w(sadj + v), ho = ld_w(sadj + NB + myw);
+        const W go = ld_w(gadj + v), ho = ld_w(sadj + myw);
         W gi = (W)0, hi = (W)0;
         if constexpr (DIR) {
-            gi = ld_w(sadj + 2 * NB + v);
-            hi = ld_w(sadj + 3 * NB + myw);
+            gi = ld_w(gadj + 2 * NB + v);
+            hi = ld_w(sadj + NB + myw);
         }
         int contrib = 0;
 #pragma unroll
