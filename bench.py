@@ -399,8 +399,8 @@ def main():
                 "bytes": "algorithmic: adjacency rows of v and the partners per child batch, "
                          "and each pushed frame's classes written once and read twice "
                          "(mcs_stats.lds_bytes, from the kernel's counters)"
-                         + ("; with 128-bit rows the classes live in the workspace (L1/L2), "
-                            "not LDS" if word == 16 else "")},
+                         + ("; with 128- and 256-bit rows the classes and v's G row live in "
+                            "the workspace (L1/L2), not LDS" if word >= 16 else "")},
         "hbm": {"achieved_GBps": traffic * K / kern_s / 1e9 if traffic and kern_s else None,
                 "peak_GBps": PEAK_HBM_BYTES / 1e9,
                 "frac": traffic * K / kern_s / PEAK_HBM_BYTES if traffic and kern_s else None,
