@@ -295,3 +295,37 @@ def test_wide256_rate_report(gpu):
             v["nodes_per_s"] = v["nodes"] / (v["kernel_ms"] / 1e3) if v["kernel_ms"] else None
     _say("wide256 report: " + json.dumps(report))
     write_report("wide256_report.json", report)
+
+
+@pytest.mark.parametrize("pad", [65, 129])
+@pytest.mark.parametrize("kind", ["batched", "directed_labelled"])
+@pytest.mark.parametrize("tun", [
+    {},
+    {"children_per_wave": 1, "check_interval": 2, "donate_low": 64, "ring_slots": 64},
+])
+def test_wide_fixed_incumbent_node_counts_match_oracle(gpu, pad, kind, tun):
+    """The order-independent node count of the segmented kernel's test
+    (incumbent held at the optimum, goal = optimum + 1), on the wide
+    kernels: an empty pair of 65 (129) vertices, skipped with goal -1, puts
+    the 48 small pairs on the 128-bit (256-bit) kernel, whose frames are
+    then split and handed on through the queue as wide records.  Each count
+    must equal the sequential oracle's."""
+    from test_gpu_parity import _fixed_incumbent_case
+    from paper_1908_06418_amd import Plan
+    pairs, goals, want = _fixed_incumbent_case(kind)
+    pairs = list(pairs) + [(mi.empty_graph(pad), mi.empty_graph(pad))]
+    goals = list(goals) + [-1]
+    _say(f"wide fixed incumbent, {pad} vertices, {kind}, {tun}: {len(pairs)} pairs")
+    plan = Plan(pairs, time_limit_s=60, tuning=tun).upload()
+    try:
+        plan.set_goals(goals)
+        plan.run()
+        res = plan.results()
+        st = plan.stats()
+    finally:
+        plan.close()
+    for i, (r, g, n) in enumerate(zip(res[:-1], goals, want)):
+        assert r.optimal and r.size < g, (i, r.size, g)
+        assert r.nodes == n, (i, r.nodes, n)
+    if tun.get("check_interval", 128) <= 4:
+        assert st.donations > 0
