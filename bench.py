@@ -41,10 +41,14 @@ PEAK_HBM_BYTES = 8e12
 # kernel code (comments aside, code_hash) is the one those counters were
 # taken on.
 TRAFFIC = {
-    # profiles/mcs_seg_kernel_c4.md: FETCH_SIZE 11,270,091.4 KiB x 1.9997 plus
-    # WRITE_SIZE 381,296,812.5 KiB x 1.000
-    "c4": {"source": "mcs_seg.hip", "kernel_code_hash": "11272294e2ea296e",
-           "bytes": 413_525_491_404},
+    # profiles/mcs_seg_kernel_c4.md: FETCH_SIZE 11,588,817.8 KiB x 1.9997 plus
+    # WRITE_SIZE 401,781,246.1 KiB x 1.000
+    "c4": {"source": "mcs_seg.hip", "kernel_code_hash": "4e05206b255fb045",
+           "bytes": 435_154_020_482},
+    # profiles/mcs_search_kernel_w.md: FETCH_SIZE 192,689.2 KiB x 1.9997 plus
+    # WRITE_SIZE 19,447,989.8 KiB x 1.000
+    "w": {"source": "mcs_search.hip", "kernel_code_hash": "31a3f47dc12d01c3",
+          "bytes": 20_309_302_811},
 }
 
 # Algorithmic 32-bit lane operations of one matched child (v, w), per class
