@@ -158,13 +158,16 @@ def usable_cores() -> int:
     return max(1, min(16, n))
 
 
-def cpu_baseline(pairs, exp, wall_s=15.0, seed=20260):
+def cpu_baseline(pairs, exp, wall_s=15.0, seed=20260, pair_cap_s=30.0):
     """The oracle, as it stands, on a bounded random sample of the workload.
 
     Pairs are drawn in a seeded random order from those the stored oracle run
-    finished (the others cannot be timed to completion), and taken until
-    their stored one-core times add up to about wall_s x cores seconds; the
-    sample is then solved one process per pair on that many host cores."""
+    finished (the others cannot be timed to completion) in at most
+    pair_cap_s seconds of one core (so that no single pair sets the leg's
+    wall time: the stored run finished some pairs only after minutes),
+    and taken until their stored one-core times add up to about
+    wall_s x cores seconds; the sample is then solved one process per pair on
+    that many host cores."""
     import random
     from concurrent.futures import ProcessPoolExecutor
 
@@ -173,9 +176,12 @@ def cpu_baseline(pairs, exp, wall_s=15.0, seed=20260):
     cores = usable_cores()
     idx = list(range(len(pairs)))
     finished = len(idx)
+    eligible = len(idx)
     if exp is not None:
         idx = [i for i in idx if exp["pairs"][i]["complete"]]
         finished = len(idx)
+        idx = [i for i in idx if exp["pairs"][i]["seconds"] <= pair_cap_s]
+        eligible = len(idx)
         random.Random(seed).shuffle(idx)
         acc, keep = 0.0, []
         for i in idx:
@@ -192,9 +198,10 @@ def cpu_baseline(pairs, exp, wall_s=15.0, seed=20260):
     nodes = sum(n for n, _ in out)
     return {"value": nodes / dt, "unit": "nodes/s", "cores": cores, "kind": "oracle",
             "instances_per_s": len(sample) / dt, "cpu": host_cpu(),
-            "sample": f"{len(sample)} pairs drawn at random (seed {seed}) from the {finished} "
-                      f"of {len(pairs)} pairs of the same workload the oracle finishes within "
-                      f"its stored node budget, until their one-core times sum to about "
+            "sample": f"{len(sample)} pairs drawn at random (seed {seed}) from the {eligible} "
+                      f"of the {finished} (of {len(pairs)}) pairs of the same workload the oracle "
+                      f"finishes within its stored node budget that took it at most {pair_cap_s:.0f} s "
+                      f"of one core, until their one-core times sum to about "
                       f"{wall_s:.0f} s x {cores} cores; solved to optimality by the plain "
                       f"recursive C oracle, one process per pair on {cores} host cores "
                       f"({host_cpu()}), {dt:.1f} s wall"}
